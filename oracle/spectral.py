@@ -1,0 +1,230 @@
+"""Spectral operators and the Navier--Stokes right-hand side, FP64 (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Follows Sec. 2 ("Pseudo-spectral discretization of incompressible
+Navier--Stokes"): the rotational form of Eq. (1b) with the modified pressure,
+the spectral ODE system of Eq. (2) whose nonlinear term u x omega is evaluated
+pointwise in physical space and transformed back (Sec. 2.1), and the
+Boussinesq system of Eqs. (3a-c), (4a-b) (Sec. 3.2).  Dealiasing uses the
+2/3 rule (see the design doc for why this replaces the 3/2 padding of Sec. 2.1.1).
+
+Every function works on the full half-spectrum layout; shapes are
+(C, N, N, N//2+1) in 3D and (C, N, N//2+1) in 2D, complex128.
+"""
+import numpy as np
+
+
+def cutoff(n):
+    """2/3-rule cutoff K = floor((N-1)/3): the largest retained |k_j|.
+
+    With 3K < N the alias of any product mode (|k| <= 2K) lands outside the
+    retained cube, which is what the 2/3 rule requires.
+    """
+    return (n - 1) // 3
+
+
+def wavenumbers(n, dim):
+    """Integer wavenumber grids broadcastable to the half-spectrum shape.
+
+    Returns (kx, ky) in 2D or (kx, ky, kz) in 3D.  Full axes carry
+    0..N/2-1, -N/2..-1; the last (real-DFT) axis carries 0..N/2.
+    """
+    kfull = np.fft.fftfreq(n, 1.0 / n)
+    khalf = np.fft.rfftfreq(n, 1.0 / n)
+    if dim == 3:
+        kz = kfull[:, None, None]
+        ky = kfull[None, :, None]
+        kx = khalf[None, None, :]
+        return kx, ky, kz
+    if dim == 2:
+        ky = kfull[:, None]
+        kx = khalf[None, :]
+        return kx, ky
+    raise ValueError("dim must be 2 or 3")
+
+
+def mask(n, dim):
+    """Boolean 2/3-rule mask: True where every |k_j| <= K."""
+    K = cutoff(n)
+    ks = wavenumbers(n, dim)
+    m = np.ones(np.broadcast_shapes(*[k.shape for k in ks]), dtype=bool)
+    for k in ks:
+        m = m & (np.abs(k) <= K)
+    return m
+
+
+def spectral_shape(n, dim):
+    return (n,) * (dim - 1) + (n // 2 + 1,)
+
+
+# ---------------------------------------------------------------------------
+# Transforms.  The normalised convention u_hat = DFT(u)/N^d is the reading of
+# the paper's kinetic-energy formula (Sec. 3.1) chosen in the design doc.
+# ---------------------------------------------------------------------------
+
+def forward(u, dim):
+    """Physical (..., N, ..., N) real -> normalised half spectrum."""
+    n = u.shape[-1]
+    axes = tuple(range(-dim, 0))
+    return np.fft.rfftn(u, axes=axes) / float(n) ** dim
+
+
+def inverse(uh, n, dim):
+    """Normalised half spectrum -> physical real values on the N^d grid."""
+    axes = tuple(range(-dim, 0))
+    return np.fft.irfftn(uh * float(n) ** dim, s=(n,) * dim, axes=axes)
+
+
+def naive_forward(u):
+    """Direct-summation real DFT (no FFT), normalised, for tiny grids.
+
+    u has shape (N,)*d.  Evaluates sum_x u(x) exp(-i k.x) / N^d for every
+    half-spectrum k, with x_j = 2 pi j / N.  O(N^(2d)); N <= 8 only.
+    """
+    dim = u.ndim
+    n = u.shape[0]
+    out = np.zeros(spectral_shape(n, dim), dtype=np.complex128)
+    kfull = [int(k) for k in np.fft.fftfreq(n, 1.0 / n)]
+    khalf = list(range(n // 2 + 1))
+    grids = np.meshgrid(*([np.arange(n)] * dim), indexing="ij")
+    if dim == 3:
+        for a, kz in enumerate(kfull):
+            for b, ky in enumerate(kfull):
+                for c, kx in enumerate(khalf):
+                    ph = 2 * np.pi * (kz * grids[0] + ky * grids[1] + kx * grids[2]) / n
+                    out[a, b, c] = np.sum(u * np.exp(-1j * ph))
+    else:
+        for b, ky in enumerate(kfull):
+            for c, kx in enumerate(khalf):
+                ph = 2 * np.pi * (ky * grids[0] + kx * grids[1]) / n
+                out[b, c] = np.sum(u * np.exp(-1j * ph))
+    return out / float(n) ** dim
+
+
+def naive_inverse(uh, n):
+    """Direct-summation inverse of a half spectrum (tiny grids only).
+
+    Rebuilds the full Hermitian spectrum and sums u(x) = sum_k uh_k e^{ik.x}.
+    Entries on the kx = N/2 plane are summed once, as irfftn does, taking
+    their real part's Hermitian completion.
+    """
+    dim = uh.ndim
+    kfull = [int(k) for k in np.fft.fftfreq(n, 1.0 / n)]
+    grids = np.meshgrid(*([np.arange(n)] * dim), indexing="ij")
+    u = np.zeros((n,) * dim)
+    # full spectrum from the half spectrum: F(-k) = conj(F(k))
+    full = np.zeros((n,) * dim, dtype=np.complex128)
+    half = n // 2 + 1
+    if dim == 3:
+        for a in range(n):
+            for b in range(n):
+                for c in range(n):
+                    if c < half:
+                        full[a, b, c] = uh[a, b, c]
+                    else:
+                        full[a, b, c] = np.conj(uh[(-a) % n, (-b) % n, (-c) % n])
+        for a, kz in enumerate(kfull):
+            for b, ky in enumerate(kfull):
+                for c, kx in enumerate(kfull):
+                    ph = 2 * np.pi * (kz * grids[0] + ky * grids[1] + kx * grids[2]) / n
+                    u = u + np.real(full[a, b, c] * np.exp(1j * ph))
+    else:
+        for b in range(n):
+            for c in range(n):
+                if c < half:
+                    full[b, c] = uh[b, c]
+                else:
+                    full[b, c] = np.conj(uh[(-b) % n, (-c) % n])
+        for b, ky in enumerate(kfull):
+            for c, kx in enumerate(kfull):
+                ph = 2 * np.pi * (ky * grids[0] + kx * grids[1]) / n
+                u = u + np.real(full[b, c] * np.exp(1j * ph))
+    return u
+
+
+# ---------------------------------------------------------------------------
+# Right-hand sides
+# ---------------------------------------------------------------------------
+
+def curl3(uh, n):
+    """omega_hat = i k x u_hat (Sec. 2: omega = curl u)."""
+    kx, ky, kz = wavenumbers(n, 3)
+    ux, uy, uz = uh
+    return np.stack([1j * (ky * uz - kz * uy),
+                     1j * (kz * ux - kx * uz),
+                     1j * (kx * uy - ky * ux)])
+
+
+def cross3(a, b):
+    """Pointwise a x b for (3, ...) arrays."""
+    return np.stack([a[1] * b[2] - a[2] * b[1],
+                     a[2] * b[0] - a[0] * b[2],
+                     a[0] * b[1] - a[1] * b[0]])
+
+
+def rhs_ns3d(uh, nu):
+    """f(u_hat) of Eq. (2), 2/3-dealiased, normalised convention.
+
+    1. omega_hat = i k x u_hat;
+    2. u, omega in physical space (inverse real DFT);
+    3. n = u x omega pointwise;
+    4. N_hat = mask * DFT(n) / N^3;
+    5. pressure: p_hat = (k . N_hat)/|k|^2, with p_hat(0) = 0 -- the Leray
+       projection that eliminates P (the stray factor i in the printed
+       projection term is a typo);
+    6. f = N_hat - k p_hat - nu |k|^2 u_hat.
+    """
+    n = uh.shape[1]
+    kx, ky, kz = wavenumbers(n, 3)
+    m = mask(n, 3)
+    u = inverse(uh, n, 3)
+    w = inverse(curl3(uh, n), n, 3)
+    nl = forward(cross3(u, w), 3) * m
+    k2 = kx * kx + ky * ky + kz * kz
+    k2safe = np.where(k2 == 0, 1.0, k2)
+    p = (kx * nl[0] + ky * nl[1] + kz * nl[2]) / k2safe
+    p = np.where(k2 == 0, 0.0, p)
+    f = np.stack([nl[0] - kx * p, nl[1] - ky * p, nl[2] - kz * p]) - nu * k2 * uh
+    return f
+
+
+def rhs_ns2d(uh, nu, kappa=0.0, ri=0.0):
+    """2D right-hand side; with three components it is the Boussinesq system.
+
+    Components: (u, v) for plain 2D NS, (u, v, rho) for Boussinesq
+    (Eqs. (3a-c) and (4a-b) of Sec. 3.2, in two dimensions with gravity
+    along -y).  omega = dv/dx - du/dy; the rotational nonlinear term is
+    n = u x omega = (v omega, -u omega).  The momentum RHS is
+    P(N_hat - Ri rho_hat e_y) - nu |k|^2 u_hat with P = I - k k^T/|k|^2 and
+    zero at k = 0; the density RHS is -i k.(rho u)^ - kappa |k|^2 rho_hat.
+    """
+    n = uh.shape[1]
+    kx, ky = wavenumbers(n, 2)
+    m = mask(n, 2)
+    k2 = kx * kx + ky * ky
+    k2safe = np.where(k2 == 0, 1.0, k2)
+    u = inverse(uh[0], n, 2)
+    v = inverse(uh[1], n, 2)
+    om = inverse(1j * (kx * uh[1] - ky * uh[0]), n, 2)
+    nx = forward(v * om, 2) * m
+    ny = forward(-u * om, 2) * m
+    if uh.shape[0] == 3:
+        rho = inverse(uh[2], n, 2)
+        qx = forward(rho * u, 2) * m
+        qy = forward(rho * v, 2) * m
+        ny = ny - ri * uh[2]
+    p = (kx * nx + ky * ny) / k2safe
+    fu = np.where(k2 == 0, 0.0, nx - kx * p) - nu * k2 * uh[0]
+    fv = np.where(k2 == 0, 0.0, ny - ky * p) - nu * k2 * uh[1]
+    if uh.shape[0] == 2:
+        return np.stack([fu, fv])
+    frho = -1j * (kx * qx + ky * qy) - kappa * k2 * uh[2]
+    return np.stack([fu, fv, frho])
+
+
+def divergence3(uh):
+    """k . u_hat (zero for a divergence-free field)."""
+    n = uh.shape[1]
+    kx, ky, kz = wavenumbers(n, 3)
+    return kx * uh[0] + ky * uh[1] + kz * uh[2]

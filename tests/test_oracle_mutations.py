@@ -1,0 +1,70 @@
+"""The pins are strong enough: a plausible mistake planted in the oracle (on
+the CPU, via monkeypatch) makes at least one of them fail."""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import test_oracle_spectral as ts
+import test_oracle_tableaux as tt
+from oracle import spectral, tableaux
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_sign_error_in_cross_product_is_caught(monkeypatch):
+    def bad_cross(a, b):
+        return np.stack([a[1] * b[2] - a[2] * b[1],
+                         a[2] * b[0] - a[0] * b[2],
+                         a[1] * b[0] - a[0] * b[1]])      # z component flipped
+    monkeypatch.setattr(spectral, "cross3", bad_cross)
+    assert _fails(ts.test_rotation_equivariance)
+
+
+def test_transposed_curl_operand_is_caught(monkeypatch):
+    orig = spectral.curl3
+
+    def bad_curl(uh, n):
+        w = orig(uh, n)
+        return np.stack([w[0], w[2], w[1]])
+    monkeypatch.setattr(spectral, "curl3", bad_curl)
+    assert _fails(ts.test_inviscid_invariants, 16, 4) or _fails(ts.test_rotation_equivariance)
+
+
+def test_missing_projection_is_caught(monkeypatch):
+    orig = spectral.rhs_ns3d
+
+    def no_proj(uh, nu):
+        n = uh.shape[1]
+        u = spectral.inverse(uh, n, 3)
+        w = spectral.inverse(spectral.curl3(uh, n), n, 3)
+        kx, ky, kz = spectral.wavenumbers(n, 3)
+        k2 = kx * kx + ky * ky + kz * kz
+        return spectral.forward(spectral.cross3(u, w), 3) * spectral.mask(n, 3) - nu * k2 * uh
+    monkeypatch.setattr(spectral, "rhs_ns3d", no_proj)
+    assert _fails(ts.test_projection_and_mask, 16, 1)
+
+
+def test_wrong_viscous_sign_is_caught(monkeypatch):
+    orig = spectral.rhs_ns3d
+    monkeypatch.setattr(spectral, "rhs_ns3d", lambda uh, nu: orig(uh, -nu))
+    assert _fails(ts.test_tgv_energy_and_dissipation_closed_form)
+
+
+def test_wrong_mask_cutoff_is_caught(monkeypatch):
+    # K = N // 3 gives 3K = N at N = 18: a product mode aliases onto |k| = K
+    monkeypatch.setattr(spectral, "cutoff", lambda n: n // 3)
+    assert _fails(ts.test_dealiased_product_is_exact_truncation, 18, 2)
+
+
+def test_mistyped_tableau_entry_is_caught(monkeypatch):
+    A = [row[:] for row in tableaux.BS5["A"]]
+    A[5][3] = F(58653, 366081)
+    bad = dict(tableaux.BS5, A=A)
+    assert _fails(tt.test_main_weights_order, bad, 5) or _fails(tt.test_row_sums_equal_c, bad, "x")

@@ -1,0 +1,220 @@
+"""Pins of the oracle's transforms and right-hand sides (Sec. 2, Eq. (2);
+Sec. 3.2, Eqs. (4a-b)) against direct summation, closed forms and exact
+invariants of the dealiased semi-discrete system."""
+import numpy as np
+import pytest
+
+from oracle import diagnostics, spectral
+from paper_1810_10197_amd import inputs
+
+
+def grid(n, dim):
+    x = 2 * np.pi * np.arange(n) / n
+    return np.meshgrid(*([x] * dim), indexing="ij")   # [z][y][x] / [y][x]
+
+
+@pytest.mark.parametrize("n,dim", [(4, 3), (6, 3), (8, 2), (6, 2)])
+def test_forward_matches_direct_dft(n, dim):
+    rng = np.random.default_rng(n + dim)
+    u = rng.standard_normal((n,) * dim)
+    assert np.abs(spectral.forward(u, dim) - spectral.naive_forward(u)).max() < 1e-13
+
+
+@pytest.mark.parametrize("n,dim", [(4, 3), (6, 2), (8, 2)])
+def test_inverse_matches_direct_sum(n, dim):
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal((n,) * dim)
+    uh = spectral.forward(u, dim)
+    # direct summation reproduces the grid values
+    assert np.abs(spectral.naive_inverse(uh, n) - u).max() < 1e-12
+    assert np.abs(spectral.inverse(uh, n, dim) - u).max() < 1e-12
+
+
+def test_parseval_weights():
+    n = 8
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal((n, n, n))
+    uh = spectral.forward(u, 3)
+    w = diagnostics.weights(n, 3)
+    assert abs(np.sum(w * np.abs(uh) ** 2) - np.mean(u * u)) < 1e-14
+
+
+def test_tgv_energy_and_dissipation_closed_form():
+    """E0 = 1/8, eps0 = 3 nu / 4 for the 3D Taylor--Green vortex."""
+    n, nu = 16, 1.0 / 1600
+    u = inputs.tgv3d(n)
+    f = spectral.rhs_ns3d(u, nu)
+    assert abs(diagnostics.energy(u, 3) - 0.125) < 1e-15
+    assert abs(diagnostics.dissipation(u, f, 3) - 0.75 * nu) < 1e-15
+
+
+def test_tgv_generator_matches_sampled_field():
+    n = 12
+    Z, Y, X = grid(n, 3)
+    up = np.stack([np.sin(X) * np.cos(Y) * np.cos(Z),
+                   -np.cos(X) * np.sin(Y) * np.cos(Z), 0 * X])
+    assert np.abs(spectral.forward(up, 3) - inputs.tgv3d(n)).max() < 1e-15
+    Y2, X2 = grid(n, 2)
+    up2 = np.stack([np.sin(X2) * np.cos(Y2), -np.cos(X2) * np.sin(Y2)])
+    assert np.abs(spectral.forward(up2, 2) - inputs.tgv2d(n)).max() < 1e-15
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_2d_tgv_is_exact_viscous_decay(n):
+    """The 2D TGV is a steady Euler flow: f = -2 nu u_hat exactly (3D and 2D)."""
+    nu = 0.013
+    u3 = inputs.tgv2d_in3d(n)
+    f3 = spectral.rhs_ns3d(u3, nu)
+    assert np.abs(f3 + 2 * nu * u3).max() < 1e-12 * 2 * nu * np.abs(u3).max() + 1e-17
+    u2 = inputs.tgv2d(n)
+    f2 = spectral.rhs_ns2d(u2, nu)
+    assert np.abs(f2 + 2 * nu * u2).max() < 1e-12 * 2 * nu * np.abs(u2).max() + 1e-17
+
+
+@pytest.mark.parametrize("n,seed", [(16, 1), (18, 2), (32, 3)])
+def test_projection_and_mask(n, seed):
+    u = inputs.random_isotropic(n, seed)
+    f = spectral.rhs_ns3d(u, 0.01)
+    div = np.abs(spectral.divergence3(f)).max()
+    assert div <= 1e-13 * np.abs(f).max()
+    m = np.broadcast_to(spectral.mask(n, 3), f.shape[1:])
+    assert np.all(f[:, ~m] == 0.0)
+
+
+@pytest.mark.parametrize("n,seed", [(16, 4), (20, 5)])
+def test_inviscid_invariants(n, seed):
+    """With nu = 0 the dealiased rotational nonlinear term conserves energy
+    and helicity exactly: sum w Re(conj(u).f) = 0 = sum w Re(conj(omega).f)."""
+    u = inputs.random_isotropic(n, seed)
+    f = spectral.rhs_ns3d(u, 0.0)
+    w = diagnostics.weights(n, 3)
+    om = spectral.curl3(u, n)
+    scale = np.sqrt(np.sum(w * np.abs(u) ** 2)) * np.sqrt(np.sum(w * np.abs(f) ** 2))
+    e_rate = np.sum(w * np.real(np.conj(u) * f).sum(0))
+    h_rate = np.sum(w * np.real(np.conj(om) * f).sum(0))
+    scale_h = np.sqrt(np.sum(w * np.abs(om) ** 2)) * np.sqrt(np.sum(w * np.abs(f) ** 2))
+    assert abs(e_rate) < 1e-14 * scale
+    assert abs(h_rate) < 1e-14 * scale_h
+    assert np.abs(f).max() > 1e-3          # the nonlinear term is not trivially zero
+
+
+def test_viscous_dissipation_identity():
+    """eps = nu sum w |k|^2 |u_hat|^2 for any solenoidal field."""
+    n, nu = 16, 0.02
+    u = inputs.random_isotropic(n, 9)
+    f = spectral.rhs_ns3d(u, nu)
+    kx, ky, kz = spectral.wavenumbers(n, 3)
+    k2 = kx * kx + ky * ky + kz * kz
+    w = diagnostics.weights(n, 3)
+    expect = nu * np.sum(w * k2 * np.sum(np.abs(u) ** 2, axis=0))
+    assert abs(diagnostics.dissipation(u, f, 3) - expect) < 1e-14 * expect
+
+
+def test_rotation_equivariance():
+    """Cyclic relabelling of the axes (a proper rotation) commutes with f:
+    catches a wrong sign or a transposed operand in the curl or the cross
+    product."""
+    n, nu = 12, 0.01
+    u = inputs.random_isotropic(n, 11)
+    up = spectral.inverse(u, n, 3)
+    fp = spectral.inverse(spectral.rhs_ns3d(u, nu), n, 3)
+
+    def rot(a):  # v(y, z, x) = (a_y, a_z, a_x)(x, y, z)
+        return np.stack([a[1].transpose(2, 0, 1), a[2].transpose(2, 0, 1),
+                         a[0].transpose(2, 0, 1)])
+    v = spectral.forward(rot(up), 3)
+    fv = spectral.inverse(spectral.rhs_ns3d(v, nu), n, 3)
+    assert np.abs(fv - rot(fp)).max() < 1e-13
+
+
+def test_nonlinear_term_against_direct_derivatives():
+    """On a field with a handful of modes, u x omega computed by hand."""
+    n = 16
+    Z, Y, X = grid(n, 3)
+    a, b = 0.3, 0.7
+    # u = (a sin(2y), b sin(z), 0): omega = (-b cos z, 0, -2a cos 2y)
+    up = np.stack([a * np.sin(2 * Y), b * np.sin(Z), 0 * X])
+    om = np.stack([-b * np.cos(Z), 0 * X, -2 * a * np.cos(2 * Y)])
+    nl = np.stack([up[1] * om[2] - up[2] * om[1],
+                   up[2] * om[0] - up[0] * om[2],
+                   up[0] * om[1] - up[1] * om[0]])
+    uh = spectral.forward(up, 3)
+    nh = spectral.forward(nl, 3) * spectral.mask(n, 3)
+    kx, ky, kz = spectral.wavenumbers(n, 3)
+    k2 = kx * kx + ky * ky + kz * kz
+    p = np.where(k2 == 0, 0, (kx * nh[0] + ky * nh[1] + kz * nh[2]) / np.where(k2 == 0, 1, k2))
+    expect = nh - np.stack([kx * p, ky * p, kz * p])
+    assert np.abs(spectral.rhs_ns3d(uh, 0.0) - expect).max() < 1e-13 * np.abs(expect).max()
+
+
+def test_boussinesq_hydrostatic_and_budgets():
+    n, nu, kappa, ri = 32, 1e-3, 2e-3, 0.5
+    # stratification rho(y) only, u = 0: hydrostatic balance, pure diffusion
+    Y, X = grid(n, 2)
+    rho = spectral.forward(np.cos(Y) + 0.3 * np.sin(2 * Y), 2)
+    st = np.zeros((3, n, n // 2 + 1), dtype=complex)
+    st[2] = rho
+    f = spectral.rhs_ns2d(st, nu, kappa, ri)
+    kx, ky = spectral.wavenumbers(n, 2)
+    k2 = kx * kx + ky * ky
+    assert np.abs(f[:2]).max() < 1e-16
+    assert np.abs(f[2] + kappa * k2 * rho).max() < 1e-16
+    # general field: density variance budget and energy budget
+    rng = np.random.default_rng(3)
+    m = spectral.mask(n, 2)
+    st = np.zeros((3, n, n // 2 + 1), dtype=complex)
+    psi = spectral.forward(rng.standard_normal((n, n)), 2) * m
+    st[0] = 1j * ky * psi / np.where(k2 == 0, 1, k2)
+    st[1] = -1j * kx * psi / np.where(k2 == 0, 1, k2)
+    st[2] = spectral.forward(rng.standard_normal((n, n)), 2) * m
+    st = spectral.forward(spectral.inverse(st, n, 2), 2)    # Hermitian-clean
+    f = spectral.rhs_ns2d(st, nu, kappa, ri)
+    w = diagnostics.weights(n, 2)
+    rho_rate = np.sum(w * np.real(np.conj(st[2]) * f[2]))
+    assert abs(rho_rate + kappa * np.sum(w * k2 * np.abs(st[2]) ** 2)) < 1e-13
+    e_rate = -diagnostics.dissipation(st, f, 2)
+    expect = (-nu * np.sum(w * k2 * (np.abs(st[0]) ** 2 + np.abs(st[1]) ** 2))
+              - ri * np.sum(w * np.real(np.conj(st[1]) * st[2])))
+    assert abs(e_rate - expect) < 1e-13
+    assert np.abs(kx * f[0] + ky * f[1]).max() < 1e-14
+
+
+def _pad(uh, n, m):
+    """Embed an N half spectrum into an M > N half spectrum (zero padding)."""
+    out = np.zeros(uh.shape[:-3] + (m, m, m // 2 + 1), dtype=complex)
+    K = n // 2 - 1
+    ks = np.arange(-K, K + 1)
+    src = np.ix_(ks % n, ks % n, np.arange(K + 1))
+    dst = np.ix_(ks % m, ks % m, np.arange(K + 1))
+    for c in range(uh.shape[0]):
+        out[c][dst] = uh[c][src]
+    return out
+
+
+@pytest.mark.parametrize("n,seed", [(18, 2), (16, 3)])
+def test_dealiased_product_is_exact_truncation(n, seed):
+    """The 2/3 rule is alias-free: on every retained mode the masked
+    pseudo-spectral product equals the exact product of the band-limited
+    fields (computed on a 2N grid, where no alias can reach a retained
+    mode), then truncated."""
+    rng = np.random.default_rng(seed)
+    msk = spectral.mask(n, 3)
+    uh = (rng.standard_normal((3,) + msk.shape) + 1j * rng.standard_normal((3,) + msk.shape)) * msk
+    uh = spectral.forward(spectral.inverse(uh, n, 3), 3) * msk      # a real field
+    m = 2 * n
+    up = _pad(uh, n, m)
+    u = spectral.inverse(up, m, 3)
+    w = spectral.inverse(spectral.curl3(up, m), m, 3)
+    exact_big = spectral.forward(spectral.cross3(u, w), 3)
+    K = spectral.cutoff(n)
+    ks = np.arange(-K, K + 1)
+    src = np.ix_(ks % m, ks % m, np.arange(K + 1))
+    dst = np.ix_(ks % n, ks % n, np.arange(K + 1))
+    exact = np.zeros_like(uh)
+    for c in range(3):
+        exact[c][dst] = exact_big[c][src]
+    kx, ky, kz = spectral.wavenumbers(n, 3)
+    k2 = kx * kx + ky * ky + kz * kz
+    p = np.where(k2 == 0, 0, (kx * exact[0] + ky * exact[1] + kz * exact[2]) / np.where(k2 == 0, 1, k2))
+    expect = exact - np.stack([kx * p, ky * p, kz * p])
+    assert np.abs(spectral.rhs_ns3d(uh, 0.0) - expect).max() < 1e-13 * np.abs(expect).max()
