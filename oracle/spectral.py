@@ -173,7 +173,7 @@ def rhs_ns3d(uh, nu):
     5. pressure: p_hat = (k . N_hat)/|k|^2, with p_hat(0) = 0 -- the Leray
        projection that eliminates P (the stray factor i in the printed
        projection term is a typo, see DESIGN.md);
-    6. f = N_hat - k p_hat - nu |k|^2 u_hat.
+    6. f = N_hat - k p_hat - nu |k|^2 u_hat, and f = 0 at k = 0.
     """
     n = uh.shape[1]
     kx, ky, kz = wavenumbers(n, 3)
@@ -186,6 +186,10 @@ def rhs_ns3d(uh, nu):
     p = (kx * nl[0] + ky * nl[1] + kz * nl[2]) / k2safe
     p = np.where(k2 == 0, 0.0, p)
     f = np.stack([nl[0] - kx * p, nl[1] - ky * p, nl[2] - kz * p]) - nu * k2 * uh
+    # k = 0: the projection is undefined there; the mean of u x omega over a
+    # periodic box vanishes for a solenoidal field, so the mean velocity is
+    # held fixed (f(0) = 0) rather than fed with rounding noise.
+    f[:, 0, 0, 0] = 0.0
     return f
 
 
@@ -220,6 +224,7 @@ def rhs_ns2d(uh, nu, kappa=0.0, ri=0.0):
     if uh.shape[0] == 2:
         return np.stack([fu, fv])
     frho = -1j * (kx * qx + ky * qy) - kappa * k2 * uh[2]
+    frho[0, 0] = 0.0
     return np.stack([fu, fv, frho])
 
 
