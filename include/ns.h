@@ -1,0 +1,180 @@
+/*
+ * ns.h -- C ABI of the MI355X (gfx950) Fourier pseudo-spectral Navier--Stokes
+ * time integrator.
+ *
+ * The library integrates the ODE system that the Fourier pseudo-spectral
+ * discretisation turns the incompressible Navier--Stokes equations into
+ * (Sec. 2.1, Eq. (2)):  d u_hat / dt = f(u_hat), with
+ *
+ *   f(u_hat) = N_hat - k (k . N_hat) / |k|^2 - nu |k|^2 u_hat,
+ *   N_hat    = 2/3-dealiased DFT of u x omega evaluated in physical space,
+ *
+ * and, in two dimensions, the Boussinesq system of Sec. 3.2, Eqs. (3a-c),
+ * (4a-b).  Steppers: classical RK4 with a fixed step and the Bogacki--Shampine
+ * 5(4) pair (Appendix A.3, Eq. (8)) with the error estimate and step-size
+ * controller of Sec. 2.2.1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State layout (device memory, complex128 = two doubles, re then im):
+ *   3D: [batch][3][n][n][n/2+1]  index [kz][ky][kx], components (u, v, w)
+ *   2D: [batch][c][n][n/2+1]     index [ky][kx],     components (u, v[, rho])
+ * i.e. numpy.fft.rfftn of the physical field over its spatial axes divided by
+ * n^dim (the normalised transform; physical values are sum_k u_hat e^{ik.x}).
+ * Full axes hold wavenumbers 0..n/2-1, -n/2..-1; the last axis 0..n/2.  Only
+ * modes with every |k_j| <= K = (n-1)/3 (2/3 rule) are read; the library
+ * writes zeros everywhere else.  The kx = 0 plane must be Hermitian (a real
+ * field).  Internally the solver keeps only the retained modes.
+ *
+ * Memory ownership: the caller owns every device buffer (state, f, the
+ * workspace); the solver keeps non-owning pointers and never frees caller
+ * memory.  The library itself allocates no device memory.  Host pointers are
+ * marked "host"; all others are device pointers.
+ *
+ * Streams: every call is enqueued on the stream given to ns_init (a
+ * hipStream_t passed as void*; NULL = the default stream) and is
+ * asynchronous, except calls that return values in host memory, which
+ * synchronise that stream before returning.
+ *
+ * Errors: functions return an int status; 0 = NS_OK, 1 = NS_STEP_REJECTED
+ * (informational), negative = error.  No C++ exception crosses the ABI.  A
+ * failed call leaves the committed state unchanged unless stated otherwise.
+ */
+#ifndef NS_H
+#define NS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NS_OK 0
+#define NS_STEP_REJECTED 1
+#define NS_ERR_ARG (-1)         /* invalid argument or configuration */
+#define NS_ERR_HIP (-2)         /* a HIP runtime call failed */
+#define NS_ERR_NOMEM (-3)       /* workspace too small */
+#define NS_ERR_NONFINITE (-4)   /* a non-finite value reached a reduction */
+#define NS_ERR_STEPFAIL (-5)    /* too many consecutive rejected steps */
+#define NS_ERR_UNSUPPORTED (-6) /* size or mode not built */
+#define NS_ERR_STATE (-7)       /* call out of order (e.g. no state set) */
+
+#define NS_FP32 0               /* FFTs and nonlinear term in float */
+#define NS_FP64 1               /* FFTs and nonlinear term in double */
+
+#define NS_CTRL_PI 0            /* Sec. 2.2.1 controller (optionally PI) */
+#define NS_CTRL_MLP 1           /* learned proposer with the PI fallback */
+
+#define NS_FORCE_COMMIT 1       /* ns_step_bs5: commit whatever err is */
+
+typedef struct ns_config {
+  int dim;              /* 3, or 2 */
+  int n;                /* points per direction: power of two, 8..512 (3D), 8..1024 (2D) */
+  int batch;            /* ensemble members B >= 1, stepped together */
+  int rhs_precision;    /* NS_FP32 or NS_FP64; state and reductions are always FP64 */
+  int scalar;           /* 2D only: 1 = Boussinesq density as third component */
+  double ri;            /* Boussinesq buoyancy coefficient (Atwood x gravity) */
+  double kappa;         /* Boussinesq scalar diffusivity */
+  double force_kf;      /* 3D: forcing band 0 < |k| <= kf after each accepted step; <= 0 off */
+  double force_e0;      /* energy the forcing restores */
+} ns_config;
+
+typedef struct ns_solver ns_solver;
+
+/* Per-member counters of ns_integrate. */
+typedef struct ns_stats {
+  double t;             /* time reached */
+  double h_next;        /* step size the controller proposes next */
+  double last_err;      /* error estimate of the last attempt */
+  long long n_rhs;      /* right-hand-side evaluations, rejected attempts included */
+  long long n_accept;
+  long long n_reject;
+} ns_stats;
+
+/* Bytes of device workspace ns_init needs for cfg (0 if cfg is invalid). */
+size_t ns_workspace_bytes(const ns_config* cfg);
+
+/* Create a solver.  nu_host[batch]: viscosity (1/Re) per member.  workspace:
+ * device buffer of at least ns_workspace_bytes(cfg) bytes, 256-byte aligned,
+ * owned by the caller and kept until ns_free.  stream: hipStream_t or NULL.
+ * On success *out receives the solver; the state is unset until
+ * ns_set_state. */
+int ns_init(const ns_config* cfg, const double* nu_host, void* workspace,
+            size_t workspace_bytes, void* stream, ns_solver** out);
+
+/* Copy in / out the state (layout above).  set_state drops non-retained modes
+ * and invalidates the cached first stage f(u_n). */
+int ns_set_state(ns_solver* s, const void* uhat);
+int ns_get_state(ns_solver* s, void* uhat);
+
+/* Per-member viscosity (host array of batch values). */
+int ns_set_nu(ns_solver* s, const double* nu_host);
+
+/* f(u_hat) of Eq. (2) (or Eqs. (4a-b)) for every member: uhat and f in the
+ * state layout, may not alias.  Does not touch the solver's state. */
+int ns_rhs(ns_solver* s, const void* uhat, void* f);
+
+/* One classical RK4 step of size h for every member (committed). */
+int ns_step_rk4(ns_solver* s, double h);
+
+/* One attempt of the BS5 pair with step h for every member (Sec. 2.2,
+ * Sec. 2.2.1).  err_host[batch] (host, may be NULL) receives
+ * err = max_j sqrt(mean_k |(u - v)_j / sc_j|^2) with
+ * sc = atol + rtol max(|u_n|, |u_{n+1}|).  A member commits iff its err <= 1,
+ * or always with flags & NS_FORCE_COMMIT (fixed-step BS5).  Returns
+ * NS_STEP_REJECTED if any member did not commit. */
+int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags,
+                double* err_host);
+
+/* Adaptive BS5 integration of every member from its current time to t_end
+ * (Sec. 2.2.1): h0 is the first trial step, the factor
+ * 0.8 err^(-1/5) clamped to [0.01, 2] (1 right after a rejection) sets the
+ * next step, a step is accepted iff err <= 1, the last step is clipped to land
+ * on t_end.  controller: NS_CTRL_PI or NS_CTRL_MLP (needs weights, see
+ * ns_mlp_set_weights).  stats_host[batch] (host, may be NULL) receives the
+ * counters.  Returns NS_ERR_STEPFAIL after 50 consecutive rejections of a
+ * member (that member's state is its last accepted one). */
+int ns_integrate(ns_solver* s, double t_end, double h0, double atol,
+                 double rtol, int controller, ns_stats* stats_host);
+
+/* Time of each member (host array of batch values); set_time resets it. */
+int ns_get_time(ns_solver* s, double* t_host);
+int ns_set_time(ns_solver* s, const double* t_host);
+
+/* Diagnostics of the current state (Sec. 3.1): kinetic energy
+ * E = 1/2 sum w |u_hat|^2, dissipation rate eps = -sum w Re(conj(u_hat).f)
+ * and the 16 shell energies (bin b: floor(16 |k| / K) = b, last bin open),
+ * w = 1 on the kx = 0 plane and 2 elsewhere.  Host arrays of batch, batch
+ * and 16*batch doubles; any may be NULL. */
+int ns_diagnostics(ns_solver* s, double* energy_host, double* dissipation_host,
+                   double* shells_host);
+
+/* Evaluate f(u_n) into the solver's cached first stage (used by the next BS5
+ * attempt and by ns_diagnostics).  Asynchronous. */
+int ns_refresh_rhs(ns_solver* s);
+
+/* Kernel timing with HIP events recorded on the solver's stream around every
+ * kernel launch while profiling is on (a tracing aid; the events add a few
+ * microseconds per launch).  Index: 0..4 the five right-hand-side passes
+ * (z-inverse, y-inverse, x-pass, y-forward, z-forward), 5 stage
+ * combinations, 6 reductions, 7 other.  stop synchronises the stream and
+ * fills total milliseconds and launch counts per index. */
+#define NS_NPROF 8
+typedef struct ns_kernel_times {
+  double ms[NS_NPROF];
+  long long count[NS_NPROF];
+} ns_kernel_times;
+int ns_profile_start(ns_solver* s);
+int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
+
+/* Static description of a status code. */
+const char* ns_strerror(int status);
+
+/* Release the solver's host-side bookkeeping (caller memory is untouched). */
+void ns_free(ns_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NS_H */

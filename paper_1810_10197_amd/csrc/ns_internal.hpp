@@ -1,0 +1,91 @@
+// Internal interfaces between the kernel translation units and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace nsk {
+
+constexpr int TWN_TABLE = 1024;   // twiddle table length (exp(-2 pi i m / 1024))
+
+// Grid geometry of one member.  Retained modes (2/3 rule): |k_j| <= K on every
+// axis.  Compact spectral layout per component: [kz'][ky'][kx] (3D) or
+// [ky'][kx] (2D) with kz', ky' in 0..2K (k = k' for k' <= K, k' - (2K+1)
+// otherwise) and kx in 0..K.
+struct Geom {
+  int dim, n, K, Kf, Kx;
+  int ncomp;          // state components: 3 (3D), 2 or 3 (2D)
+  long long mr;       // retained modes per component
+  long long epm;      // compact elements per member = ncomp * mr
+  long long full;     // half-spectrum entries per component (n^(d-1) (n/2+1))
+  int batch;
+};
+
+// Physical parameters seen by the RHS epilogue.
+struct RhsParams {
+  const double* nu;   // [batch]
+  double ri, kappa;   // Boussinesq
+};
+
+// Optional timing hook called around every kernel launch: phase 0 before,
+// 1 after; id is one of the PROF_* values.
+typedef void (*HookFn)(void* ctx, int id, int phase);
+enum { PROF_P1 = 0, PROF_P2, PROF_P3, PROF_P4, PROF_P5, PROF_COMBINE, PROF_REDUCE, PROF_OTHER, NPROF };
+
+// Scratch for one RHS evaluation (rhs precision T).
+struct RhsBufs {
+  void* a1;           // after the first inverse pass
+  void* a2;           // after the second inverse pass
+  HookFn hook;        // may be null
+  void* hook_ctx;
+};
+
+// k = f(U) on compact FP64 buffers for every member (3D: rhs3d.hip,
+// 2D: rhs2d.hip).  tw: table of TWN twiddles in the rhs precision.
+size_t rhs3d_scratch_bytes(const Geom& g, int fp64);
+hipError_t rhs3d_compact(const Geom& g, int fp64, const double2* U, double2* k,
+                         const RhsParams& p, const RhsBufs& b, const void* tw, hipStream_t st);
+size_t rhs2d_scratch_bytes(const Geom& g, int fp64);
+hipError_t rhs2d_compact(const Geom& g, int fp64, const double2* U, double2* k,
+                         const RhsParams& p, const RhsBufs& b, const void* tw, hipStream_t st);
+
+// ---- FP64 state kernels (step.hip) ----
+constexpr int MAXTERMS = 9;
+struct Combo {
+  const double2* src[MAXTERMS];
+  double coef[MAXTERMS];
+  int nterms;
+};
+// out = base + h_m * sum_j coef_j src_j (per member m; base may be null = 0)
+hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
+                   double2* out, hipStream_t st);
+
+// Full <-> compact state conversions.
+hipError_t pack_state(const Geom& g, const double2* full, double2* compact, hipStream_t st);
+hipError_t unpack_state(const Geom& g, const double2* compact, double2* full, hipStream_t st);
+
+// Fused reduction: embedded error sums (if delta != null), energy,
+// dissipation (if fk != null) and shell spectrum of `un` per member.
+// out[m*NRED + ...]: [0..2] sum |delta_j/sc_j|^2, [3] E, [4] eps, [5..20] shells.
+constexpr int NRED = 21;
+constexpr int NBINS = 16;
+struct ReduceArgs {
+  const double2* uo;      // u_n (for sc), may be null when no error
+  const double2* un;      // state whose diagnostics are taken (u_{n+1})
+  const double2* fk;      // f(un) for the dissipation, may be null
+  Combo delta;            // delta = h_m * sum coef_j src_j (nterms = 0: no error)
+  const double* h;        // [batch]
+  double atol, rtol;
+};
+size_t reduce_scratch_bytes(const Geom& g);
+hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, double* out,
+                        hipStream_t st);
+
+// p[0..n) = v
+hipError_t fill(double* p, double v, int n, hipStream_t st);
+
+// Copy member slices src -> dst for members with mask[m] != 0 (host mask copied
+// as a device array).
+hipError_t masked_copy(const Geom& g, const double2* src, double2* dst, const int* mask_dev,
+                       hipStream_t st);
+
+}  // namespace nsk

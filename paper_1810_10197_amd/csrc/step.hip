@@ -1,0 +1,248 @@
+// FP64 state kernels around the right-hand side: Runge--Kutta stage
+// combinations (Sec. 2.2), the embedded error norm of Sec. 2.2.1 fused with
+// the kinetic-energy / dissipation / shell diagnostics of Sec. 3.1, and the
+// conversions between the full half-spectrum layout of the C ABI and the
+// compact retained-mode layout used internally.  All reductions are
+// deterministic: a fixed number of blocks per member, fixed per-thread
+// strides, fixed shuffle trees and a fixed-order final sum.
+#include "ns_internal.hpp"
+
+namespace nsk {
+
+// Decode a compact element index (within one member) into component and
+// signed wavenumbers.
+struct Modes {
+  int c, kx, ky, kz;
+};
+__device__ __forceinline__ Modes decode(const Geom& g, long long i) {
+  Modes r;
+  r.c = (int)(i / g.mr);
+  long long q = i - (long long)r.c * g.mr;
+  r.kx = (int)(q % g.Kx);
+  q /= g.Kx;
+  const int kyp = (int)(q % g.Kf);
+  r.ky = kyp <= g.K ? kyp : kyp - g.Kf;
+  if (g.dim == 3) {
+    const int kzp = (int)(q / g.Kf);
+    r.kz = kzp <= g.K ? kzp : kzp - g.Kf;
+  } else {
+    r.kz = 0;
+  }
+  return r;
+}
+
+// Offset of a retained mode in the full half-spectrum layout of one component.
+__device__ __forceinline__ long long full_offset(const Geom& g, const Modes& md) {
+  const long long nh = g.n / 2 + 1;
+  const int iy = md.ky < 0 ? md.ky + g.n : md.ky;
+  if (g.dim == 3) {
+    const int iz = md.kz < 0 ? md.kz + g.n : md.kz;
+    return ((long long)iz * g.n + iy) * nh + md.kx;
+  }
+  return (long long)iy * nh + md.kx;
+}
+
+__global__ void k_combine(const double2* __restrict__ base, Combo c, const double* __restrict__ h,
+                          double2* __restrict__ out, long long epm, long long total) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const double hm = h[i / epm];
+    double sx = 0.0, sy = 0.0;
+    for (int j = 0; j < c.nterms; ++j) {
+      const double2 v = c.src[j][i];
+      sx += c.coef[j] * v.x;
+      sy += c.coef[j] * v.y;
+    }
+    double2 r = base ? base[i] : make_double2(0.0, 0.0);
+    r.x += hm * sx;
+    r.y += hm * sy;
+    out[i] = r;
+  }
+}
+
+static unsigned grid_for(long long total, int bs) {
+  long long b = (total + bs - 1) / bs;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
+                   double2* out, hipStream_t st) {
+  const long long total = g.epm * g.batch;
+  hipLaunchKernelGGL(k_combine, dim3(grid_for(total, 256)), dim3(256), 0, st, base, c, h, out,
+                     g.epm, total);
+  return hipGetLastError();
+}
+
+__global__ void k_pack(const double2* __restrict__ full, double2* __restrict__ compact, Geom g,
+                       long long total) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const long long m = i / g.epm, q = i - m * g.epm;
+    const Modes md = decode(g, q);
+    compact[i] = full[(m * g.ncomp + md.c) * g.full + full_offset(g, md)];
+  }
+}
+
+hipError_t pack_state(const Geom& g, const double2* full, double2* compact, hipStream_t st) {
+  const long long total = g.epm * g.batch;
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(total, 256)), dim3(256), 0, st, full, compact, g, total);
+  return hipGetLastError();
+}
+
+__global__ void k_unpack(const double2* __restrict__ compact, double2* __restrict__ full, Geom g,
+                         long long total) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long nh = g.n / 2 + 1;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const long long mc = i / g.full, q = i - mc * g.full;       // member*ncomp + c
+    const int kx = (int)(q % nh);
+    const long long r = q / nh;
+    const int iy = (int)(r % g.n);
+    const int iz = (int)(r / g.n);                             // 0 in 2D
+    const int ky = iy < g.n / 2 ? iy : iy - g.n;
+    const int kz = iz < g.n / 2 ? iz : iz - g.n;
+    const bool keep = kx <= g.K && ky <= g.K && -ky <= g.K && (g.dim == 2 || (kz <= g.K && -kz <= g.K));
+    double2 v = make_double2(0.0, 0.0);
+    if (keep) {
+      const long long m = mc / g.ncomp, c = mc - m * g.ncomp;
+      const int kyp = ky >= 0 ? ky : ky + g.Kf;
+      long long off = (long long)kyp * g.Kx + kx;
+      if (g.dim == 3) off += (long long)(kz >= 0 ? kz : kz + g.Kf) * g.Kf * g.Kx;
+      v = compact[m * g.epm + c * g.mr + off];
+    }
+    full[i] = v;
+  }
+}
+
+hipError_t unpack_state(const Geom& g, const double2* compact, double2* full, hipStream_t st) {
+  const long long total = g.full * g.ncomp * g.batch;
+  hipLaunchKernelGGL(k_unpack, dim3(grid_for(total, 256)), dim3(256), 0, st, compact, full, g, total);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int RBS = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+static int reduce_blocks(const Geom& g) {
+  long long nb = (g.epm + (long long)RBS * 8 - 1) / ((long long)RBS * 8);
+  if (nb < 1) nb = 1;
+  if (nb > 1024) nb = 1024;
+  return (int)nb;
+}
+
+size_t reduce_scratch_bytes(const Geom& g) {
+  return (size_t)reduce_blocks(g) * g.batch * NRED * sizeof(double);
+}
+
+__global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, Geom g, double* __restrict__ partials,
+                                                int nblk, int nvel) {
+  const int m = blockIdx.y;
+  double acc[NRED];
+#pragma unroll
+  for (int q = 0; q < NRED; ++q) acc[q] = 0.0;
+  const long long base = (long long)m * g.epm;
+  const double hm = a.h ? a.h[m] : 0.0;
+  const double kdiv = g.K > 0 ? (double)g.K : 1.0;
+  for (long long i = (long long)blockIdx.x * RBS + threadIdx.x; i < g.epm; i += (long long)nblk * RBS) {
+    const long long gi = base + i;
+    const Modes md = decode(g, i);
+    const double2 un = a.un[gi];
+    if (a.delta.nterms > 0) {
+      double dx = 0.0, dy = 0.0;
+      for (int j = 0; j < a.delta.nterms; ++j) {
+        const double2 v = a.delta.src[j][gi];
+        dx += a.delta.coef[j] * v.x;
+        dy += a.delta.coef[j] * v.y;
+      }
+      dx *= hm;
+      dy *= hm;
+      const double2 uo = a.uo[gi];
+      const double mo = sqrt(uo.x * uo.x + uo.y * uo.y), mn = sqrt(un.x * un.x + un.y * un.y);
+      const double sc = a.atol + a.rtol * (mo > mn ? mo : mn);
+      const double r = (dx * dx + dy * dy) / (sc * sc);
+      acc[0] += md.c == 0 ? r : 0.0;
+      acc[1] += md.c == 1 ? r : 0.0;
+      acc[2] += md.c == 2 ? r : 0.0;
+    }
+    if (md.c < nvel) {
+      const double w = md.kx == 0 ? 1.0 : 2.0;
+      const double e = 0.5 * w * (un.x * un.x + un.y * un.y);
+      acc[3] += e;
+      if (a.fk) {
+        const double2 f = a.fk[gi];
+        acc[4] -= w * (un.x * f.x + un.y * f.y);
+      }
+      const double kmag = sqrt((double)(md.kx * md.kx + md.ky * md.ky + md.kz * md.kz));
+      int bin = (int)floor((16.0 * kmag) / kdiv);
+      bin = bin > NBINS - 1 ? NBINS - 1 : bin;
+#pragma unroll
+      for (int b = 0; b < NBINS; ++b) acc[5 + b] += (b == bin) ? e : 0.0;
+    }
+  }
+  __shared__ double red[RBS / 64][NRED];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NRED; ++q) {
+    const double s = wave_sum(acc[q]);
+    if (lane == 0) red[wv][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NRED) {
+    double s = 0.0;
+    for (int w = 0; w < RBS / 64; ++w) s += red[w][threadIdx.x];
+    partials[((long long)m * nblk + blockIdx.x) * NRED + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_reduce_final(const double* __restrict__ partials, int nblk, double* __restrict__ out) {
+  const int m = blockIdx.x;
+  const int q = threadIdx.x;
+  if (q >= NRED) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partials[((long long)m * nblk + b) * NRED + q];
+  out[(long long)m * NRED + q] = s;
+}
+
+hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, double* out,
+                        hipStream_t st) {
+  const int nblk = reduce_blocks(g);
+  const int nvel = g.dim == 3 ? 3 : 2;
+  hipLaunchKernelGGL(k_reduce, dim3(nblk, g.batch), dim3(RBS), 0, st, a, g, partials, nblk, nvel);
+  hipLaunchKernelGGL(k_reduce_final, dim3(g.batch), dim3(64), 0, st, partials, nblk, out);
+  return hipGetLastError();
+}
+
+__global__ void k_masked_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                              const int* __restrict__ mask, long long epm, long long total) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+    if (mask[i / epm]) dst[i] = src[i];
+}
+
+__global__ void k_fill(double* __restrict__ p, double v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t fill(double* p, double v, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t masked_copy(const Geom& g, const double2* src, double2* dst, const int* mask_dev,
+                       hipStream_t st) {
+  const long long total = g.epm * g.batch;
+  hipLaunchKernelGGL(k_masked_copy, dim3(grid_for(total, 256)), dim3(256), 0, st, src, dst,
+                     mask_dev, g.epm, total);
+  return hipGetLastError();
+}
+
+}  // namespace nsk

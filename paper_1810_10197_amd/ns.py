@@ -1,0 +1,299 @@
+"""Thin ctypes binding of the C ABI in include/ns.h (argument marshalling only).
+
+The module-level functions carry the C names (ns_init, ns_rhs, ...) and
+take plain integers for device pointers; :class:`Solver` wraps them with
+PyTorch tensors, which provide the device memory (state, right-hand side,
+workspace) and the stream.  Every numerical step runs in the HIP library;
+if ``libns.so`` is missing this module raises on import.
+"""
+import ctypes
+import os
+
+import numpy as np
+# torch first: libns.so then binds to the HIP runtime torch already loaded
+# (same soname), so streams and device pointers from torch are valid in it.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libns.so")
+
+NS_OK = 0
+NS_STEP_REJECTED = 1
+NS_ERR_ARG = -1
+NS_ERR_HIP = -2
+NS_ERR_NOMEM = -3
+NS_ERR_NONFINITE = -4
+NS_ERR_STEPFAIL = -5
+NS_ERR_UNSUPPORTED = -6
+NS_ERR_STATE = -7
+NS_FP32 = 0
+NS_FP64 = 1
+NS_CTRL_PI = 0
+NS_CTRL_MLP = 1
+NS_FORCE_COMMIT = 1
+
+EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_set_nu",
+           "ns_rhs", "ns_step_rk4", "ns_step_bs5", "ns_integrate", "ns_get_time",
+           "ns_set_time", "ns_diagnostics", "ns_refresh_rhs", "ns_profile_start",
+           "ns_profile_stop", "ns_strerror", "ns_free"]
+PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other"]
+
+
+class NsConfig(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("batch", ctypes.c_int),
+                ("rhs_precision", ctypes.c_int), ("scalar", ctypes.c_int),
+                ("ri", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("force_kf", ctypes.c_double), ("force_e0", ctypes.c_double)]
+
+
+class NsStats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h_next", ctypes.c_double),
+                ("last_err", ctypes.c_double), ("n_rhs", ctypes.c_longlong),
+                ("n_accept", ctypes.c_longlong), ("n_reject", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NsKernelTimes(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_longlong * 8)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("HIP library %s is not built (run __graft_entry__.build())" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_DP = ctypes.POINTER(ctypes.c_double)
+_sig = {
+    "ns_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(NsConfig)]),
+    "ns_init": (_I, [ctypes.POINTER(NsConfig), _DP, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "ns_set_state": (_I, [_P, _P]),
+    "ns_get_state": (_I, [_P, _P]),
+    "ns_set_nu": (_I, [_P, _DP]),
+    "ns_rhs": (_I, [_P, _P, _P]),
+    "ns_step_rk4": (_I, [_P, _D]),
+    "ns_step_bs5": (_I, [_P, _D, _D, _D, _I, _DP]),
+    "ns_integrate": (_I, [_P, _D, _D, _D, _D, _I, ctypes.POINTER(NsStats)]),
+    "ns_get_time": (_I, [_P, _DP]),
+    "ns_set_time": (_I, [_P, _DP]),
+    "ns_diagnostics": (_I, [_P, _DP, _DP, _DP]),
+    "ns_refresh_rhs": (_I, [_P]),
+    "ns_profile_start": (_I, [_P]),
+    "ns_profile_stop": (_I, [_P, ctypes.POINTER(NsKernelTimes)]),
+    "ns_strerror": (ctypes.c_char_p, [_I]),
+    "ns_free": (None, [_P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class NsError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__("%s: %s (%d)" % (where, ns_strerror(status), status))
+        self.status = status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+def _check(status, where, ok=(NS_OK,)):
+    if status not in ok:
+        raise NsError(status, where)
+    return status
+
+
+# ---------------------------------------------------------------- C names
+def ns_strerror(status):
+    return _lib.ns_strerror(int(status)).decode()
+
+
+def ns_workspace_bytes(cfg):
+    return int(_lib.ns_workspace_bytes(ctypes.byref(cfg)))
+
+
+def ns_init(cfg, nu, workspace_ptr, workspace_bytes, stream_ptr):
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    h = _P()
+    _check(_lib.ns_init(ctypes.byref(cfg), _dptr(nu), _P(workspace_ptr), workspace_bytes,
+                        _P(stream_ptr), ctypes.byref(h)), "ns_init")
+    return h
+
+
+def ns_set_state(h, uhat_ptr):
+    return _check(_lib.ns_set_state(h, _P(uhat_ptr)), "ns_set_state")
+
+
+def ns_get_state(h, uhat_ptr):
+    return _check(_lib.ns_get_state(h, _P(uhat_ptr)), "ns_get_state")
+
+
+def ns_set_nu(h, nu):
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    return _check(_lib.ns_set_nu(h, _dptr(nu)), "ns_set_nu")
+
+
+def ns_rhs(h, uhat_ptr, f_ptr):
+    return _check(_lib.ns_rhs(h, _P(uhat_ptr), _P(f_ptr)), "ns_rhs")
+
+
+def ns_step_rk4(h, dt):
+    return _check(_lib.ns_step_rk4(h, float(dt)), "ns_step_rk4")
+
+
+def ns_step_bs5(h, dt, atol, rtol, flags, err_out):
+    return _check(_lib.ns_step_bs5(h, float(dt), float(atol), float(rtol), int(flags),
+                                   _dptr(err_out)), "ns_step_bs5",
+                  ok=(NS_OK, NS_STEP_REJECTED))
+
+
+def ns_integrate(h, t_end, h0, atol, rtol, controller, stats_out):
+    return _check(_lib.ns_integrate(h, float(t_end), float(h0), float(atol), float(rtol),
+                                    int(controller), stats_out), "ns_integrate")
+
+
+def ns_get_time(h, t_out):
+    return _check(_lib.ns_get_time(h, _dptr(t_out)), "ns_get_time")
+
+
+def ns_set_time(h, t):
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    return _check(_lib.ns_set_time(h, _dptr(t)), "ns_set_time")
+
+
+def ns_diagnostics(h, e_out, eps_out, shells_out):
+    return _check(_lib.ns_diagnostics(h, _dptr(e_out), _dptr(eps_out), _dptr(shells_out)),
+                  "ns_diagnostics")
+
+
+def ns_refresh_rhs(h):
+    return _check(_lib.ns_refresh_rhs(h), "ns_refresh_rhs")
+
+
+def ns_profile_start(h):
+    return _check(_lib.ns_profile_start(h), "ns_profile_start")
+
+
+def ns_profile_stop(h, out):
+    return _check(_lib.ns_profile_stop(h, ctypes.byref(out)), "ns_profile_stop")
+
+
+def ns_free(h):
+    _lib.ns_free(h)
+
+
+# ---------------------------------------------------------------- wrapper
+class Solver:
+    """One solver instance on a CUDA/HIP device, memory owned by torch."""
+
+    def __init__(self, dim=3, n=32, batch=1, nu=0.0, rhs_precision="fp32", scalar=0,
+                 ri=0.0, kappa=0.0, force_kf=0.0, force_e0=0.0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        prec = {"fp32": NS_FP32, "fp64": NS_FP64}[rhs_precision]
+        self.cfg = NsConfig(dim, n, batch, prec, scalar, ri, kappa, force_kf, force_e0)
+        nbytes = ns_workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise ValueError("unsupported configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.device)
+        nu = np.broadcast_to(np.asarray(nu, dtype=np.float64), (batch,)).copy()
+        self.handle = ns_init(self.cfg, nu, self._ws_ptr, nbytes, self.stream.cuda_stream)
+        self.batch = batch
+        self.dim = dim
+        self.n = n
+        self.ncomp = 3 if dim == 3 else (3 if scalar else 2)
+        self.shape = ((batch, self.ncomp) + (n,) * (dim - 1) + (n // 2 + 1,))
+
+    def _tensor(self, x):
+        t = self.torch
+        if isinstance(x, np.ndarray):
+            x = t.from_numpy(np.ascontiguousarray(x, dtype=np.complex128))
+        x = x.to(device=self.device, dtype=t.complex128).contiguous()
+        if tuple(x.shape) != self.shape:
+            x = x.reshape(self.shape)
+        return x
+
+    def set_state(self, uhat):
+        x = self._tensor(uhat)
+        ns_set_state(self.handle, x.data_ptr())
+        self.stream.synchronize()
+
+    def get_state(self):
+        out = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        ns_get_state(self.handle, out.data_ptr())
+        self.stream.synchronize()
+        return out
+
+    def rhs(self, uhat):
+        x = self._tensor(uhat)
+        out = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        ns_rhs(self.handle, x.data_ptr(), out.data_ptr())
+        self.stream.synchronize()
+        return out
+
+    def set_nu(self, nu):
+        ns_set_nu(self.handle, np.broadcast_to(np.asarray(nu, dtype=np.float64), (self.batch,)))
+
+    def step_rk4(self, h):
+        ns_step_rk4(self.handle, h)
+
+    def step_bs5(self, h, atol, rtol, force=False):
+        errs = np.zeros(self.batch)
+        st = ns_step_bs5(self.handle, h, atol, rtol, NS_FORCE_COMMIT if force else 0, errs)
+        return st, errs
+
+    def integrate(self, t_end, h0, atol, rtol, controller="pi"):
+        stats = (NsStats * self.batch)()
+        ctl = {"pi": NS_CTRL_PI, "mlp": NS_CTRL_MLP}[controller]
+        ns_integrate(self.handle, t_end, h0, atol, rtol, ctl, stats)
+        return [s.as_dict() for s in stats]
+
+    def time(self):
+        t = np.zeros(self.batch)
+        ns_get_time(self.handle, t)
+        return t
+
+    def set_time(self, t):
+        ns_set_time(self.handle, np.broadcast_to(np.asarray(t, dtype=np.float64), (self.batch,)))
+
+    def diagnostics(self):
+        e = np.zeros(self.batch)
+        eps = np.zeros(self.batch)
+        sh = np.zeros(self.batch * 16)
+        ns_diagnostics(self.handle, e, eps, sh)
+        return e, eps, sh.reshape(self.batch, 16)
+
+    def refresh_rhs(self):
+        ns_refresh_rhs(self.handle)
+
+    def profile_start(self):
+        ns_profile_start(self.handle)
+
+    def profile_stop(self):
+        """{kernel name: (total ms, launches)} since profile_start."""
+        out = NsKernelTimes()
+        ns_profile_stop(self.handle, out)
+        return {PROF_NAMES[i]: (out.ms[i], out.count[i]) for i in range(8)}
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ns_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
