@@ -89,9 +89,23 @@ template <int R, int DIR, typename V> struct DftSplit {
     Dft<M, DIR, V>::run(o);
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-      const int k16 = k * (16 / R);
-      const V w = mk<V>((T)cos16(k16), (T)(DIR * sin16(k16)));
-      V t = (k == 0) ? o[k] : cmul(o[k], w);
+      const int k16 = k * (16 / R);     // twiddle angle in units of 2 pi / 16
+      V t;
+      if (k16 == 0) {
+        t = o[k];
+      } else if (k16 == 4) {            // exp(DIR i pi/2) = DIR i
+        t = mul_si<DIR>(o[k]);
+      } else if (k16 == 2 || k16 == 6) {
+        // w = c (1 + DIR i) or c (-1 + DIR i), c = cos(pi/4): two products
+        const T c = (T)NSK_C2, x = o[k].x, y = o[k].y;
+        if (k16 == 2)
+          t = DIR > 0 ? mk<V>(c * (x - y), c * (x + y)) : mk<V>(c * (x + y), c * (y - x));
+        else
+          t = DIR > 0 ? mk<V>(-(c * (x + y)), c * (x - y)) : mk<V>(c * (y - x), -(c * (x + y)));
+      } else {
+        const V w = mk<V>((T)cos16(k16), (T)(DIR * sin16(k16)));
+        t = cmul(o[k], w);
+      }
       v[k] = cadd(e[k], t);
       v[k + M] = csub(e[k], t);
     }
@@ -100,16 +114,34 @@ template <int R, int DIR, typename V> struct DftSplit {
 template <int DIR, typename V> struct Dft<8, DIR, V> : DftSplit<8, DIR, V> {};
 template <int DIR, typename V> struct Dft<16, DIR, V> : DftSplit<16, DIR, V> {};
 
-// Radix plans: E values per thread, N/E threads per transform.
+// Radix plans: a transform of length N in P passes of radices R0, R1, R2
+// (R0 = E, the values each thread holds; N/E threads per transform).
+template <int N_, int E_, int P_, int R0_, int R1_, int R2_> struct PlanT {
+  static constexpr int N = N_, E = E_, P = P_, R0 = R0_, R1 = R1_, R2 = R2_;
+  static constexpr int TT = N / E;
+  static constexpr int RL = P == 1 ? R0 : (P == 2 ? R1 : R2);   // last radix
+  static_assert(R0 * R1 * R2 == N && R0 == E, "radix plan");
+};
+// Wide plans: few passes, up to 16 values per thread.
 template <int N> struct Plan;
-template <> struct Plan<8>    { static constexpr int E = 8,  P = 1, R0 = 8,  R1 = 1, R2 = 1; };
-template <> struct Plan<16>   { static constexpr int E = 16, P = 1, R0 = 16, R1 = 1, R2 = 1; };
-template <> struct Plan<32>   { static constexpr int E = 8,  P = 2, R0 = 8,  R1 = 4, R2 = 1; };
-template <> struct Plan<64>   { static constexpr int E = 8,  P = 2, R0 = 8,  R1 = 8, R2 = 1; };
-template <> struct Plan<128>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 8, R2 = 1; };
-template <> struct Plan<256>  { static constexpr int E = 16, P = 2, R0 = 16, R1 = 16, R2 = 1; };
-template <> struct Plan<512>  { static constexpr int E = 8,  P = 3, R0 = 8,  R1 = 8, R2 = 8; };
-template <> struct Plan<1024> { static constexpr int E = 16, P = 3, R0 = 16, R1 = 16, R2 = 4; };
+template <> struct Plan<8>    : PlanT<8, 8, 1, 8, 1, 1> {};
+template <> struct Plan<16>   : PlanT<16, 16, 1, 16, 1, 1> {};
+template <> struct Plan<32>   : PlanT<32, 8, 2, 8, 4, 1> {};
+template <> struct Plan<64>   : PlanT<64, 8, 2, 8, 8, 1> {};
+template <> struct Plan<128>  : PlanT<128, 16, 2, 16, 8, 1> {};
+template <> struct Plan<256>  : PlanT<256, 16, 2, 16, 16, 1> {};
+template <> struct Plan<512>  : PlanT<512, 8, 3, 8, 8, 8> {};
+template <> struct Plan<1024> : PlanT<1024, 16, 3, 16, 16, 4> {};
+// Narrow plans: at most 8 values per thread (fewer registers, one more pass).
+template <int N> struct PlanS;
+template <> struct PlanS<8>    : PlanT<8, 8, 1, 8, 1, 1> {};
+template <> struct PlanS<16>   : PlanT<16, 8, 2, 8, 2, 1> {};
+template <> struct PlanS<32>   : PlanT<32, 8, 2, 8, 4, 1> {};
+template <> struct PlanS<64>   : PlanT<64, 8, 2, 8, 8, 1> {};
+template <> struct PlanS<128>  : PlanT<128, 8, 3, 8, 8, 2> {};
+template <> struct PlanS<256>  : PlanT<256, 8, 3, 8, 8, 4> {};
+template <> struct PlanS<512>  : PlanT<512, 8, 3, 8, 8, 8> {};
+template <> struct PlanS<1024> : PlanT<1024, 16, 3, 16, 16, 4> {};
 
 // Butterflies of one pass on the thread's registers: radix R, span NS.
 template <int N, int E, int R, int NS, int DIR, typename V>
@@ -132,8 +164,14 @@ __device__ __forceinline__ void pass_compute(V (&v)[E], int t, const V* __restri
   }
 }
 
+// LDS slot of element pos: with PAD one spare slot follows every 16
+// elements, so that threads writing pos = 16 t + r (a radix-16 pass with
+// unit span) hit distinct banks.  A padded buffer holds N + N/16 values.
+template <bool PAD> __device__ __forceinline__ int lslot(int pos) { return PAD ? pos + (pos >> 4) : pos; }
+template <int N, bool PAD> struct LdsLen { static constexpr int value = PAD ? N + N / 16 : N; };
+
 // Write a pass's outputs to a transform buffer (unit element stride).
-template <int N, int E, int R, int NS, typename V>
+template <int N, int E, int R, int NS, typename V, bool PAD = false>
 __device__ __forceinline__ void pass_write(const V (&v)[E], int t, V* buf) {
   constexpr int TT = N / E;
   constexpr int S = E / R;
@@ -142,12 +180,12 @@ __device__ __forceinline__ void pass_write(const V (&v)[E], int t, V* buf) {
     const int j = t + TT * s;
     const int base = (j / NS) * NS * R + (j & (NS - 1));
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[base + r * NS] = v[s * R + r];
+    for (int r = 0; r < R; ++r) buf[lslot<PAD>(base + r * NS)] = v[s * R + r];
   }
 }
 
 // Read the inputs of a pass with radix R from a transform buffer.
-template <int N, int E, int R, typename V>
+template <int N, int E, int R, typename V, bool PAD = false>
 __device__ __forceinline__ void pass_read(V (&v)[E], int t, const V* buf) {
   constexpr int TT = N / E;
   constexpr int S = E / R;
@@ -155,77 +193,75 @@ __device__ __forceinline__ void pass_read(V (&v)[E], int t, const V* buf) {
   for (int s = 0; s < S; ++s) {
     const int j = t + TT * s;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[s * R + r] = buf[j + r * (N / R)];
+    for (int r = 0; r < R; ++r) v[s * R + r] = buf[lslot<PAD>(j + r * (N / R))];
   }
 }
 
 // Element index held in v[i] after the last pass (natural order output).
-template <int N> __device__ __forceinline__ int out_pos(int t, int i) {
-  using P = Plan<N>;
-  constexpr int RL = P::P == 1 ? P::R0 : (P::P == 2 ? P::R1 : P::R2);
-  constexpr int TT = N / P::E;
-  const int s = i / RL, r = i % RL;
-  return t + TT * s + r * (N / RL);
+template <class PL> __device__ __forceinline__ int out_pos(int t, int i) {
+  const int s = i / PL::RL, r = i % PL::RL;
+  return t + PL::TT * s + r * (PL::N / PL::RL);
 }
 // Element index expected in v[i] before the first pass (R0 == E for all plans).
-template <int N> __device__ __forceinline__ int in_pos(int t, int i) {
-  constexpr int TT = N / Plan<N>::E;
-  return t + i * TT;
+template <class PL> __device__ __forceinline__ int in_pos(int t, int i) { return t + i * PL::TT; }
+
+// Synchronisation of the threads sharing a transform buffer: the whole block,
+// or (WAVE) only the wavefront, when every transform's threads lie inside one
+// wavefront -- LDS operations of one wavefront complete in order, so a
+// wavefront-scope fence plus a scheduling barrier orders the exchange.
+template <bool WAVE> __device__ __forceinline__ void group_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
 }
 
 // Whole transform on registers: v holds the inputs at in_pos on entry and the
-// outputs at out_pos on exit.  buf is this transform's LDS scratch (N values);
-// every thread of the block must call this (it synchronises the block).
-template <int N, int DIR, typename V>
-__device__ __forceinline__ void fft_regs(V (&v)[Plan<N>::E], int t, V* buf, const V* __restrict__ tw) {
-  using P = Plan<N>;
+// outputs at out_pos on exit.  buf is this transform's LDS scratch
+// (LdsLen<N, PAD> values); every thread of the block (WAVE: of the wavefront)
+// must call this, since it synchronises them.
+template <class P, int DIR, typename V, bool PAD = false, bool WAVE = false>
+__device__ __forceinline__ void fft_regs(V (&v)[P::E], int t, V* buf, const V* __restrict__ tw) {
+  constexpr int N = P::N;
   constexpr int E = P::E;
   pass_compute<N, E, P::R0, 1, DIR>(v, t, tw);
   if constexpr (P::P >= 2) {
-    pass_write<N, E, P::R0, 1>(v, t, buf);
-    __syncthreads();
-    pass_read<N, E, P::R1>(v, t, buf);
+    pass_write<N, E, P::R0, 1, V, PAD>(v, t, buf);
+    group_sync<WAVE>();
+    pass_read<N, E, P::R1, V, PAD>(v, t, buf);
     pass_compute<N, E, P::R1, P::R0, DIR>(v, t, tw);
   }
   if constexpr (P::P >= 3) {
-    __syncthreads();
-    pass_write<N, E, P::R1, P::R0>(v, t, buf);
-    __syncthreads();
-    pass_read<N, E, P::R2>(v, t, buf);
+    group_sync<WAVE>();
+    pass_write<N, E, P::R1, P::R0, V, PAD>(v, t, buf);
+    group_sync<WAVE>();
+    pass_read<N, E, P::R2, V, PAD>(v, t, buf);
     pass_compute<N, E, P::R2, P::R0 * P::R1, DIR>(v, t, tw);
   }
 }
 
-// Transform held entirely in an LDS buffer (natural order in and out).
-// active == false threads only take part in the barriers.
-template <int N, int DIR, typename V>
-__device__ __forceinline__ void fft_lds(V* buf, int t, bool active, const V* __restrict__ tw) {
-  using P = Plan<N>;
-  constexpr int E = P::E;
-  V v[E];
-  if (active) pass_read<N, E, P::R0>(v, t, buf);
-  if (active) pass_compute<N, E, P::R0, 1, DIR>(v, t, tw);
-  __syncthreads();
-  if (active) pass_write<N, E, P::R0, 1>(v, t, buf);
-  __syncthreads();
-  if constexpr (P::P >= 2) {
-    if (active) {
-      pass_read<N, E, P::R1>(v, t, buf);
-      pass_compute<N, E, P::R1, P::R0, DIR>(v, t, tw);
-    }
-    __syncthreads();
-    if (active) pass_write<N, E, P::R1, P::R0>(v, t, buf);
-    __syncthreads();
-  }
-  if constexpr (P::P >= 3) {
-    if (active) {
-      pass_read<N, E, P::R2>(v, t, buf);
-      pass_compute<N, E, P::R2, P::R0 * P::R1, DIR>(v, t, tw);
-    }
-    __syncthreads();
-    if (active) pass_write<N, E, P::R2, P::R0 * P::R1>(v, t, buf);
-    __syncthreads();
-  }
+// Register index that holds output element (N - pos) mod N, where pos is the
+// element held in register i of thread t after fft_regs (natural order,
+// out_pos).  Thread t >= 1 finds it in thread TT - t ("partner", same
+// register map); thread 0 in itself.  Returns the register index for the
+// partner case (self == false) or the thread-0 case (self == true).
+template <class P> __device__ __forceinline__ constexpr int mirror_reg(int i, bool self) {
+  constexpr int RL = P::RL;
+  constexpr int S = P::E / RL;
+  const int s = i / RL, r = i % RL;
+  if (!self) return (S - 1 - s) * RL + (RL - 1 - r);
+  if (s >= 1) return (S - s) * RL + (RL - 1 - r);
+  return r == 0 ? 0 : RL - r;
+}
+
+// Register index i' (in in_pos order) of the element held in out_pos register i.
+template <class P> __device__ __forceinline__ constexpr int out_to_in(int i) {
+  constexpr int RL = P::RL;
+  constexpr int S = P::E / RL;
+  return (i / RL) + (i % RL) * S;
 }
 
 }  // namespace nsk

@@ -17,8 +17,12 @@
 //   P5 z-forward  n values of z -> the 2K+1 retained kz, then the projection,
 //                 the viscous term and the cast to FP64, fused
 //
-// Intermediate layouts (T complex):  A1 [m][6][z][ky'][kx],  A2 [m][6][z][y][kx],
-// A3 [m][3][z][y][kx] (reuses A1),   A4 [m][3][z][ky'][kx] (reuses A2).
+// Intermediate layouts (T complex), chosen so that every column pass tiles a
+// contiguous run of columns:
+//   A1 [m][6][ky'][z][kx]   written by P1, read by P2 (columns (z, kx))
+//   A2 [m][6][z][y][kx]     written by P2, read by P3 (rows (z, y))
+//   A3 [m][3][y][z][kx]     written by P3 (reuses A1), read by P4 (columns (z, kx))
+//   A4 [m][3][z][ky'][kx]   written by P4 (reuses A2), read by P5 (columns (ky', kx))
 #include "fft_core.hpp"
 #include "ns_internal.hpp"
 
@@ -31,9 +35,10 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int floor_pow2(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p; }
 
 // Column passes: C adjacent columns per block, N/E threads per column.
-template <int N, typename T> struct ColCfg {
+template <class PL, typename T> struct ColCfg {
   using V = cplx<T>;
-  static constexpr int E = Plan<N>::E;
+  static constexpr int N = PL::N;
+  static constexpr int E = PL::E;
   static constexpr int TT = N / E;
   static constexpr int LDS_BUDGET = 80 * 1024;
   static constexpr int C = floor_pow2(cmin(cmax(256 / TT, 16), LDS_BUDGET / ((N + 1) * (int)sizeof(V))));
@@ -41,217 +46,278 @@ template <int N, typename T> struct ColCfg {
   static constexpr int LD = N + 1;      // padded LDS stride per column
 };
 
-// Row pass: ROWS rows per block, three transforms per row.
-template <int N, typename T> struct RowCfg {
-  static constexpr int E = Plan<N>::E;
-  static constexpr int TT = N / E;
-  static constexpr int ROWS = cmin(32, cmax(2, 64 / TT));
-  static constexpr int NBUF = 3 * ROWS;
-  static constexpr int NT = NBUF * TT;
-  static constexpr int LD = N + 1;
-};
-
-__device__ __forceinline__ long long batch_index() {
-  return (long long)blockIdx.y + (long long)blockIdx.z * gridDim.y;
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8, each with its own L2).  With a grid padded to a multiple of 8 this
+// remap hands each XCD a contiguous range of logical block ids, so blocks
+// with neighbouring logical ids share an L2.
+__device__ __forceinline__ long long xcd_logical(long long b, long long nb_padded) {
+  return (b & 7) * (nb_padded >> 3) + (b >> 3);
 }
 
 // ---------------------------------------------------------------- P1
-template <int N, typename T>
-__global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_zinv(const double2* __restrict__ U,
-                                                           cplx<T>* __restrict__ A1, Geom g,
-                                                           const cplx<T>* __restrict__ tw) {
+// Logical block id = (member, column tile, field) with the field fastest: the
+// six blocks of one tile run on one XCD back to back and read u_hat once from
+// HBM, the rest from L2.
+template <class PL, typename T>
+__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_zinv(const double2* __restrict__ U,
+                                                             cplx<T>* __restrict__ A1, Geom g,
+                                                             long long nblocks,
+                                                             const cplx<T>* __restrict__ tw) {
+  constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<N, T>;
+  using CF = ColCfg<PL, T>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
-  const int lc = threadIdx.x % C, t = threadIdx.x / C;
+  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;                     // uniform per block
   const int ncol = g.Kf * g.Kx;
-  const int col = blockIdx.x * C + lc;
-  const int f = blockIdx.y, m = blockIdx.z;
+  const int ntiles = (ncol + C - 1) / C;
+  const int f = (int)(L % 6);
+  const long long q = L / 6;
+  const int tile = (int)(q % ntiles);
+  const int m = (int)(q / ntiles);
+  const int lc = threadIdx.x % C, t = threadIdx.x / C;
+  const int col = tile * C + lc;
   const bool valid = col < ncol;
-  int kx = 0, ky = 0;
+  int kx = 0, ky = 0, kyp = 0;
   if (valid) {
-    const int kyp = col / g.Kx;
+    kyp = col / g.Kx;
     kx = col - kyp * g.Kx;
     ky = kyp <= g.K ? kyp : kyp - g.Kf;
   }
   const long long cs = g.mr;
-  const double2* Um = U + (long long)m * 3 * cs + col;
+  const double2* Um = U + (long long)m * 3 * cs + (valid ? col : 0);
+  // Loads without branches (clamped addresses, zeroed by selects) so that all
+  // of a thread's loads are in flight together.
+  double2 a[E], b[E];
+  bool use[E];
+  int kzs[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = in_pos<PL>(t, i);
+    const bool ret = (e <= g.K) || (e >= N - g.K);
+    use[i] = valid && ret;
+    const int kz = e <= g.K ? e : e - N;
+    kzs[i] = kz;
+    const int kzp = ret ? (kz >= 0 ? kz : kz + g.Kf) : 0;
+    const double2* pp = Um + (long long)kzp * ncol;
+    if (f < 3) {
+      a[i] = pp[f * cs];
+    } else {
+      // omega_hat = i k x u_hat: (ky, kz, kx) pair with (u_z, u_y), (u_x, u_z), (u_y, u_x)
+      a[i] = pp[(f == 3 ? 2 : (f == 4 ? 0 : 1)) * cs];
+      b[i] = pp[(f == 3 ? 1 : (f == 4 ? 2 : 0)) * cs];
+    }
+  }
   V v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const int e = in_pos<N>(t, i);
-    const bool ret = (e <= g.K) || (e >= N - g.K);
-    const int kz = e <= g.K ? e : e - N;
-    double vx = 0.0, vy = 0.0;
-    if (valid && ret) {
-      const double2* p = Um + (long long)(kz >= 0 ? kz : kz + g.Kf) * ncol;
-      if (f < 3) {
-        const double2 a = p[f * cs];
-        vx = a.x; vy = a.y;
-      } else {
-        // omega_hat = i k x u_hat, one component per field
-        double2 a, b;
-        double ka, kb;
-        if (f == 3) { a = p[2 * cs]; ka = ky; b = p[cs]; kb = kz; }
-        else if (f == 4) { a = p[0]; ka = kz; b = p[2 * cs]; kb = kx; }
-        else { a = p[cs]; ka = kx; b = p[0]; kb = ky; }
-        const double wr = ka * a.x - kb * b.x, wi = ka * a.y - kb * b.y;
-        vx = -wi; vy = wr;
-      }
+    double vx, vy;
+    if (f < 3) {
+      vx = a[i].x; vy = a[i].y;
+    } else {
+      const double kz = kzs[i];
+      const double ka = f == 3 ? ky : (f == 4 ? kz : kx);
+      const double kb = f == 3 ? kz : (f == 4 ? kx : ky);
+      const double wr = ka * a[i].x - kb * b[i].x, wi = ka * a[i].y - kb * b[i].y;
+      vx = -wi; vy = wr;
     }
-    v[i] = mk<V>((T)vx, (T)vy);
+    v[i] = use[i] ? mk<V>((T)vx, (T)vy) : mk<V>((T)0, (T)0);
   }
-  fft_regs<N, +1>(v, t, lds + lc * CF::LD, tw);
+  fft_regs<PL, +1>(v, t, lds + lc * CF::LD, tw);
   if (valid) {
-    V* out = A1 + ((long long)(m * 6 + f) * N) * ncol + col;
+    const long long nkx = (long long)N * g.Kx;
+    V* out = A1 + ((long long)(m * 6 + f) * g.Kf + kyp) * nkx + kx;
 #pragma unroll
-    for (int i = 0; i < E; ++i) out[(long long)out_pos<N>(t, i) * ncol] = v[i];
+    for (int i = 0; i < E; ++i) out[(long long)out_pos<PL>(t, i) * g.Kx] = v[i];
   }
 }
 
 // ---------------------------------------------------------------- P2
-template <int N, typename T>
-__global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
-                                                           cplx<T>* __restrict__ A2, Geom g,
-                                                           long long nbatch,
-                                                           const cplx<T>* __restrict__ tw) {
+// Columns (z, kx) of one (member, field): 2K+1 non-zero ky' -> N values of y.
+template <class PL, typename T>
+__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
+                                                             cplx<T>* __restrict__ A2, Geom g,
+                                                             const cplx<T>* __restrict__ tw) {
+  constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<N, T>;
+  using CF = ColCfg<PL, T>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
-  const long long b = batch_index();
-  if (b >= nbatch) return;                      // uniform per block
+  const long long bf = blockIdx.y;                // member * 6 + field
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int col = blockIdx.x * C + lc;
-  const bool valid = col < g.Kx;
-  const V* in = A1 + b * g.Kf * g.Kx + col;
+  const int nkx = N * g.Kx;
+  const int cz = blockIdx.x * C + lc;
+  const bool valid = cz < nkx;
+  const V* in = A1 + bf * g.Kf * nkx + (valid ? cz : 0);
   V v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const int e = in_pos<N>(t, i);
+    const int e = in_pos<PL>(t, i);
     const bool ret = (e <= g.K) || (e >= N - g.K);
-    const int kyp = e <= g.K ? e : e - N + g.Kf;
-    v[i] = (valid && ret) ? in[(long long)kyp * g.Kx] : mk<V>((T)0, (T)0);
+    const int kyp = e <= g.K ? e : (ret ? e - N + g.Kf : 0);
+    const V x = in[(long long)kyp * nkx];
+    v[i] = (valid && ret) ? x : mk<V>((T)0, (T)0);
   }
-  fft_regs<N, +1>(v, t, lds + lc * CF::LD, tw);
+  fft_regs<PL, +1>(v, t, lds + lc * CF::LD, tw);
   if (valid) {
-    V* out = A2 + b * N * g.Kx + col;
+    const int z = cz / g.Kx, kx = cz - z * g.Kx;
+    V* out = A2 + (bf * N + z) * (long long)nkx + kx;
 #pragma unroll
-    for (int i = 0; i < E; ++i) out[(long long)out_pos<N>(t, i) * g.Kx] = v[i];
+    for (int i = 0; i < E; ++i) out[(long long)out_pos<PL>(t, i) * g.Kx] = v[i];
   }
 }
 
 // ---------------------------------------------------------------- P3
-template <int N, typename T>
-__global__ __launch_bounds__((RowCfg<N, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2,
-                                                            cplx<T>* __restrict__ A3, Geom g,
-                                                            const cplx<T>* __restrict__ tw) {
+// One group of N/E threads per (member, z, y) row, everything in registers:
+//  1. the three paired half spectra (u_x + i u_y), (u_z + i w_x), (w_y + i w_z)
+//     are loaded straight into the first pass's registers, completing each
+//     Hermitian half to the full spectrum Z = A + iB on the fly;
+//  2. three inverse transforms; their outputs sit at the same positions in
+//     every thread, so u x omega is formed in registers;
+//  3. forward transforms of (n_x + i n_y) and of (n_z + 0i) start from those
+//     registers (the last inverse pass's output positions are the first
+//     forward pass's input positions);
+//  4. n_x, n_y are split from Z(k) and conj(Z(N-k)), the mirror value coming
+//     from the partner thread through a cross-lane shuffle; keep kx <= K.
+template <class PL, typename T> struct RowCfg {
+  static constexpr int N = PL::N;
+  static constexpr int E = PL::E;
+  static constexpr int TT = N / E;
+  static constexpr int RPB = 256 / TT;              // rows per block
+  static constexpr int LD = LdsLen<N, true>::value;
+  static constexpr int NT = RPB * TT;
+};
+
+template <typename V> __device__ __forceinline__ V shfl_c(V v, int src, int width) {
+  return mk<V>(__shfl(v.x, src, width), __shfl(v.y, src, width));
+}
+
+template <class PL, typename T>
+__global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2,
+                                                              cplx<T>* __restrict__ A3, Geom g,
+                                                              long long nrows,
+                                                              const cplx<T>* __restrict__ tw) {
+  constexpr int N = PL::N;
   using V = cplx<T>;
-  using RC = RowCfg<N, T>;
-  constexpr int ROWS = RC::ROWS, NBUF = RC::NBUF, NT = RC::NT, LD = RC::LD, TT = RC::TT;
-  __shared__ V lds[NBUF * LD];
-  const long long rpm = (long long)N * N;             // rows per member
-  const long long row0 = (long long)blockIdx.x * ROWS;
+  using RC = RowCfg<PL, T>;
+  constexpr int E = RC::E, TT = RC::TT;
+  __shared__ V lds[RC::RPB * RC::LD];
+  const int grp = threadIdx.x / TT, t = threadIdx.x - grp * TT;
+  const long long row = (long long)blockIdx.x * RC::RPB + grp;
+  const bool valid = row < nrows;
+  const long long rpm = (long long)N * N;
+  const long long m = valid ? row / rpm : 0, rr = valid ? row - m * rpm : 0;
   const int K = g.K, Kx = g.Kx;
   const T zero = (T)0;
+  V* buf = lds + grp * RC::LD;
 
-  // 1. paired half spectra -> full spectra Z = A + iB (A, B Hermitian)
-  for (int idx = threadIdx.x; idx < NBUF * Kx; idx += NT) {
-    const int buf = idx / Kx, kk = idx - buf * Kx;
-    const int r = buf / 3, p = buf - 3 * r;
-    const long long grow = row0 + r;
-    const long long m = grow / rpm, rr = grow - m * rpm;
-    V A = A2[((m * 6 + 2 * p) * rpm + rr) * Kx + kk];
-    V B = A2[((m * 6 + 2 * p + 1) * rpm + rr) * Kx + kk];
-    if (kk == 0) { A.y = zero; B.y = zero; }
-    V* L = lds + buf * LD;
-    L[kk] = mk<V>(A.x - B.y, A.y + B.x);
-    if (kk > 0) L[N - kk] = mk<V>(A.x + B.y, B.x - A.y);
-  }
-  const int nmid = N - 2 * K - 1;
-  for (int idx = threadIdx.x; idx < NBUF * nmid; idx += NT) {
-    const int buf = idx / nmid, q = idx - buf * nmid;
-    lds[buf * LD + K + 1 + q] = mk<V>(zero, zero);
-  }
-  __syncthreads();
-
-  // 2. inverse transforms: (u_x + i u_y), (u_z + i w_x), (w_y + i w_z)
-  const int grp = threadIdx.x / TT, tt = threadIdx.x - grp * TT;
-  fft_lds<N, +1>(lds + grp * LD, tt, true, tw);
-
-  // 3. n = u x omega at every point; n_z of the two rows of a pair shares one buffer
-  for (int idx = threadIdx.x; idx < (ROWS / 2) * N; idx += NT) {
-    const int pr = idx / N, x = idx - pr * N;
-    T nz[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int r = 2 * pr + h;
-      V* L0 = lds + (3 * r) * LD;
-      const V a = L0[x], b = L0[LD + x], c = L0[2 * LD + x];
-      const T ux = a.x, uy = a.y, uz = b.x, wx = b.y, wy = c.x, wz = c.y;
-      L0[x] = mk<V>(uy * wz - uz * wy, uz * wx - ux * wz);
-      nz[h] = ux * wy - uy * wx;
-    }
-    lds[(3 * (2 * pr) + 1) * LD + x] = mk<V>(nz[0], nz[1]);
-  }
-  __syncthreads();
-
-  // 4. forward transforms of (n_x + i n_y) per row and (n_z(r0) + i n_z(r1)) per pair
+  V z0[E], z1[E], z2[E];
   {
-    const int r = grp / 3, p = grp - 3 * r;
-    const bool active = (p == 0) || (p == 1 && (r & 1) == 0);
-    fft_lds<N, -1>(lds + grp * LD, tt, active, tw);
+    // Loads without branches: every lane reads a clamped in-row address and
+    // zeroes what lies outside the retained band with selects, so a whole
+    // pair's loads are in flight together.  Z = A + iB at k <= K and
+    // conj(A) + i conj(B) at N - k (s = +1 / -1 below).
+    const V* base = A2 + (m * 6 * rpm + rr) * Kx;
+    int kk[E];
+    T sg[E];
+    bool use[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int pos = in_pos<PL>(t, i);
+      const bool lo = pos <= K, hi = pos >= N - K;
+      use[i] = valid && (lo || hi);
+      const int k0 = lo ? pos : N - pos;
+      kk[i] = k0 <= K ? k0 : K;
+      sg[i] = lo ? (T)1 : (T)-1;
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      V a[E], b[E];
+      const V* pa = base + (long long)(2 * p) * rpm * Kx;
+      const V* pb = pa + rpm * Kx;
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        a[i] = pa[kk[i]];
+        b[i] = pb[kk[i]];
+      }
+      V* z = p == 0 ? z0 : (p == 1 ? z1 : z2);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const T ay = kk[i] == 0 ? zero : a[i].y, by = kk[i] == 0 ? zero : b[i].y;
+        const V r = mk<V>(a[i].x - sg[i] * by, sg[i] * ay + b[i].x);
+        z[i] = use[i] ? r : mk<V>(zero, zero);
+      }
+    }
   }
+  static_assert(64 % TT == 0, "a row's threads must lie in one wavefront");
+  fft_regs<PL, +1, V, true, true>(z0, t, buf, tw);
+  group_sync<true>();
+  fft_regs<PL, +1, V, true, true>(z1, t, buf, tw);
+  group_sync<true>();
+  fft_regs<PL, +1, V, true, true>(z2, t, buf, tw);
 
-  // 5. split the paired spectra, keep kx <= K
-  for (int idx = threadIdx.x; idx < ROWS * Kx; idx += NT) {
-    const int r = idx / Kx, kk = idx - r * Kx;
-    const long long grow = row0 + r;
-    const long long m = grow / rpm, rr = grow - m * rpm;
-    const V* Z = lds + (3 * r) * LD;
-    const V zk = Z[kk], zm = Z[(N - kk) & (N - 1)];
-    const V* P = lds + (3 * (r & ~1) + 1) * LD;
-    const V pk = P[kk], pm = P[(N - kk) & (N - 1)];
-    const T half = (T)0.5;
-    // (X + conj(Y))/2 and (X - conj(Y))/(2i)
-    const V nx = mk<V>(half * (zk.x + zm.x), half * (zk.y - zm.y));
-    const V ny = mk<V>(half * (zk.y + zm.y), half * (zm.x - zk.x));
-    const V nzv = (r & 1) == 0 ? mk<V>(half * (pk.x + pm.x), half * (pk.y - pm.y))
-                               : mk<V>(half * (pk.y + pm.y), half * (pm.x - pk.x));
-    V* out = A3 + ((m * 3) * rpm + rr) * Kx + kk;
-    out[0] = nx;
-    out[rpm * Kx] = ny;
-    out[2 * rpm * Kx] = nzv;
+  V nxy[E], nz[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const T ux = z0[i].x, uy = z0[i].y, uz = z1[i].x, wx = z1[i].y, wy = z2[i].x, wz = z2[i].y;
+    nxy[out_to_in<PL>(i)] = mk<V>(uy * wz - uz * wy, uz * wx - ux * wz);
+    nz[out_to_in<PL>(i)] = mk<V>(ux * wy - uy * wx, zero);
+  }
+  group_sync<true>();
+  fft_regs<PL, -1, V, true, true>(nxy, t, buf, tw);
+  group_sync<true>();
+  fft_regs<PL, -1, V, true, true>(nz, t, buf, tw);
+
+  const int partner = (TT - t) & (TT - 1);
+  V* out = A3 + ((m * 3) * N + (rr % N)) * (long long)N * Kx + (rr / N) * (long long)Kx;
+  const long long cstride = rpm * Kx;
+  const T half = (T)0.5;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const V own = nxy[mirror_reg<PL>(i, true)];
+    V pv = own;
+    if constexpr (TT > 1) {
+      const V sh = shfl_c(nxy[mirror_reg<PL>(i, false)], partner, TT);
+      if (t != 0) pv = sh;
+    }
+    const int pos = out_pos<PL>(t, i);
+    if (valid && pos <= K) {
+      const V zk = nxy[i];
+      out[pos] = mk<V>(half * (zk.x + pv.x), half * (zk.y - pv.y));
+      out[cstride + pos] = mk<V>(half * (zk.y + pv.y), half * (pv.x - zk.x));
+      out[2 * cstride + pos] = nz[i];
+    }
   }
 }
 
 // ---------------------------------------------------------------- P4
-template <int N, typename T>
-__global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3,
-                                                           cplx<T>* __restrict__ A4, Geom g,
-                                                           long long nbatch,
-                                                           const cplx<T>* __restrict__ tw) {
+// Columns (z, kx) of one (member, component): N values of y -> 2K+1 retained ky.
+template <class PL, typename T>
+__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3,
+                                                             cplx<T>* __restrict__ A4, Geom g,
+                                                             const cplx<T>* __restrict__ tw) {
+  constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<N, T>;
+  using CF = ColCfg<PL, T>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
-  const long long b = batch_index();
-  if (b >= nbatch) return;
+  const long long bc = blockIdx.y;                // member * 3 + component
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int col = blockIdx.x * C + lc;
-  const bool valid = col < g.Kx;
-  const V* in = A3 + b * N * g.Kx + col;
+  const int nkx = N * g.Kx;
+  const int cz = blockIdx.x * C + lc;
+  const bool valid = cz < nkx;
+  const V* in = A3 + bc * N * (long long)nkx + (valid ? cz : 0);
   V v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i)
-    v[i] = valid ? in[(long long)in_pos<N>(t, i) * g.Kx] : mk<V>((T)0, (T)0);
-  fft_regs<N, -1>(v, t, lds + lc * CF::LD, tw);
+  for (int i = 0; i < E; ++i) v[i] = in[(long long)in_pos<PL>(t, i) * nkx];
+  fft_regs<PL, -1>(v, t, lds + lc * CF::LD, tw);
   if (valid) {
-    V* out = A4 + b * g.Kf * g.Kx + col;
+    const int z = cz / g.Kx, kx = cz - z * g.Kx;
+    V* out = A4 + (bc * N + z) * (long long)g.Kf * g.Kx + kx;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const int e = out_pos<N>(t, i);
+      const int e = out_pos<PL>(t, i);
       if (e <= g.K) out[(long long)e * g.Kx] = v[i];
       else if (e >= N - g.K) out[(long long)(e - N + g.Kf) * g.Kx] = v[i];
     }
@@ -259,14 +325,15 @@ __global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_yfwd(const cplx<T>* __re
 }
 
 // ---------------------------------------------------------------- P5
-template <int N, typename T>
-__global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_zfwd(const cplx<T>* __restrict__ A4,
+template <class PL, typename T>
+__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_zfwd(const cplx<T>* __restrict__ A4,
                                                            const double2* __restrict__ U,
                                                            double2* __restrict__ Kout, Geom g,
                                                            const double* __restrict__ nu,
                                                            const cplx<T>* __restrict__ tw) {
+  constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<N, T>;
+  using CF = ColCfg<PL, T>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
@@ -278,11 +345,10 @@ __global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_zfwd(const cplx<T>* __re
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();                // LDS reuse across fields
-    const V* in = A4 + ((long long)(m * 3 + c) * N) * ncol + col;
+    const V* in = A4 + ((long long)(m * 3 + c) * N) * ncol + (valid ? col : 0);
 #pragma unroll
-    for (int i = 0; i < E; ++i)
-      o[c][i] = valid ? in[(long long)in_pos<N>(t, i) * ncol] : mk<V>((T)0, (T)0);
-    fft_regs<N, -1>(o[c], t, lds + lc * CF::LD, tw);
+    for (int i = 0; i < E; ++i) o[c][i] = in[(long long)in_pos<PL>(t, i) * ncol];
+    fft_regs<PL, -1>(o[c], t, lds + lc * CF::LD, tw);
   }
   if (!valid) return;
   const int kyp = col / g.Kx;
@@ -293,7 +359,7 @@ __global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_zfwd(const cplx<T>* __re
   const long long cs = g.mr;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const int e = out_pos<N>(t, i);
+    const int e = out_pos<PL>(t, i);
     if (!((e <= g.K) || (e >= N - g.K))) continue;
     const int kz = e <= g.K ? e : e - N;
     const long long idx = (long long)m * 3 * cs + (long long)(kz >= 0 ? kz : kz + g.Kf) * ncol + col;
@@ -320,48 +386,54 @@ __global__ __launch_bounds__((ColCfg<N, T>::NT)) void k_zfwd(const cplx<T>* __re
 }
 
 // ---------------------------------------------------------------- host side
-static void batch_grid(long long nb, unsigned& y, unsigned& z) {
-  y = (unsigned)(nb < 32768 ? nb : 32768);
-  z = (unsigned)((nb + y - 1) / y);
-}
+// Radix plan of each pass (registers vs. passes, tuned per pass).
+template <int N> struct Plans3 {
+  using zinv = Plan<N>;
+  using yinv = Plan<N>;
+  using xpass = Plan<N>;
+  using yfwd = Plan<N>;
+  using zfwd = Plan<N>;
+};
 
 template <int N, typename T>
 static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
                         const RhsBufs& bufs, const void* twv, hipStream_t st) {
   using V = cplx<T>;
-  using CF = ColCfg<N, T>;
-  using RC = RowCfg<N, T>;
+  using PS = Plans3<N>;
+  using C1 = ColCfg<typename PS::zinv, T>;
+  using C2 = ColCfg<typename PS::yinv, T>;
+  using RC = RowCfg<typename PS::xpass, T>;
+  using C4 = ColCfg<typename PS::yfwd, T>;
+  using C5 = ColCfg<typename PS::zfwd, T>;
   const V* tw = (const V*)twv;
   V* A1 = (V*)bufs.a1;
   V* A2 = (V*)bufs.a2;
   const int ncol = g.Kf * g.Kx;
-  unsigned y, z;
+  const int nkx = N * g.Kx;
 #define NSK_MARK(id, ph) \
   if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph)
+  const long long nb1 = (long long)g.batch * 6 * ((ncol + C1::C - 1) / C1::C);
+  const long long nb1p = (nb1 + 7) / 8 * 8;
   NSK_MARK(PROF_P1, 0);
-  hipLaunchKernelGGL((k_zinv<N, T>), dim3((ncol + CF::C - 1) / CF::C, 6, g.batch), dim3(CF::NT), 0, st,
-                     U, A1, g, tw);
+  hipLaunchKernelGGL((k_zinv<typename PS::zinv, T>), dim3((unsigned)nb1p), dim3(C1::NT), 0, st, U, A1, g,
+                     nb1, tw);
   NSK_MARK(PROF_P1, 1);
-  const long long nb2 = (long long)g.batch * 6 * N;
-  batch_grid(nb2, y, z);
   NSK_MARK(PROF_P2, 0);
-  hipLaunchKernelGGL((k_yinv<N, T>), dim3((g.Kx + CF::C - 1) / CF::C, y, z), dim3(CF::NT), 0, st,
-                     A1, A2, g, nb2, tw);
+  hipLaunchKernelGGL((k_yinv<typename PS::yinv, T>), dim3((nkx + C2::C - 1) / C2::C, g.batch * 6),
+                     dim3(C2::NT), 0, st, A1, A2, g, tw);
   NSK_MARK(PROF_P2, 1);
   const long long rows = (long long)g.batch * N * N;
   NSK_MARK(PROF_P3, 0);
-  hipLaunchKernelGGL((k_xpass<N, T>), dim3((unsigned)(rows / RC::ROWS)), dim3(RC::NT), 0, st,
-                     A2, A1, g, tw);
+  hipLaunchKernelGGL((k_xpass<typename PS::xpass, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
+                     dim3(RC::NT), 0, st, A2, A1, g, rows, tw);
   NSK_MARK(PROF_P3, 1);
-  const long long nb4 = (long long)g.batch * 3 * N;
-  batch_grid(nb4, y, z);
   NSK_MARK(PROF_P4, 0);
-  hipLaunchKernelGGL((k_yfwd<N, T>), dim3((g.Kx + CF::C - 1) / CF::C, y, z), dim3(CF::NT), 0, st,
-                     A1, A2, g, nb4, tw);
+  hipLaunchKernelGGL((k_yfwd<typename PS::yfwd, T>), dim3((nkx + C4::C - 1) / C4::C, g.batch * 3),
+                     dim3(C4::NT), 0, st, A1, A2, g, tw);
   NSK_MARK(PROF_P4, 1);
   NSK_MARK(PROF_P5, 0);
-  hipLaunchKernelGGL((k_zfwd<N, T>), dim3((ncol + CF::C - 1) / CF::C, g.batch), dim3(CF::NT), 0, st,
-                     A2, U, K, g, p.nu, tw);
+  hipLaunchKernelGGL((k_zfwd<typename PS::zfwd, T>), dim3((ncol + C5::C - 1) / C5::C, g.batch),
+                     dim3(C5::NT), 0, st, A2, U, K, g, p.nu, tw);
   NSK_MARK(PROF_P5, 1);
 #undef NSK_MARK
   return hipGetLastError();

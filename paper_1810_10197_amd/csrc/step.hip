@@ -202,13 +202,26 @@ __global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, Geom g, double* __
   }
 }
 
-__global__ void k_reduce_final(const double* __restrict__ partials, int nblk, double* __restrict__ out) {
+// One block per member: thread i sums partial blocks i, i + RBS, ... in order,
+// then a fixed shuffle tree and a fixed-order sum over the waves.
+__global__ __launch_bounds__(RBS) void k_reduce_final(const double* __restrict__ partials, int nblk,
+                                                      double* __restrict__ out) {
   const int m = blockIdx.x;
-  const int q = threadIdx.x;
-  if (q >= NRED) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partials[((long long)m * nblk + b) * NRED + q];
-  out[(long long)m * NRED + q] = s;
+  __shared__ double red[RBS / 64][NRED];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double* p = partials + (long long)m * nblk * NRED;
+  for (int q = 0; q < NRED; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RBS) s += p[(long long)b * NRED + q];
+    s = wave_sum(s);
+    if (lane == 0) red[wv][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NRED) {
+    double s = 0.0;
+    for (int w = 0; w < RBS / 64; ++w) s += red[w][threadIdx.x];
+    out[(long long)m * NRED + threadIdx.x] = s;
+  }
 }
 
 hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, double* out,
@@ -216,7 +229,7 @@ hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, do
   const int nblk = reduce_blocks(g);
   const int nvel = g.dim == 3 ? 3 : 2;
   hipLaunchKernelGGL(k_reduce, dim3(nblk, g.batch), dim3(RBS), 0, st, a, g, partials, nblk, nvel);
-  hipLaunchKernelGGL(k_reduce_final, dim3(g.batch), dim3(64), 0, st, partials, nblk, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(g.batch), dim3(RBS), 0, st, partials, nblk, out);
   return hipGetLastError();
 }
 
