@@ -50,7 +50,6 @@ bool valid_config(const ns_config* c) {
   if (c->batch < 1 || c->batch > 65535) return false;
   if (c->rhs_precision != NS_FP32 && c->rhs_precision != NS_FP64) return false;
   if (c->scalar != 0 && !(c->dim == 2 && c->scalar == 1)) return false;
-  if (c->dim == 2) return false;        // 2D path not built yet
   return true;
 }
 

@@ -23,36 +23,11 @@
 //   A2 [m][6][z][y][kx]     written by P2, read by P3 (rows (z, y))
 //   A3 [m][3][y][z][kx]     written by P3 (reuses A1), read by P4 (columns (z, kx))
 //   A4 [m][3][z][ky'][kx]   written by P4 (reuses A2), read by P5 (columns (ky', kx))
-#include "fft_core.hpp"
-#include "ns_internal.hpp"
+#include "pass_common.hpp"
 
 namespace nsk {
 
 static_assert(TWN == TWN_TABLE, "twiddle table length");
-
-constexpr int cmin(int a, int b) { return a < b ? a : b; }
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int floor_pow2(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p; }
-
-// Column passes: C adjacent columns per block, N/E threads per column.
-template <class PL, typename T> struct ColCfg {
-  using V = cplx<T>;
-  static constexpr int N = PL::N;
-  static constexpr int E = PL::E;
-  static constexpr int TT = N / E;
-  static constexpr int LDS_BUDGET = 80 * 1024;
-  static constexpr int C = floor_pow2(cmin(cmax(256 / TT, 16), LDS_BUDGET / ((N + 1) * (int)sizeof(V))));
-  static constexpr int NT = C * TT;
-  static constexpr int LD = N + 1;      // padded LDS stride per column
-};
-
-// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
-// b % 8, each with its own L2).  With a grid padded to a multiple of 8 this
-// remap hands each XCD a contiguous range of logical block ids, so blocks
-// with neighbouring logical ids share an L2.
-__device__ __forceinline__ long long xcd_logical(long long b, long long nb_padded) {
-  return (b & 7) * (nb_padded >> 3) + (b >> 3);
-}
 
 // ---------------------------------------------------------------- P1
 // Logical block id = (member, column tile, field) with the field fastest: the
@@ -180,19 +155,6 @@ __global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_yinv(const cplx<T>* __r
 //     forward pass's input positions);
 //  4. n_x, n_y are split from Z(k) and conj(Z(N-k)), the mirror value coming
 //     from the partner thread through a cross-lane shuffle; keep kx <= K.
-template <class PL, typename T> struct RowCfg {
-  static constexpr int N = PL::N;
-  static constexpr int E = PL::E;
-  static constexpr int TT = N / E;
-  static constexpr int RPB = 256 / TT;              // rows per block
-  static constexpr int LD = LdsLen<N, true>::value;
-  static constexpr int NT = RPB * TT;
-};
-
-template <typename V> __device__ __forceinline__ V shfl_c(V v, int src, int width) {
-  return mk<V>(__shfl(v.x, src, width), __shfl(v.y, src, width));
-}
-
 template <class PL, typename T>
 __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2,
                                                               cplx<T>* __restrict__ A3, Geom g,

@@ -1,0 +1,109 @@
+"""GPU parity of the 2D right-hand sides (plain 2D Navier--Stokes and the
+Boussinesq system of Sec. 3.2, Eqs. (4a-b)) against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, per_field_rel_l2
+from oracle import control, diagnostics, spectral, stepping
+from paper_1810_10197_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ns():
+    from paper_1810_10197_amd import ns as mod
+    return mod
+
+
+def random2d(n, seed, ncomp):
+    """Random real, masked 2D state; the velocity made solenoidal through a
+    stream function (test input)."""
+    rng = np.random.default_rng(seed)
+    m = spectral.mask(n, 2)
+    kx, ky = spectral.wavenumbers(n, 2)
+    k2 = kx * kx + ky * ky
+    psi = spectral.forward(rng.standard_normal((n, n)), 2) * m * np.exp(-k2 / (n / 4) ** 2)
+    st = np.zeros((ncomp, n, n // 2 + 1), dtype=complex)
+    st[0] = 1j * ky * psi
+    st[1] = -1j * kx * psi
+    if ncomp == 3:
+        st[2] = spectral.forward(rng.standard_normal((n, n)), 2) * m * np.exp(-k2 / (n / 4) ** 2)
+    return spectral.forward(spectral.inverse(st, n, 2), 2) * m
+
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rhs2d_ns(ns, n, prec):
+    announce("rhs2d ns n=%d %s" % (n, prec))
+    nu = 0.01
+    u = random2d(n, n, 2)
+    s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision=prec)
+    got = s.rhs(u[None]).cpu().numpy()[0]
+    s.close()
+    ref = spectral.rhs_ns2d(u, nu)
+    err = max(per_field_rel_l2(got, ref))
+    assert err <= (1e-12 if prec == "fp64" else 2e-6), err
+
+
+@pytest.mark.parametrize("n", [32, 128, 1024])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rhs2d_boussinesq(ns, n, prec):
+    announce("rhs2d boussinesq n=%d %s" % (n, prec))
+    nu, kappa, ri = 1e-3, 2e-3, 0.5
+    u = random2d(n, 3 * n, 3)
+    s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision=prec, scalar=1, ri=ri, kappa=kappa)
+    got = s.rhs(u[None]).cpu().numpy()[0]
+    s.close()
+    ref = spectral.rhs_ns2d(u, nu, kappa, ri)
+    err = max(per_field_rel_l2(got, ref))
+    assert err <= (1e-12 if prec == "fp64" else 3e-6), err
+
+
+def test_rayleigh_taylor_1024(ns):
+    """The Rayleigh--Taylor workload's initial state at 1024^2, FP32 RHS."""
+    n, nu, kappa, ri = 1024, 1e-4, 1e-4, 0.5
+    announce("rt 1024 fp32")
+    st = inputs.rayleigh_taylor2d(n)
+    s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision="fp32", scalar=1, ri=ri, kappa=kappa)
+    got = s.rhs(st[None]).cpu().numpy()[0]
+    s.close()
+    ref = spectral.rhs_ns2d(st, nu, kappa, ri)
+    # u = 0 initially: f_u is the projected buoyancy (no FFT involved), f_rho
+    # pure diffusion; both agree to rounding
+    err = per_field_rel_l2(got, ref)
+    assert max(err) <= 1e-6, err
+
+
+def test_tgv2d_exact_decay_1024(ns):
+    n, nu = 1024, 1e-4
+    announce("tgv2d exact n=1024")
+    u = inputs.tgv2d(n)
+    s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision="fp32")
+    got = s.rhs(u[None]).cpu().numpy()[0]
+    s.close()
+    err = np.abs(got + 2 * nu * u).max() / (2 * nu * np.abs(u).max())
+    assert err <= 1e-3, err
+
+
+def test_boussinesq_bs5_steps_and_diagnostics(ns):
+    n, nu, kappa, ri = 64, 1e-3, 1e-3, 0.5
+    announce("boussinesq bs5 n=%d" % n)
+    u0 = random2d(n, 7, 3)
+    rhs = lambda u: spectral.rhs_ns2d(u, nu, kappa, ri)
+    s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision="fp64", scalar=1, ri=ri, kappa=kappa)
+    s.set_state(u0[None])
+    ref = u0
+    for _ in range(3):
+        st, errs = s.step_bs5(0.05, 1e-8, 1e-8, force=True)
+        r = stepping.bs5_attempt(rhs, ref, 0.05, 1e-8, 1e-8)
+        ref = r["u_new"]
+        assert errs[0] == pytest.approx(r["err"], rel=1e-8)
+    got = s.get_state().cpu().numpy()[0]
+    assert max(per_field_rel_l2(got, ref)) <= 1e-12
+    e, eps, sh = s.diagnostics()
+    f = rhs(ref)
+    assert e[0] == pytest.approx(diagnostics.energy(ref, 2), rel=1e-12)
+    assert eps[0] == pytest.approx(diagnostics.dissipation(ref, f, 2), rel=1e-9)
+    assert sh[0] == pytest.approx(diagnostics.shells(ref, 2), rel=1e-12, abs=1e-300)
+    s.close()
