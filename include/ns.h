@@ -66,6 +66,11 @@ extern "C" {
 #define NS_CTRL_MLP 1           /* learned proposer with the PI fallback */
 
 #define NS_FORCE_COMMIT 1       /* ns_step_bs5: commit whatever err is */
+#define NS_INTEGRATE_HOST 0x100 /* ns_integrate: launch each attempt's kernels
+                                   individually instead of replaying a graph */
+
+#define NS_MLP_NPARAM 5569      /* W1 64x20, b1 64, W2 64x64, b2 64, W3 1x64, b3 1 */
+#define NS_MLP_NWEIGHTS 5609    /* parameters + feature mean [20] + feature scale [20] */
 
 typedef struct ns_config {
   int dim;              /* 3, or 2 */
@@ -130,10 +135,16 @@ int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags,
  * (Sec. 2.2.1): h0 is the first trial step, the factor
  * 0.8 err^(-1/5) clamped to [0.01, 2] (1 right after a rejection) sets the
  * next step, a step is accepted iff err <= 1, the last step is clipped to land
- * on t_end.  controller: NS_CTRL_PI or NS_CTRL_MLP (needs weights, see
- * ns_mlp_set_weights).  stats_host[batch] (host, may be NULL) receives the
- * counters.  Returns NS_ERR_STEPFAIL after 50 consecutive rejections of a
- * member (that member's state is its last accepted one). */
+ * on t_end.  Each member is controlled on the device (own step, time and
+ * counters); one attempt -- stages, error norm, decision, commit, forcing --
+ * is captured once as a HIP graph and replayed until every member is done.
+ * controller: NS_CTRL_PI or NS_CTRL_MLP (needs weights, see
+ * ns_mlp_set_weights: after an accepted step the network's proposal replaces
+ * the factor, clamped to [0.01, 2] (1 after a rejection); after a rejection,
+ * or if the proposal is not finite, the Sec. 2.2.1 factor is used), optionally
+ * or-ed with NS_INTEGRATE_HOST.  stats_host[batch] (host, may be NULL)
+ * receives the counters.  Returns NS_ERR_STEPFAIL after 50 consecutive
+ * rejections of a member (that member keeps its last accepted state). */
 int ns_integrate(ns_solver* s, double t_end, double h0, double atol,
                  double rtol, int controller, ns_stats* stats_host);
 
@@ -152,6 +163,39 @@ int ns_diagnostics(ns_solver* s, double* energy_host, double* dissipation_host,
 /* Evaluate f(u_n) into the solver's cached first stage (used by the next BS5
  * attempt and by ns_diagnostics).  Asynchronous. */
 int ns_refresh_rhs(ns_solver* s);
+
+/* ---- learned step-size proposer (20-64-64-1 tanh network, FP32) ----
+ * Features of an accepted state: log10(E_b / E + 1e-30) of the 16 shell
+ * energies, then log10 of the last four accepted error estimates (oldest
+ * first, padded with 1.0); normalised by the stored mean and scale.  Output:
+ * y = log(h_next / h).  Weights live in the solver's workspace. */
+int ns_mlp_set_weights(ns_solver* s, const float* w_host);   /* NS_MLP_NWEIGHTS */
+int ns_mlp_get_weights(ns_solver* s, float* w_host);
+/* y_dev[n] = network(x_dev[n][20]) for raw (unnormalised) feature rows. */
+int ns_mlp_forward(ns_solver* s, const float* x_dev, int n, float* y_dev);
+/* Mean-squared-error loss over (x_dev[n][20], t_dev[n]) and its gradient
+ * w.r.t. the NS_MLP_NPARAM parameters (host array), 1 <= n <= 1024. */
+int ns_mlp_grad(ns_solver* s, const float* x_dev, const float* t_dev, int n,
+                float* grad_host, float* loss_host);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that batch. */
+int ns_mlp_train_batch(ns_solver* s, const float* x_dev, const float* t_dev, int n,
+                       float lr, float* loss_host);
+/* Zero Adam's moments and step count. */
+int ns_mlp_reset_optimizer(ns_solver* s);
+/* While enabled, ns_integrate records a training row (features after an
+ * accepted step, label log(h_next_accepted / h)) for every accepted step that
+ * follows an accepted step, into a ring of 65536 rows. */
+int ns_mlp_collect(ns_solver* s, int enable);
+/* Number of rows recorded (host); copies min(count, capacity, max_rows) rows
+ * to x_host[.][20] / y_host[.] when they are not NULL. */
+int ns_mlp_rows(ns_solver* s, float* x_host, float* y_host, int max_rows, long long* count_host);
+/* Set the feature mean and scale from the recorded rows. */
+int ns_mlp_fit_stats(ns_solver* s);
+/* iters Adam steps on minibatches of `batch` recorded rows drawn with
+ * splitmix64(seed + iteration * batch + sample); loss_host (may be NULL)
+ * receives the last minibatch loss. */
+int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long long seed,
+                 float* loss_host);
 
 /* Kernel timing with HIP events recorded on the solver's stream around every
  * kernel launch while profiling is on (a tracing aid; the events add a few

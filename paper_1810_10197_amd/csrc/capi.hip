@@ -1,6 +1,7 @@
 // C ABI of the solver (declared in include/ns.h): argument checking,
-// workspace carving, the Runge--Kutta drivers of Sec. 2.2 and the host-side
-// step-size controller of Sec. 2.2.1.
+// workspace carving, the Runge--Kutta drivers of Sec. 2.2, the step-size
+// control of Sec. 2.2.1 (host-side for single attempts, device-side and
+// graph-replayed for ns_integrate), HIT forcing and the proposer network.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -38,7 +39,8 @@ const Q BS5_B[8] = {{587, 8064}, {0, 1}, {4440339, 15491840}, {24353, 124800},
 const Q BS5_BH[8] = {{2479, 34992}, {0, 1}, {123, 416}, {612941, 3411720},
                      {43, 1440}, {2272, 6561}, {79937, 1113912}, {3293, 556956}};
 
-constexpr int MAX_CONSEC_REJECT = 50;
+constexpr int RING_CAP = 65536;        // training rows
+constexpr int TRAIN_MAX = 1024;        // rows per gradient evaluation
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -50,6 +52,10 @@ bool valid_config(const ns_config* c) {
   if (c->batch < 1 || c->batch > 65535) return false;
   if (c->rhs_precision != NS_FP32 && c->rhs_precision != NS_FP64) return false;
   if (c->scalar != 0 && !(c->dim == 2 && c->scalar == 1)) return false;
+  if (c->force_kf > 0.0 && c->dim != 3) return false;
+  if (!std::isfinite(c->ri) || !std::isfinite(c->kappa) || !std::isfinite(c->force_kf) ||
+      !std::isfinite(c->force_e0))
+    return false;
   return true;
 }
 
@@ -69,26 +75,49 @@ Geom make_geom(const ns_config* c) {
 }
 
 struct Layout {
-  size_t tw32, tw64, nu, h, red_out, mask, red_part, fields[10], a1, a2, total;
+  size_t tw32, tw64, nu, h, red_out, mask, alpha, red_part;
+  size_t ctl_d[6], ctl_i[7], ctl_l[3];
+  size_t mw, mmom, mvel, mgrad, mloss, mx, my, pend_x, pend_h, pend_ok, ring_x, ring_y, ring_n, rows, act;
+  size_t fields[10], a1, a2, total;
 };
 
 Layout make_layout(const ns_config* c) {
   const Geom g = make_geom(c);
+  const size_t B = (size_t)g.batch;
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   L.tw32 = take(nsk::TWN_TABLE * 8);
   L.tw64 = take(nsk::TWN_TABLE * 16);
-  L.nu = take((size_t)g.batch * 8);
-  L.h = take((size_t)g.batch * 8);
-  L.red_out = take((size_t)g.batch * nsk::NRED * 8);
-  L.mask = take((size_t)g.batch * 4);
+  L.nu = take(B * 8);
+  L.h = take(B * 8);
+  L.red_out = take(B * nsk::NRED * 8);
+  L.mask = take(B * 4);
+  L.alpha = take(B * 8);
   L.red_part = take(nsk::reduce_scratch_bytes(g));
-  for (int i = 0; i < 10; ++i) L.fields[i] = take((size_t)g.epm * g.batch * 16);
+  for (int i = 0; i < 6; ++i) L.ctl_d[i] = take(B * 8 * (i == 5 ? 3 : 1));
+  for (int i = 0; i < 7; ++i) L.ctl_i[i] = take(B * 4);
+  for (int i = 0; i < 3; ++i) L.ctl_l[i] = take(B * 8);
+  L.mw = take(nsk::MLP_NWEIGHTS * 4);
+  L.mmom = take(nsk::MLP_NPARAM * 4);
+  L.mvel = take(nsk::MLP_NPARAM * 4);
+  L.mgrad = take(nsk::MLP_NPARAM * 4);
+  L.mloss = take(4);
+  L.mx = take(B * 20 * 4);
+  L.my = take(B * 4);
+  L.pend_x = take(B * 20 * 4);
+  L.pend_h = take(B * 8);
+  L.pend_ok = take(B * 4);
+  L.ring_x = take((size_t)RING_CAP * 20 * 4);
+  L.ring_y = take((size_t)RING_CAP * 4);
+  L.ring_n = take(8);
+  L.rows = take((size_t)TRAIN_MAX * 4);
+  L.act = take(nsk::mlp_act_floats(TRAIN_MAX) * 4);
+  for (int i = 0; i < 10; ++i) L.fields[i] = take((size_t)g.epm * B * 16);
   const int fp64 = c->rhs_precision == NS_FP64;
   const size_t scratch = c->dim == 3 ? nsk::rhs3d_scratch_bytes(g, fp64) : nsk::rhs2d_scratch_bytes(g, fp64);
   const size_t cb = fp64 ? 16 : 8;
-  const size_t a1 = c->dim == 3 ? (size_t)g.batch * 6 * g.n * g.Kf * g.Kx * cb : scratch / 2;
+  const size_t a1 = c->dim == 3 ? B * 6 * g.n * g.Kf * g.Kx * cb : scratch / 2;
   L.a1 = take(a1);
   L.a2 = take(scratch - a1);
   L.total = off;
@@ -109,17 +138,42 @@ struct ns_solver {
   double* red_out;
   double* red_part;
   int* mask_d;
+  double* alpha_d;
   void* tw;          // twiddles in the rhs precision
   double2* u;        // committed state u_n (compact)
   double2* U;        // stage / candidate state
   double2* k[8];     // stage derivatives; k[0] = f(u_n) when k1_valid
   nsk::RhsBufs rb;
-  bool have_state;
-  bool k1_valid;
+  nsk::CtlState ctl;
+  // proposer network
+  float* mw;
+  float* mmom;
+  float* mvel;
+  float* mgrad;
+  float* mloss;
+  float* mx;
+  float* my;
+  float* pend_x;
+  double* pend_h;
+  int* pend_ok;
+  float* ring_x;
+  float* ring_y;
+  long long* ring_n;
+  int* rows;
+  float* act;
+  bool mlp_loaded = false;
+  bool collect = false;
+  long long adam_t = 0;
+  bool have_state = false;
+  bool k1_valid = false;
   std::vector<double> t;          // per-member time
-  std::vector<double> hbuf;       // per-member step staging for uploads
   std::vector<int> maskbuf;
   std::vector<double> red_host;   // per-member reductions
+  // captured attempt graph of ns_integrate and the parameters it bakes in
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_st = nullptr;   // private stream: graphs cannot be captured on the null stream
+  double g_atol = -1, g_rtol = -1, g_tend = 0;
+  int g_ctrl = -1, g_collect = -1;
   // kernel timing (ns_profile_start/stop)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -138,9 +192,9 @@ static void prof_hook(void* ctx, int id, int phase) {
   ++s->prof_used;
 }
 
-#define NS_HIP(call)                         \
-  do {                                       \
-    if ((call) != hipSuccess) return NS_ERR_HIP; \
+#define NS_HIP(call)                              \
+  do {                                            \
+    if ((call) != hipSuccess) return NS_ERR_HIP;  \
   } while (0)
 
 static int rhs(ns_solver* s, const double2* U, double2* K) {
@@ -160,11 +214,6 @@ static int ensure_k1(ns_solver* s) {
   return rc;
 }
 
-static int upload_h(ns_solver* s) {
-  NS_HIP(hipMemcpyAsync(s->h_d, s->hbuf.data(), sizeof(double) * s->g.batch, hipMemcpyHostToDevice, s->st));
-  return NS_OK;
-}
-
 static int fetch_reductions(ns_solver* s) {
   NS_HIP(hipMemcpyAsync(s->red_host.data(), s->red_out, sizeof(double) * nsk::NRED * s->g.batch,
                         hipMemcpyDeviceToHost, s->st));
@@ -172,11 +221,14 @@ static int fetch_reductions(ns_solver* s) {
   return NS_OK;
 }
 
-// One BS5 attempt with the per-member steps already in h_d.  Leaves the
-// candidate u_{n+1} in U and f(u_{n+1}) in k[7]; errs receives err per member.
-static int bs5_attempt(ns_solver* s, double atol, double rtol, std::vector<double>& errs) {
-  int rc = ensure_k1(s);
-  if (rc) return rc;
+static double forcing_kf2(const ns_solver* s) {
+  return s->cfg.force_kf > 0.0 ? s->cfg.force_kf * s->cfg.force_kf : -1.0;
+}
+
+// Stages 2..8 of a BS5 attempt and the fused error / diagnostics reduction,
+// with the per-member steps in h.  Leaves u_{n+1} in U, f(u_{n+1}) in k[7],
+// the reduction in red_out.  Needs a valid k[0].
+static int bs5_stages(ns_solver* s, const double* h, double atol, double rtol) {
   for (int i = 1; i < 8; ++i) {
     Combo c;
     c.nterms = 0;
@@ -188,9 +240,9 @@ static int bs5_attempt(ns_solver* s, double atol, double rtol, std::vector<doubl
       ++c.nterms;
     }
     prof_hook(s, nsk::PROF_COMBINE, 0);
-    NS_HIP(nsk::combine(s->g, s->u, c, s->h_d, s->U, s->st));
+    NS_HIP(nsk::combine(s->g, s->u, c, h, s->U, s->st));
     prof_hook(s, nsk::PROF_COMBINE, 1);
-    rc = rhs(s, s->U, s->k[i]);
+    int rc = rhs(s, s->U, s->k[i]);
     if (rc) return rc;
   }
   nsk::ReduceArgs ra;
@@ -205,14 +257,43 @@ static int bs5_attempt(ns_solver* s, double atol, double rtol, std::vector<doubl
     ra.delta.coef[ra.delta.nterms] = e;
     ++ra.delta.nterms;
   }
-  ra.h = s->h_d;
+  ra.h = h;
   ra.atol = atol;
   ra.rtol = rtol;
+  ra.kf2 = forcing_kf2(s);
   prof_hook(s, nsk::PROF_REDUCE, 0);
   NS_HIP(nsk::reduce_state(s->g, ra, s->red_part, s->red_out, s->st));
   prof_hook(s, nsk::PROF_REDUCE, 1);
-  rc = fetch_reductions(s);
+  return NS_OK;
+}
+
+// Diagnostics-only reduction of the committed state into red_out.
+static int reduce_committed(ns_solver* s, const double2* fk) {
+  nsk::ReduceArgs ra;
+  ra.uo = nullptr;
+  ra.un = s->u;
+  ra.fk = fk;
+  ra.delta.nterms = 0;
+  ra.h = nullptr;
+  ra.atol = ra.rtol = 0.0;
+  ra.kf2 = forcing_kf2(s);
+  NS_HIP(nsk::reduce_state(s->g, ra, s->red_part, s->red_out, s->st));
+  return NS_OK;
+}
+
+// Sec. 3.3.1 forcing after committed steps: rescale 0 < |k| <= kf of every
+// member whose mask_dev entry is set (all if mask_dev is null) to restore E0.
+static int apply_forcing(ns_solver* s, const int* mask_dev) {
+  if (s->cfg.force_kf <= 0.0) return NS_OK;
+  int rc = reduce_committed(s, nullptr);
   if (rc) return rc;
+  NS_HIP(nsk::force_alpha(s->red_out, mask_dev, s->cfg.force_e0, s->alpha_d, s->g.batch, s->st));
+  NS_HIP(nsk::scale_band(s->g, s->u, s->alpha_d, forcing_kf2(s), s->st));
+  s->k1_valid = false;
+  return NS_OK;
+}
+
+static void errs_from_reductions(ns_solver* s, std::vector<double>& errs) {
   const double M = (double)s->g.full;
   errs.assign(s->g.batch, 0.0);
   for (int m = 0; m < s->g.batch; ++m) {
@@ -225,35 +306,55 @@ static int bs5_attempt(ns_solver* s, double atol, double rtol, std::vector<doubl
     }
     errs[m] = finite ? e : NAN;
   }
-  return NS_OK;
 }
 
 // Commit the candidate for members with accept[m] != 0: u <- U, k1 <- k8.
-static int commit(ns_solver* s, const std::vector<int>& accept) {
+static int commit_host(ns_solver* s, const std::vector<int>& accept) {
   int nacc = 0;
   for (int a : accept) nacc += a ? 1 : 0;
-  if (nacc == 0) return NS_OK;
+  s->maskbuf = accept;
+  NS_HIP(hipMemcpyAsync(s->mask_d, s->maskbuf.data(), sizeof(int) * s->g.batch, hipMemcpyHostToDevice, s->st));
   if (nacc == s->g.batch) {
     std::swap(s->u, s->U);
     std::swap(s->k[0], s->k[7]);
-    return NS_OK;
+    if (s->gexec) {                            // the captured graph holds the old pointers
+      (void)hipGraphExecDestroy(s->gexec);
+      s->gexec = nullptr;
+    }
+  } else if (nacc > 0) {
+    NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->mask_d, s->st));
+    NS_HIP(nsk::masked_copy(s->g, s->k[7], s->k[0], s->mask_d, s->st));
   }
-  s->maskbuf = accept;
-  NS_HIP(hipMemcpyAsync(s->mask_d, s->maskbuf.data(), sizeof(int) * s->g.batch, hipMemcpyHostToDevice, s->st));
-  NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->mask_d, s->st));
-  NS_HIP(nsk::masked_copy(s->g, s->k[7], s->k[0], s->mask_d, s->st));
+  if (nacc > 0) return apply_forcing(s, s->mask_d);
   return NS_OK;
 }
 
-// Sec. 2.2.1 step-size factor; cap_at_one after a rejection.
-static double step_factor(double err, bool cap_at_one) {
-  if (!std::isfinite(err)) return 0.01;
-  const double fmax = cap_at_one ? 1.0 : 2.0;
-  if (err == 0.0) return fmax;
-  double fac = 0.8 * std::pow(err, -0.2);
-  if (fac < 0.01) fac = 0.01;
-  if (fac > fmax) fac = fmax;
-  return fac;
+// One attempt of ns_integrate, all on the device: stages, reduction, the
+// proposer's features (and proposal), the controller, row collection, the
+// masked commit and the forcing.  Captured once into a graph.
+static int integrate_attempt(ns_solver* s, double atol, double rtol, double t_end, int use_mlp) {
+  int rc = bs5_stages(s, s->ctl.hc, atol, rtol);
+  if (rc) return rc;
+  const double M = (double)s->g.full;
+  const bool need_x = use_mlp || s->collect;
+  if (need_x)
+    NS_HIP(nsk::mlp_propose(s->red_out, s->ctl.errhist, M, s->g.ncomp, s->mw, use_mlp, s->mx, s->my,
+                            s->g.batch, s->st));
+  const int extra = s->cfg.force_kf > 0.0 ? 1 : 0;
+  NS_HIP(nsk::control_step(s->ctl, s->red_out, M, s->g.ncomp, t_end, s->g.batch, s->my, use_mlp, extra, s->st));
+  if (s->collect)
+    NS_HIP(nsk::collect_rows(s->ctl, s->mx, s->pend_x, s->pend_h, s->pend_ok, s->ring_x, s->ring_y, s->ring_n,
+                             RING_CAP, s->g.batch, s->st));
+  NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->ctl.accept, s->st));
+  NS_HIP(nsk::masked_copy(s->g, s->k[7], s->k[0], s->ctl.accept, s->st));
+  if (s->cfg.force_kf > 0.0) {
+    rc = apply_forcing(s, s->ctl.accept);
+    if (rc) return rc;
+    rc = rhs(s, s->u, s->k[0]);
+    if (rc) return rc;
+    s->k1_valid = true;
+  }
+  return NS_OK;
 }
 
 extern "C" {
@@ -279,23 +380,54 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->fp64 = cfg->rhs_precision == NS_FP64;
   s->ws = (char*)workspace;
   s->L = L;
-  s->nu_d = (double*)(s->ws + L.nu);
-  s->h_d = (double*)(s->ws + L.h);
-  s->red_out = (double*)(s->ws + L.red_out);
-  s->red_part = (double*)(s->ws + L.red_part);
-  s->mask_d = (int*)(s->ws + L.mask);
-  s->tw = s->ws + (s->fp64 ? L.tw64 : L.tw32);
-  s->u = (double2*)(s->ws + L.fields[0]);
-  s->U = (double2*)(s->ws + L.fields[1]);
-  for (int i = 0; i < 8; ++i) s->k[i] = (double2*)(s->ws + L.fields[2 + i]);
-  s->rb.a1 = s->ws + L.a1;
-  s->rb.a2 = s->ws + L.a2;
+  char* w = s->ws;
+  s->nu_d = (double*)(w + L.nu);
+  s->h_d = (double*)(w + L.h);
+  s->red_out = (double*)(w + L.red_out);
+  s->red_part = (double*)(w + L.red_part);
+  s->mask_d = (int*)(w + L.mask);
+  s->alpha_d = (double*)(w + L.alpha);
+  s->tw = w + (s->fp64 ? L.tw64 : L.tw32);
+  s->u = (double2*)(w + L.fields[0]);
+  s->U = (double2*)(w + L.fields[1]);
+  for (int i = 0; i < 8; ++i) s->k[i] = (double2*)(w + L.fields[2 + i]);
+  s->rb.a1 = w + L.a1;
+  s->rb.a2 = w + L.a2;
   s->rb.hook = prof_hook;
   s->rb.hook_ctx = s;
-  s->have_state = false;
-  s->k1_valid = false;
+  nsk::CtlState& c = s->ctl;
+  c.t = (double*)(w + L.ctl_d[0]);
+  c.h = (double*)(w + L.ctl_d[1]);
+  c.hc = (double*)(w + L.ctl_d[2]);
+  c.hacc = (double*)(w + L.ctl_d[3]);
+  c.err = (double*)(w + L.ctl_d[4]);
+  c.errhist = (double*)(w + L.ctl_d[5]);
+  c.prev_rej = (int*)(w + L.ctl_i[0]);
+  c.consec = (int*)(w + L.ctl_i[1]);
+  c.done = (int*)(w + L.ctl_i[2]);
+  c.last = (int*)(w + L.ctl_i[3]);
+  c.clipped = (int*)(w + L.ctl_i[4]);
+  c.accept = (int*)(w + L.ctl_i[5]);
+  c.fail = (int*)(w + L.ctl_i[6]);
+  c.nacc = (long long*)(w + L.ctl_l[0]);
+  c.nrej = (long long*)(w + L.ctl_l[1]);
+  c.nrhs = (long long*)(w + L.ctl_l[2]);
+  s->mw = (float*)(w + L.mw);
+  s->mmom = (float*)(w + L.mmom);
+  s->mvel = (float*)(w + L.mvel);
+  s->mgrad = (float*)(w + L.mgrad);
+  s->mloss = (float*)(w + L.mloss);
+  s->mx = (float*)(w + L.mx);
+  s->my = (float*)(w + L.my);
+  s->pend_x = (float*)(w + L.pend_x);
+  s->pend_h = (double*)(w + L.pend_h);
+  s->pend_ok = (int*)(w + L.pend_ok);
+  s->ring_x = (float*)(w + L.ring_x);
+  s->ring_y = (float*)(w + L.ring_y);
+  s->ring_n = (long long*)(w + L.ring_n);
+  s->rows = (int*)(w + L.rows);
+  s->act = (float*)(w + L.act);
   s->t.assign(cfg->batch, 0.0);
-  s->hbuf.assign(cfg->batch, 0.0);
   s->maskbuf.assign(cfg->batch, 0);
   s->red_host.assign((size_t)cfg->batch * nsk::NRED, 0.0);
   // twiddles exp(-2 pi i m / TWN) from the host's double-precision libm
@@ -309,9 +441,16 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
     t32[2 * m] = (float)t64[2 * m];
     t32[2 * m + 1] = (float)t64[2 * m + 1];
   }
-  bool ok = hipMemcpyAsync(s->ws + L.tw32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, s->st) == hipSuccess &&
-            hipMemcpyAsync(s->ws + L.tw64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, s->st) == hipSuccess &&
+  std::vector<float> zf(nsk::MLP_NPARAM, 0.0f);
+  const long long zero_ll = 0;
+  std::vector<int> zi(cfg->batch, 0);
+  bool ok = hipMemcpyAsync(w + L.tw32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, s->st) == hipSuccess &&
+            hipMemcpyAsync(w + L.tw64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, s->st) == hipSuccess &&
             hipMemcpyAsync(s->nu_d, nu_host, sizeof(double) * cfg->batch, hipMemcpyHostToDevice, s->st) == hipSuccess &&
+            hipMemcpyAsync(s->ring_n, &zero_ll, 8, hipMemcpyHostToDevice, s->st) == hipSuccess &&
+            hipMemcpyAsync(s->pend_ok, zi.data(), sizeof(int) * cfg->batch, hipMemcpyHostToDevice, s->st) == hipSuccess &&
+            hipMemcpyAsync(s->mmom, zf.data(), nsk::MLP_NPARAM * 4, hipMemcpyHostToDevice, s->st) == hipSuccess &&
+            hipMemcpyAsync(s->mvel, zf.data(), nsk::MLP_NPARAM * 4, hipMemcpyHostToDevice, s->st) == hipSuccess &&
             hipStreamSynchronize(s->st) == hipSuccess;
   if (!ok) {
     delete s;
@@ -373,7 +512,9 @@ int ns_step_rk4(ns_solver* s, double h) {
     c.nterms = 1;
     c.src[0] = s->k[i - 1];
     c.coef[0] = stage_a[i - 1];
+    prof_hook(s, nsk::PROF_COMBINE, 0);
     NS_HIP(nsk::combine(s->g, s->u, c, s->h_d, s->U, s->st));
+    prof_hook(s, nsk::PROF_COMBINE, 1);
     rc = rhs(s, s->U, s->k[i]);
     if (rc) return rc;
   }
@@ -384,21 +525,32 @@ int ns_step_rk4(ns_solver* s, double h) {
     c.src[j] = s->k[j];
     c.coef[j] = b[j];
   }
+  prof_hook(s, nsk::PROF_COMBINE, 0);
   NS_HIP(nsk::combine(s->g, s->u, c, s->h_d, s->U, s->st));
+  prof_hook(s, nsk::PROF_COMBINE, 1);
   std::swap(s->u, s->U);
+  if (s->gexec) {                              // the captured graph holds the old pointers
+    (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+  }
   s->k1_valid = false;
   for (double& tm : s->t) tm += h;
-  return NS_OK;
+  return apply_forcing(s, nullptr);
 }
 
 int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags, double* err_host) {
   if (!s || !std::isfinite(h) || h < 0.0 || !(atol >= 0.0) || !(rtol >= 0.0) || atol + rtol <= 0.0)
     return NS_ERR_ARG;
   if (!s->have_state) return NS_ERR_STATE;
-  NS_HIP(nsk::fill(s->h_d, h, s->g.batch, s->st));
-  std::vector<double> errs;
-  int rc = bs5_attempt(s, atol, rtol, errs);
+  int rc = ensure_k1(s);
   if (rc) return rc;
+  NS_HIP(nsk::fill(s->h_d, h, s->g.batch, s->st));
+  rc = bs5_stages(s, s->h_d, atol, rtol);
+  if (rc) return rc;
+  rc = fetch_reductions(s);
+  if (rc) return rc;
+  std::vector<double> errs;
+  errs_from_reductions(s, errs);
   std::vector<int> acc(s->g.batch);
   bool any_rej = false;
   for (int m = 0; m < s->g.batch; ++m) {
@@ -407,7 +559,7 @@ int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags, dou
     else any_rej = true;
     if (err_host) err_host[m] = errs[m];
   }
-  rc = commit(s, acc);
+  rc = commit_host(s, acc);
   if (rc) return rc;
   return any_rej ? NS_STEP_REJECTED : NS_OK;
 }
@@ -416,66 +568,139 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
                  ns_stats* stats_host) {
   if (!s || !std::isfinite(t_end) || !(h0 > 0.0) || !(atol >= 0.0) || !(rtol >= 0.0) || atol + rtol <= 0.0)
     return NS_ERR_ARG;
-  if (controller != NS_CTRL_PI) return NS_ERR_UNSUPPORTED;
+  const int ctrl = controller & 0xff;
+  const bool use_graph = !(controller & NS_INTEGRATE_HOST);
+  if (ctrl != NS_CTRL_PI && ctrl != NS_CTRL_MLP) return NS_ERR_ARG;
+  if (ctrl == NS_CTRL_MLP && !s->mlp_loaded) return NS_ERR_STATE;
   if (!s->have_state) return NS_ERR_STATE;
   const int B = s->g.batch;
-  std::vector<double> h(B, h0), hc(B, 0.0), errs;
-  std::vector<int> prev_rej(B, 0), consec(B, 0), acc(B, 0), last(B, 0), done(B, 0);
-  std::vector<ns_stats> st(B);
-  for (int m = 0; m < B; ++m) {
-    st[m] = ns_stats{s->t[m], h0, 0.0, 0, 0, 0};
-    done[m] = s->t[m] >= t_end;
+  const int use_mlp = ctrl == NS_CTRL_MLP;
+  // reset the controller: time from the host, h0, no history
+  {
+    std::vector<double> hv(B, h0), ones(3 * (size_t)B, 1.0), zd(B, 0.0);
+    std::vector<int> zi(B, 0);
+    std::vector<long long> zl(B, 0);
+    const nsk::CtlState& c = s->ctl;
+    NS_HIP(hipMemcpyAsync(c.t, s->t.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    NS_HIP(hipMemcpyAsync(c.h, hv.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    NS_HIP(hipMemcpyAsync(c.err, zd.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    NS_HIP(hipMemcpyAsync(c.errhist, ones.data(), 24 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    int* ints[] = {c.prev_rej, c.consec, c.clipped, c.accept, c.fail};
+    for (int* p : ints) NS_HIP(hipMemcpyAsync(p, zi.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    long long* lls[] = {c.nacc, c.nrej, c.nrhs};
+    for (long long* p : lls) NS_HIP(hipMemcpyAsync(p, zl.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    NS_HIP(hipMemcpyAsync(s->pend_ok, zi.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    NS_HIP(nsk::control_start(c, t_end, B, s->st));
+    NS_HIP(hipStreamSynchronize(s->st));   // the host vectors go out of scope
   }
+  const bool first = !s->k1_valid;
+  int rc = ensure_k1(s);
+  if (rc) return rc;
+  const bool prof = s->prof_on;
+  // Attempts run on a private non-blocking stream (a graph cannot be captured
+  // on the null stream), ordered after and before the caller's stream.
+  if (!s->cap_st) NS_HIP(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
+  hipStream_t user_st = s->st;
+  hipEvent_t ev[2];
+  if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return NS_ERR_HIP;
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return NS_ERR_HIP;
+  }
+  int* done_pinned = nullptr;
   int status = NS_OK;
-  for (;;) {
-    bool any = false;
-    for (int m = 0; m < B; ++m) {
-      if (done[m]) { hc[m] = 0.0; continue; }
-      any = true;
-      last[m] = h[m] >= t_end - s->t[m];
-      hc[m] = last[m] ? t_end - s->t[m] : h[m];
-    }
-    if (!any) break;
-    const bool first = !s->k1_valid;
-    s->hbuf = hc;
-    int rc = upload_h(s);
-    if (rc) return rc;
-    rc = bs5_attempt(s, atol, rtol, errs);
-    if (rc) return rc;
-    for (int m = 0; m < B; ++m) {
-      acc[m] = 0;
-      if (done[m]) continue;
-      st[m].n_rhs += first ? 8 : 7;
-      const double err = errs[m];
-      const bool ok = std::isfinite(err) && err <= 1.0;
-      const double fac = step_factor(err, ok && prev_rej[m]);
-      st[m].last_err = err;
-      if (ok) {
-        acc[m] = 1;
-        s->t[m] = last[m] ? t_end : s->t[m] + hc[m];
-        prev_rej[m] = 0;
-        consec[m] = 0;
-        st[m].n_accept++;
-        h[m] = hc[m] * fac;
-        if (s->t[m] >= t_end) done[m] = 1;
+  if (hipEventRecord(ev[0], user_st) != hipSuccess || hipStreamWaitEvent(s->cap_st, ev[0], 0) != hipSuccess ||
+      hipHostMalloc((void**)&done_pinned, sizeof(int) * 2 * (size_t)B, 0) != hipSuccess)
+    status = NS_ERR_HIP;
+  s->st = s->cap_st;
+  if (!status && use_graph) {
+    const bool stale = !s->gexec || s->g_atol != atol || s->g_rtol != rtol || s->g_tend != t_end ||
+                       s->g_ctrl != ctrl || s->g_collect != (int)s->collect;
+    if (stale) {
+      if (s->gexec) {
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+      }
+      s->prof_on = false;                      // no timing events inside the graph
+      hipGraph_t graph = nullptr;
+      if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        status = NS_ERR_HIP;
       } else {
-        prev_rej[m] = 1;
-        st[m].n_reject++;
-        h[m] = hc[m] * fac;
-        if (++consec[m] >= MAX_CONSEC_REJECT) {
-          done[m] = 1;
-          status = NS_ERR_STEPFAIL;
+        rc = integrate_attempt(s, atol, rtol, t_end, use_mlp);
+        hipError_t ec = hipStreamEndCapture(s->st, &graph);
+        if (rc) status = rc;
+        else if (ec != hipSuccess) status = NS_ERR_HIP;
+        else if (hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+          s->gexec = nullptr;
+          status = NS_ERR_HIP;
         }
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      s->prof_on = prof;
+      if (!status) {
+        s->g_atol = atol;
+        s->g_rtol = rtol;
+        s->g_tend = t_end;
+        s->g_ctrl = ctrl;
+        s->g_collect = (int)s->collect;
       }
     }
-    rc = commit(s, acc);
-    if (rc) return rc;
   }
-  if (stats_host) {
-    for (int m = 0; m < B; ++m) {
-      st[m].t = s->t[m];
-      st[m].h_next = h[m];
-      stats_host[m] = st[m];
+  // Replay attempts; the done flags are read back one attempt behind, so the
+  // host never waits on the attempt in flight (at most one extra attempt,
+  // which is a no-op for finished members).
+  long long attempts = 0;
+  while (!status) {
+    const int slot = (int)(attempts & 1);
+    if (use_graph) {
+      if (hipGraphLaunch(s->gexec, s->st) != hipSuccess) { status = NS_ERR_HIP; break; }
+    } else {
+      rc = integrate_attempt(s, atol, rtol, t_end, use_mlp);
+      if (rc) { status = rc; break; }
+    }
+    if (hipMemcpyAsync(done_pinned + (size_t)slot * B, s->ctl.done, sizeof(int) * B, hipMemcpyDeviceToHost,
+                       s->st) != hipSuccess ||
+        hipEventRecord(ev[slot], s->st) != hipSuccess) {
+      status = NS_ERR_HIP;
+      break;
+    }
+    ++attempts;
+    if (attempts >= 2) {
+      const int prev = 1 - slot;
+      if (hipEventSynchronize(ev[prev]) != hipSuccess) { status = NS_ERR_HIP; break; }
+      bool all = true;
+      for (int m = 0; m < B; ++m) all = all && done_pinned[(size_t)prev * B + m];
+      if (all) break;
+    }
+  }
+  (void)hipStreamSynchronize(s->st);
+  s->st = user_st;
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (done_pinned) (void)hipHostFree(done_pinned);
+  if (status) return status;
+  s->k1_valid = true;
+  // results back to the host
+  std::vector<double> tt(B), hh(B), ee(B);
+  std::vector<long long> na(B), nr(B), nh(B);
+  std::vector<int> fl(B);
+  NS_HIP(hipMemcpy(tt.data(), s->ctl.t, 8 * (size_t)B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(hh.data(), s->ctl.h, 8 * (size_t)B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(ee.data(), s->ctl.err, 8 * (size_t)B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(na.data(), s->ctl.nacc, 8 * (size_t)B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(nr.data(), s->ctl.nrej, 8 * (size_t)B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(nh.data(), s->ctl.nrhs, 8 * (size_t)B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(fl.data(), s->ctl.fail, 4 * (size_t)B, hipMemcpyDeviceToHost));
+  for (int m = 0; m < B; ++m) {
+    s->t[m] = tt[m];
+    if (fl[m]) status = NS_ERR_STEPFAIL;
+    if (stats_host) {
+      stats_host[m].t = tt[m];
+      stats_host[m].h_next = hh[m];
+      stats_host[m].last_err = ee[m];
+      stats_host[m].n_rhs = nh[m] + (first ? 1 : 0);
+      stats_host[m].n_accept = na[m];
+      stats_host[m].n_reject = nr[m];
     }
   }
   return status;
@@ -498,14 +723,8 @@ int ns_diagnostics(ns_solver* s, double* energy_host, double* dissipation_host, 
   if (!s->have_state) return NS_ERR_STATE;
   int rc = ensure_k1(s);
   if (rc) return rc;
-  nsk::ReduceArgs ra;
-  ra.uo = nullptr;
-  ra.un = s->u;
-  ra.fk = s->k[0];
-  ra.delta.nterms = 0;
-  ra.h = nullptr;
-  ra.atol = ra.rtol = 0.0;
-  NS_HIP(nsk::reduce_state(s->g, ra, s->red_part, s->red_out, s->st));
+  rc = reduce_committed(s, s->k[0]);
+  if (rc) return rc;
   rc = fetch_reductions(s);
   if (rc) return rc;
   for (int m = 0; m < s->g.batch; ++m) {
@@ -518,6 +737,115 @@ int ns_diagnostics(ns_solver* s, double* energy_host, double* dissipation_host, 
   return NS_OK;
 }
 
+// ---------------------------------------------------------------- proposer
+int ns_mlp_set_weights(ns_solver* s, const float* w_host) {
+  if (!s || !w_host) return NS_ERR_ARG;
+  NS_HIP(hipStreamSynchronize(s->st));
+  NS_HIP(hipMemcpy(s->mw, w_host, sizeof(float) * nsk::MLP_NWEIGHTS, hipMemcpyHostToDevice));
+  s->mlp_loaded = true;
+  return NS_OK;
+}
+
+int ns_mlp_get_weights(ns_solver* s, float* w_host) {
+  if (!s || !w_host) return NS_ERR_ARG;
+  NS_HIP(hipStreamSynchronize(s->st));
+  NS_HIP(hipMemcpy(w_host, s->mw, sizeof(float) * nsk::MLP_NWEIGHTS, hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+int ns_mlp_forward(ns_solver* s, const float* x_dev, int n, float* y_dev) {
+  if (!s || !x_dev || !y_dev || n < 0) return NS_ERR_ARG;
+  if (!s->mlp_loaded) return NS_ERR_STATE;
+  NS_HIP(nsk::mlp_forward(s->mw, x_dev, y_dev, n, s->st));
+  return NS_OK;
+}
+
+int ns_mlp_grad(ns_solver* s, const float* x_dev, const float* t_dev, int n, float* grad_host, float* loss_host) {
+  if (!s || !x_dev || !t_dev || n < 1 || n > TRAIN_MAX) return NS_ERR_ARG;
+  if (!s->mlp_loaded) return NS_ERR_STATE;
+  NS_HIP(nsk::mlp_grad(s->mw, x_dev, t_dev, nullptr, n, s->act, s->mgrad, s->mloss, s->st));
+  NS_HIP(hipStreamSynchronize(s->st));
+  if (grad_host) NS_HIP(hipMemcpy(grad_host, s->mgrad, sizeof(float) * nsk::MLP_NPARAM, hipMemcpyDeviceToHost));
+  if (loss_host) NS_HIP(hipMemcpy(loss_host, s->mloss, sizeof(float), hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+int ns_mlp_train_batch(ns_solver* s, const float* x_dev, const float* t_dev, int n, float lr, float* loss_host) {
+  if (!s || !x_dev || !t_dev || n < 1 || n > TRAIN_MAX || !(lr > 0.0f)) return NS_ERR_ARG;
+  if (!s->mlp_loaded) return NS_ERR_STATE;
+  NS_HIP(nsk::mlp_grad(s->mw, x_dev, t_dev, nullptr, n, s->act, s->mgrad, s->mloss, s->st));
+  NS_HIP(nsk::mlp_adam(s->mw, s->mgrad, s->mmom, s->mvel, lr, ++s->adam_t, s->st));
+  NS_HIP(hipStreamSynchronize(s->st));
+  if (loss_host) NS_HIP(hipMemcpy(loss_host, s->mloss, sizeof(float), hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+int ns_mlp_reset_optimizer(ns_solver* s) {
+  if (!s) return NS_ERR_ARG;
+  std::vector<float> z(nsk::MLP_NPARAM, 0.0f);
+  NS_HIP(hipStreamSynchronize(s->st));
+  NS_HIP(hipMemcpy(s->mmom, z.data(), sizeof(float) * z.size(), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(s->mvel, z.data(), sizeof(float) * z.size(), hipMemcpyHostToDevice));
+  s->adam_t = 0;
+  return NS_OK;
+}
+
+int ns_mlp_collect(ns_solver* s, int enable) {
+  if (!s) return NS_ERR_ARG;
+  s->collect = enable != 0;
+  return NS_OK;
+}
+
+static int ring_count(ns_solver* s, long long* cnt) {
+  NS_HIP(hipStreamSynchronize(s->st));
+  NS_HIP(hipMemcpy(cnt, s->ring_n, 8, hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+int ns_mlp_rows(ns_solver* s, float* x_host, float* y_host, int max_rows, long long* count_host) {
+  if (!s || max_rows < 0) return NS_ERR_ARG;
+  long long cnt = 0;
+  int rc = ring_count(s, &cnt);
+  if (rc) return rc;
+  if (count_host) *count_host = cnt;
+  long long n = cnt < RING_CAP ? cnt : RING_CAP;
+  if (n > max_rows) n = max_rows;
+  if (n > 0 && x_host) NS_HIP(hipMemcpy(x_host, s->ring_x, sizeof(float) * 20 * n, hipMemcpyDeviceToHost));
+  if (n > 0 && y_host) NS_HIP(hipMemcpy(y_host, s->ring_y, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+int ns_mlp_fit_stats(ns_solver* s) {
+  if (!s) return NS_ERR_ARG;
+  long long cnt = 0;
+  int rc = ring_count(s, &cnt);
+  if (rc) return rc;
+  const int nrows = (int)(cnt < RING_CAP ? cnt : RING_CAP);
+  if (nrows < 2) return NS_ERR_STATE;
+  NS_HIP(nsk::mlp_stats(s->mw, s->ring_x, nrows, s->st));
+  NS_HIP(hipStreamSynchronize(s->st));
+  return NS_OK;
+}
+
+int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long long seed, float* loss_host) {
+  if (!s || iters < 0 || batch < 1 || batch > TRAIN_MAX || !(lr > 0.0f)) return NS_ERR_ARG;
+  if (!s->mlp_loaded) return NS_ERR_STATE;
+  long long cnt = 0;
+  int rc = ring_count(s, &cnt);
+  if (rc) return rc;
+  const int nrows = (int)(cnt < RING_CAP ? cnt : RING_CAP);
+  if (nrows < 1) return NS_ERR_STATE;
+  for (int it = 0; it < iters; ++it) {
+    NS_HIP(nsk::mlp_rows(s->rows, batch, seed, it, nrows, s->st));
+    NS_HIP(nsk::mlp_grad(s->mw, s->ring_x, s->ring_y, s->rows, batch, s->act, s->mgrad, s->mloss, s->st));
+    NS_HIP(nsk::mlp_adam(s->mw, s->mgrad, s->mmom, s->mvel, lr, ++s->adam_t, s->st));
+  }
+  NS_HIP(hipStreamSynchronize(s->st));
+  if (loss_host) NS_HIP(hipMemcpy(loss_host, s->mloss, sizeof(float), hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+// ---------------------------------------------------------------- timing
 int ns_profile_start(ns_solver* s) {
   if (!s) return NS_ERR_ARG;
   if (s->prof_ev.empty()) {
@@ -567,13 +895,15 @@ const char* ns_strerror(int status) {
     case NS_ERR_NONFINITE: return "non-finite value in a reduction";
     case NS_ERR_STEPFAIL: return "too many consecutive rejected steps";
     case NS_ERR_UNSUPPORTED: return "size or mode not supported";
-    case NS_ERR_STATE: return "call out of order (state not set)";
+    case NS_ERR_STATE: return "call out of order (state or weights not set)";
     default: return "unknown status";
   }
 }
 
 void ns_free(ns_solver* s) {
   if (!s) return;
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
   for (auto& e : s->prof_ev) (void)hipEventDestroy(e);
   delete s;
 }

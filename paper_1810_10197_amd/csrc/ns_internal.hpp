@@ -65,8 +65,9 @@ hipError_t unpack_state(const Geom& g, const double2* compact, double2* full, hi
 
 // Fused reduction: embedded error sums (if delta != null), energy,
 // dissipation (if fk != null) and shell spectrum of `un` per member.
-// out[m*NRED + ...]: [0..2] sum |delta_j/sc_j|^2, [3] E, [4] eps, [5..20] shells.
-constexpr int NRED = 21;
+// out[m*NRED + ...]: [0..2] sum |delta_j/sc_j|^2, [3] E, [4] eps, [5..20] shells,
+// [21] energy of the forcing band 0 < |k|^2 <= kf2.
+constexpr int NRED = 22;
 constexpr int NBINS = 16;
 struct ReduceArgs {
   const double2* uo;      // u_n (for sc), may be null when no error
@@ -75,6 +76,7 @@ struct ReduceArgs {
   Combo delta;            // delta = h_m * sum coef_j src_j (nterms = 0: no error)
   const double* h;        // [batch]
   double atol, rtol;
+  double kf2;             // forcing band |k|^2 <= kf2 (<= 0: none)
 };
 size_t reduce_scratch_bytes(const Geom& g);
 hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, double* out,
@@ -83,9 +85,55 @@ hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, do
 // p[0..n) = v
 hipError_t fill(double* p, double v, int n, hipStream_t st);
 
+// u_hat <- alpha_m u_hat on the modes 0 < |k|^2 <= kf2 of every member
+// (alpha per member, device array; 3D only).
+hipError_t scale_band(const Geom& g, double2* u, const double* alpha, double kf2, hipStream_t st);
+
 // Copy member slices src -> dst for members with mask[m] != 0 (host mask copied
 // as a device array).
 hipError_t masked_copy(const Geom& g, const double2* src, double2* dst, const int* mask_dev,
+                       hipStream_t st);
+
+// ---- step-size proposer network (mlp.hip) ----
+constexpr int MLP_NPARAM = 5569;     // W1 64x20, b1, W2 64x64, b2, W3 1x64, b3
+constexpr int MLP_NWEIGHTS = 5609;   // + feature mean [20] and scale [20]
+hipError_t mlp_propose(const double* red, const double* errhist, double M, int ncomp, const float* w,
+                       int infer, float* xout, float* yout, int batch, hipStream_t st);
+hipError_t mlp_forward(const float* w, const float* x, float* y, int n, hipStream_t st);
+size_t mlp_act_floats(int nmax);
+hipError_t mlp_grad(const float* w, const float* x, const float* t, const int* rows, int n, float* act,
+                    float* grad, float* loss, hipStream_t st);
+hipError_t mlp_adam(float* w, const float* grad, float* mom, float* vel, float lr, long long t,
+                    hipStream_t st);
+hipError_t mlp_rows(int* rows, int n, unsigned long long seed, long long iter, int nrows, hipStream_t st);
+hipError_t mlp_stats(float* w, const float* x, int nrows, hipStream_t st);
+
+// ---- device-side controller (control.hip) ----
+struct CtlState {         // one entry per member, device memory
+  double* t;              // time reached
+  double* h;              // unclipped step proposed by the controller
+  double* hc;             // step of the next attempt (clipped; 0 when done)
+  double* hacc;           // step of the attempt just decided
+  double* err;            // its error estimate
+  double* errhist;        // [3] previous accepted errors, oldest first
+  int* prev_rej;
+  int* consec;
+  int* done;
+  int* last;              // the next attempt is clipped to t_end
+  int* clipped;           // the attempt just decided was clipped
+  int* accept;            // the attempt just decided is accepted
+  int* fail;
+  long long* nacc;
+  long long* nrej;
+  long long* nrhs;
+};
+hipError_t control_step(const CtlState& c, const double* red, double M, int ncomp, double t_end, int batch,
+                        const float* mlp_y, int use_mlp, int extra_rhs, hipStream_t st);
+hipError_t control_start(const CtlState& c, double t_end, int batch, hipStream_t st);
+hipError_t collect_rows(const CtlState& c, const float* xnew, float* pend_x, double* pend_h, int* pend_ok,
+                        float* ring_x, float* ring_y, long long* ring_count, int cap, int batch,
+                        hipStream_t st);
+hipError_t force_alpha(const double* red, const int* accept, double e0, double* alpha, int batch,
                        hipStream_t st);
 
 }  // namespace nsk

@@ -180,11 +180,13 @@ __global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, Geom g, double* __
         const double2 f = a.fk[gi];
         acc[4] -= w * (un.x * f.x + un.y * f.y);
       }
-      const double kmag = sqrt((double)(md.kx * md.kx + md.ky * md.ky + md.kz * md.kz));
+      const int k2i = md.kx * md.kx + md.ky * md.ky + md.kz * md.kz;
+      const double kmag = sqrt((double)k2i);
       int bin = (int)floor((16.0 * kmag) / kdiv);
       bin = bin > NBINS - 1 ? NBINS - 1 : bin;
 #pragma unroll
       for (int b = 0; b < NBINS; ++b) acc[5 + b] += (b == bin) ? e : 0.0;
+      acc[21] += (k2i > 0 && (double)k2i <= a.kf2) ? e : 0.0;
     }
   }
   __shared__ double red[RBS / 64][NRED];
@@ -238,6 +240,38 @@ __global__ void k_masked_copy(const double2* __restrict__ src, double2* __restri
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
     if (mask[i / epm]) dst[i] = src[i];
+}
+
+// The band 0 < |k|^2 <= kf2 lies in the cube |k_j| <= kc = floor(sqrt(kf2)):
+// one thread per (member, component, cube mode).
+__global__ void k_scale_band(double2* __restrict__ u, const double* __restrict__ alpha, Geom g,
+                             double kf2, int kc) {
+  const int side = 2 * kc + 1;
+  const long long per = (long long)side * side * (kc + 1);
+  const long long total = per * g.ncomp * g.batch;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long mc = i / per, q = i - mc * per;
+  const int kx = (int)(q % (kc + 1));
+  const long long r = q / (kc + 1);
+  const int ky = (int)(r % side) - kc, kz = (int)(r / side) - kc;
+  const int k2 = kx * kx + ky * ky + kz * kz;
+  if (k2 == 0 || (double)k2 > kf2) return;
+  const long long m = mc / g.ncomp, c = mc - m * g.ncomp;
+  const long long off = ((long long)(kz >= 0 ? kz : kz + g.Kf) * g.Kf + (ky >= 0 ? ky : ky + g.Kf)) * g.Kx + kx;
+  double2* p = u + m * g.epm + c * g.mr + off;
+  const double a = alpha[m];
+  *p = make_double2(p->x * a, p->y * a);
+}
+
+hipError_t scale_band(const Geom& g, double2* u, const double* alpha, double kf2, hipStream_t st) {
+  int kc = (int)floor(sqrt(kf2));
+  if (kc > g.K) kc = g.K;
+  if (kc < 1) return hipSuccess;
+  const long long total = (long long)(2 * kc + 1) * (2 * kc + 1) * (kc + 1) * g.ncomp * g.batch;
+  hipLaunchKernelGGL(k_scale_band, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, u, alpha, g,
+                     kf2, kc);
+  return hipGetLastError();
 }
 
 __global__ void k_fill(double* __restrict__ p, double v, int n) {

@@ -31,11 +31,16 @@ NS_FP64 = 1
 NS_CTRL_PI = 0
 NS_CTRL_MLP = 1
 NS_FORCE_COMMIT = 1
+NS_INTEGRATE_HOST = 0x100
+NS_MLP_NPARAM = 5569
+NS_MLP_NWEIGHTS = 5609
 
 EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_set_nu",
            "ns_rhs", "ns_step_rk4", "ns_step_bs5", "ns_integrate", "ns_get_time",
-           "ns_set_time", "ns_diagnostics", "ns_refresh_rhs", "ns_profile_start",
-           "ns_profile_stop", "ns_strerror", "ns_free"]
+           "ns_set_time", "ns_diagnostics", "ns_refresh_rhs", "ns_mlp_set_weights",
+           "ns_mlp_get_weights", "ns_mlp_forward", "ns_mlp_grad", "ns_mlp_train_batch",
+           "ns_mlp_reset_optimizer", "ns_mlp_collect", "ns_mlp_rows", "ns_mlp_fit_stats",
+           "ns_mlp_train", "ns_profile_start", "ns_profile_stop", "ns_strerror", "ns_free"]
 PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other"]
 
 
@@ -67,6 +72,7 @@ _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int
 _DP = ctypes.POINTER(ctypes.c_double)
+_FP = ctypes.POINTER(ctypes.c_float)
 _sig = {
     "ns_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(NsConfig)]),
     "ns_init": (_I, [ctypes.POINTER(NsConfig), _DP, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
@@ -81,6 +87,16 @@ _sig = {
     "ns_set_time": (_I, [_P, _DP]),
     "ns_diagnostics": (_I, [_P, _DP, _DP, _DP]),
     "ns_refresh_rhs": (_I, [_P]),
+    "ns_mlp_set_weights": (_I, [_P, _FP]),
+    "ns_mlp_get_weights": (_I, [_P, _FP]),
+    "ns_mlp_forward": (_I, [_P, _P, _I, _P]),
+    "ns_mlp_grad": (_I, [_P, _P, _P, _I, _FP, _FP]),
+    "ns_mlp_train_batch": (_I, [_P, _P, _P, _I, ctypes.c_float, _FP]),
+    "ns_mlp_reset_optimizer": (_I, [_P]),
+    "ns_mlp_collect": (_I, [_P, _I]),
+    "ns_mlp_rows": (_I, [_P, _FP, _FP, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "ns_mlp_fit_stats": (_I, [_P]),
+    "ns_mlp_train": (_I, [_P, _I, _I, ctypes.c_float, ctypes.c_ulonglong, _FP]),
     "ns_profile_start": (_I, [_P]),
     "ns_profile_stop": (_I, [_P, ctypes.POINTER(NsKernelTimes)]),
     "ns_strerror": (ctypes.c_char_p, [_I]),
@@ -100,6 +116,10 @@ class NsError(RuntimeError):
 
 def _dptr(a):
     return a.ctypes.data_as(_DP) if a is not None else None
+
+
+def _fptr(a):
+    return a.ctypes.data_as(_FP) if a is not None else None
 
 
 def _check(status, where, ok=(NS_OK,)):
@@ -173,6 +193,55 @@ def ns_diagnostics(h, e_out, eps_out, shells_out):
 
 def ns_refresh_rhs(h):
     return _check(_lib.ns_refresh_rhs(h), "ns_refresh_rhs")
+
+
+def ns_mlp_set_weights(h, w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    if w.size != NS_MLP_NWEIGHTS:
+        raise ValueError("expected %d weights" % NS_MLP_NWEIGHTS)
+    return _check(_lib.ns_mlp_set_weights(h, _fptr(w)), "ns_mlp_set_weights")
+
+
+def ns_mlp_get_weights(h, out):
+    return _check(_lib.ns_mlp_get_weights(h, _fptr(out)), "ns_mlp_get_weights")
+
+
+def ns_mlp_forward(h, x_ptr, n, y_ptr):
+    return _check(_lib.ns_mlp_forward(h, _P(x_ptr), int(n), _P(y_ptr)), "ns_mlp_forward")
+
+
+def ns_mlp_grad(h, x_ptr, t_ptr, n, grad_out, loss_out):
+    return _check(_lib.ns_mlp_grad(h, _P(x_ptr), _P(t_ptr), int(n), _fptr(grad_out),
+                                   _fptr(loss_out)), "ns_mlp_grad")
+
+
+def ns_mlp_train_batch(h, x_ptr, t_ptr, n, lr, loss_out):
+    return _check(_lib.ns_mlp_train_batch(h, _P(x_ptr), _P(t_ptr), int(n), float(lr),
+                                          _fptr(loss_out)), "ns_mlp_train_batch")
+
+
+def ns_mlp_reset_optimizer(h):
+    return _check(_lib.ns_mlp_reset_optimizer(h), "ns_mlp_reset_optimizer")
+
+
+def ns_mlp_collect(h, enable):
+    return _check(_lib.ns_mlp_collect(h, int(bool(enable))), "ns_mlp_collect")
+
+
+def ns_mlp_rows(h, x_out, y_out, max_rows):
+    cnt = ctypes.c_longlong(0)
+    _check(_lib.ns_mlp_rows(h, _fptr(x_out), _fptr(y_out), int(max_rows), ctypes.byref(cnt)),
+           "ns_mlp_rows")
+    return cnt.value
+
+
+def ns_mlp_fit_stats(h):
+    return _check(_lib.ns_mlp_fit_stats(h), "ns_mlp_fit_stats")
+
+
+def ns_mlp_train(h, iters, batch, lr, seed, loss_out):
+    return _check(_lib.ns_mlp_train(h, int(iters), int(batch), float(lr), int(seed),
+                                    _fptr(loss_out)), "ns_mlp_train")
 
 
 def ns_profile_start(h):
@@ -251,11 +320,73 @@ class Solver:
         st = ns_step_bs5(self.handle, h, atol, rtol, NS_FORCE_COMMIT if force else 0, errs)
         return st, errs
 
-    def integrate(self, t_end, h0, atol, rtol, controller="pi"):
+    def integrate(self, t_end, h0, atol, rtol, controller="pi", graph=True):
         stats = (NsStats * self.batch)()
         ctl = {"pi": NS_CTRL_PI, "mlp": NS_CTRL_MLP}[controller]
+        if not graph:
+            ctl |= NS_INTEGRATE_HOST
         ns_integrate(self.handle, t_end, h0, atol, rtol, ctl, stats)
         return [s.as_dict() for s in stats]
+
+    # ---- step-size proposer
+    def mlp_set_weights(self, w):
+        ns_mlp_set_weights(self.handle, w)
+
+    def mlp_get_weights(self):
+        out = np.zeros(NS_MLP_NWEIGHTS, dtype=np.float32)
+        ns_mlp_get_weights(self.handle, out)
+        return out
+
+    def _f32(self, a):
+        t = self.torch
+        return t.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(self.device).contiguous()
+
+    def mlp_forward(self, x):
+        xd = self._f32(x)
+        n = xd.shape[0]
+        y = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        self.torch.cuda.synchronize(self.device)
+        ns_mlp_forward(self.handle, xd.data_ptr(), n, y.data_ptr())
+        self.stream.synchronize()
+        return y.cpu().numpy()
+
+    def mlp_grad(self, x, t):
+        xd, td = self._f32(x), self._f32(t)
+        g = np.zeros(NS_MLP_NPARAM, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        self.torch.cuda.synchronize(self.device)
+        ns_mlp_grad(self.handle, xd.data_ptr(), td.data_ptr(), xd.shape[0], g, loss)
+        return float(loss[0]), g
+
+    def mlp_train_batch(self, x, t, lr):
+        xd, td = self._f32(x), self._f32(t)
+        loss = np.zeros(1, dtype=np.float32)
+        self.torch.cuda.synchronize(self.device)
+        ns_mlp_train_batch(self.handle, xd.data_ptr(), td.data_ptr(), xd.shape[0], lr, loss)
+        return float(loss[0])
+
+    def mlp_reset_optimizer(self):
+        ns_mlp_reset_optimizer(self.handle)
+
+    def mlp_collect(self, enable=True):
+        ns_mlp_collect(self.handle, enable)
+
+    def mlp_rows(self, max_rows=65536):
+        cnt = ns_mlp_rows(self.handle, None, None, 0)
+        n = min(cnt, 65536, max_rows)
+        x = np.zeros((n, 20), dtype=np.float32)
+        y = np.zeros(n, dtype=np.float32)
+        if n:
+            ns_mlp_rows(self.handle, x, y, n)
+        return x, y, cnt
+
+    def mlp_fit_stats(self):
+        ns_mlp_fit_stats(self.handle)
+
+    def mlp_train(self, iters, batch, lr, seed=0):
+        loss = np.zeros(1, dtype=np.float32)
+        ns_mlp_train(self.handle, iters, batch, lr, seed, loss)
+        return float(loss[0])
 
     def time(self):
         t = np.zeros(self.batch)

@@ -61,8 +61,8 @@ def test_host_only_entry_points(lib):
 
 def test_workspace_scales_with_problem():
     from paper_1810_10197_amd import ns
-    a = ns.ns_workspace_bytes(ns.NsConfig(3, 64, 1, 0, 0, 0, 0, 0, 0))
-    b = ns.ns_workspace_bytes(ns.NsConfig(3, 64, 4, 0, 0, 0, 0, 0, 0))
-    c = ns.ns_workspace_bytes(ns.NsConfig(3, 64, 1, 1, 0, 0, 0, 0, 0))
+    a = ns.ns_workspace_bytes(ns.NsConfig(3, 128, 1, 0, 0, 0, 0, 0, 0))
+    b = ns.ns_workspace_bytes(ns.NsConfig(3, 128, 4, 0, 0, 0, 0, 0, 0))
+    c = ns.ns_workspace_bytes(ns.NsConfig(3, 128, 1, 1, 0, 0, 0, 0, 0))
     assert 3.5 * a < b < 4.5 * a
     assert c > a
