@@ -88,6 +88,7 @@ def main():
     atol = rtol = 1e-6
     s = ns.Solver(dim=3, n=n, batch=1, nu=nu, rhs_precision=args.prec)
     s.set_state(inputs.tgv3d(n)[None])
+    tune_variants, tune_ms = s.autotune(reps=3)
     for _ in range(args.warmup):
         s.step_bs5(args.dt, atol, rtol)
     # pure right-hand-side rate (context): f(u_n) into the cached stage
@@ -150,6 +151,8 @@ def main():
         "rhs_model_gbs": model_bytes / (rhs_ms * 1e-3) / 1e9,
         "rhs_only_per_s": rhs_only,
         "rejected_steps": rejected,
+        "autotune": {"variants": tune_variants,
+                     "ms": [[round(x, 4) for x in row] for row in tune_ms.tolist()]},
         "kernels": per_kernel,
     }
     if not args.no_cpu:

@@ -211,6 +211,20 @@ typedef struct ns_kernel_times {
 int ns_profile_start(ns_solver* s);
 int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
 
+/* Autotuner of the 3D right-hand side: each of the NS_NTUNE passes
+ * (z-inverse, y-inverse, x-pass, y-forward, z-forward) has launch variants
+ * (radix plan: wide = few passes, narrow = at most 8 values per thread;
+ * column tile: 16 or 32 columns per block).  ns_autotune times every variant
+ * of every pass on the current state (reps evaluations each, HIP events on the
+ * solver's stream) and keeps the fastest; ms_host (NS_NTUNE x 4 doubles, may
+ * be NULL) receives the average milliseconds (0 for variants a pass lacks).
+ * tune_get / tune_set read or restore the choice (e.g. from a cache).  2D
+ * solvers accept the calls and ignore the choice. */
+#define NS_NTUNE 5
+int ns_autotune(ns_solver* s, int reps, double* ms_host);
+int ns_tune_get(ns_solver* s, int* variant_host);
+int ns_tune_set(ns_solver* s, const int* variant_host);
+
 /* Static description of a status code. */
 const char* ns_strerror(int status);
 

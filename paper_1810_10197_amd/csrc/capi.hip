@@ -395,6 +395,7 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->rb.a2 = w + L.a2;
   s->rb.hook = prof_hook;
   s->rb.hook_ctx = s;
+  for (int i = 0; i < NS_NTUNE; ++i) s->rb.variant[i] = 0;
   nsk::CtlState& c = s->ctl;
   c.t = (double*)(w + L.ctl_d[0]);
   c.h = (double*)(w + L.ctl_d[1]);
@@ -843,6 +844,68 @@ int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long lon
   NS_HIP(hipStreamSynchronize(s->st));
   if (loss_host) NS_HIP(hipMemcpy(loss_host, s->mloss, sizeof(float), hipMemcpyDeviceToHost));
   return NS_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+int ns_tune_get(ns_solver* s, int* v) {
+  if (!s || !v) return NS_ERR_ARG;
+  for (int i = 0; i < NS_NTUNE; ++i) v[i] = s->rb.variant[i];
+  return NS_OK;
+}
+
+int ns_tune_set(ns_solver* s, const int* v) {
+  if (!s || !v) return NS_ERR_ARG;
+  for (int i = 0; i < NS_NTUNE; ++i) {
+    const int nv = i == 2 ? nsk::NVARIANT_ROW : nsk::NVARIANT_COL;
+    if (v[i] < 0 || v[i] >= nv) return NS_ERR_ARG;
+  }
+  for (int i = 0; i < NS_NTUNE; ++i) s->rb.variant[i] = v[i];
+  if (s->gexec) {                              // captured with the old launches
+    (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+  }
+  return NS_OK;
+}
+
+int ns_autotune(ns_solver* s, int reps, double* ms_host) {
+  if (!s || reps < 1) return NS_ERR_ARG;
+  if (!s->have_state) return NS_ERR_STATE;
+  if (ms_host)
+    for (int i = 0; i < NS_NTUNE * 4; ++i) ms_host[i] = 0.0;
+  if (s->g.dim != 3) return NS_OK;
+  const bool was_on = s->prof_on;
+  int rc = NS_OK;
+  for (int p = 0; p < NS_NTUNE && !rc; ++p) {
+    const int nv = p == 2 ? nsk::NVARIANT_ROW : nsk::NVARIANT_COL;
+    double best = 1e300;
+    int best_v = s->rb.variant[p];
+    for (int v = 0; v < nv && !rc; ++v) {
+      s->rb.variant[p] = v;
+      rc = rhs(s, s->u, s->k[7]);               // warm-up (and first-launch costs)
+      if (rc) break;
+      rc = ns_profile_start(s);
+      for (int r = 0; r < reps && !rc; ++r) rc = rhs(s, s->u, s->k[7]);
+      ns_kernel_times kt;
+      const int rc2 = ns_profile_stop(s, &kt);
+      if (rc || rc2) {
+        rc = rc ? rc : rc2;
+        break;
+      }
+      const double ms = kt.count[p] ? kt.ms[p] / (double)kt.count[p] : 1e300;
+      if (ms_host) ms_host[p * 4 + v] = ms;
+      if (ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    s->rb.variant[p] = best_v;
+  }
+  if (was_on) (void)ns_profile_start(s);
+  if (s->gexec) {
+    (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+  }
+  return rc;
 }
 
 // ---------------------------------------------------------------- timing

@@ -37,7 +37,9 @@ struct RhsBufs {
   void* a2;           // after the second inverse pass
   HookFn hook;        // may be null
   void* hook_ctx;
+  int variant[5];     // launch variant of each 3D pass (the autotuner's choice)
 };
+constexpr int NVARIANT_COL = 4, NVARIANT_ROW = 2;
 
 // k = f(U) on compact FP64 buffers for every member (3D: rhs3d.hip,
 // 2D: rhs2d.hip).  tw: table of TWN twiddles in the rhs precision.

@@ -23,6 +23,8 @@
 //   A2 [m][6][z][y][kx]     written by P2, read by P3 (rows (z, y))
 //   A3 [m][3][y][z][kx]     written by P3 (reuses A1), read by P4 (columns (z, kx))
 //   A4 [m][3][z][ky'][kx]   written by P4 (reuses A2), read by P5 (columns (ky', kx))
+#include <type_traits>
+
 #include "pass_common.hpp"
 
 namespace nsk {
@@ -33,14 +35,14 @@ static_assert(TWN == TWN_TABLE, "twiddle table length");
 // Logical block id = (member, column tile, field) with the field fastest: the
 // six blocks of one tile run on one XCD back to back and read u_hat once from
 // HBM, the rest from L2.
-template <class PL, typename T>
-__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_zinv(const double2* __restrict__ U,
+template <class PL, typename T, int CW>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const double2* __restrict__ U,
                                                              cplx<T>* __restrict__ A1, Geom g,
                                                              long long nblocks,
                                                              const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<PL, T>;
+  using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
   const long long L = xcd_logical(blockIdx.x, gridDim.x);
@@ -110,13 +112,13 @@ __global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_zinv(const double2* __r
 
 // ---------------------------------------------------------------- P2
 // Columns (z, kx) of one (member, field): 2K+1 non-zero ky' -> N values of y.
-template <class PL, typename T>
-__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
+template <class PL, typename T, int CW>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
                                                              cplx<T>* __restrict__ A2, Geom g,
                                                              const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<PL, T>;
+  using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
   const long long bf = blockIdx.y;                // member * 6 + field
@@ -255,13 +257,13 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
 
 // ---------------------------------------------------------------- P4
 // Columns (z, kx) of one (member, component): N values of y -> 2K+1 retained ky.
-template <class PL, typename T>
-__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3,
+template <class PL, typename T, int CW>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3,
                                                              cplx<T>* __restrict__ A4, Geom g,
                                                              const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<PL, T>;
+  using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
   const long long bc = blockIdx.y;                // member * 3 + component
@@ -287,15 +289,15 @@ __global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_yfwd(const cplx<T>* __r
 }
 
 // ---------------------------------------------------------------- P5
-template <class PL, typename T>
-__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_zfwd(const cplx<T>* __restrict__ A4,
+template <class PL, typename T, int CW>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>* __restrict__ A4,
                                                            const double2* __restrict__ U,
                                                            double2* __restrict__ Kout, Geom g,
                                                            const double* __restrict__ nu,
                                                            const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<PL, T>;
+  using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
@@ -348,58 +350,109 @@ __global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k_zfwd(const cplx<T>* __r
 }
 
 // ---------------------------------------------------------------- host side
-// Radix plan of each pass (registers vs. passes, tuned per pass).
-template <int N> struct Plans3 {
-  using zinv = Plan<N>;
-  using yinv = Plan<N>;
-  using xpass = Plan<N>;
-  using yfwd = Plan<N>;
-  using zfwd = Plan<N>;
+// Launch variants of each pass, chosen at run time (the autotuner times them
+// on the live workspace): column passes 0 wide plan / 16 columns, 1 wide /
+// 32, 2 narrow plan / 16, 3 narrow / 32; x-pass 0 wide, 1 narrow.  Sizes
+// below 64 always use variant 0.
+template <int N, int V> struct ColVar {
+  using PL = typename std::conditional<(V >= 2 && N >= 64), PlanS<N>, Plan<N>>::type;
+  static constexpr int CW = (V & 1) && N >= 64 ? 32 : 16;
 };
+
+#define NSK_MARK(id, ph) \
+  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph)
+
+template <int N, typename T, int V>
+static void launch_zinv(const Geom& g, const double2* U, cplx<T>* A1, const cplx<T>* tw, hipStream_t st) {
+  using CV = ColVar<N, V>;
+  using CF = ColCfg<typename CV::PL, T, CV::CW>;
+  const int ncol = g.Kf * g.Kx;
+  const long long nb = (long long)g.batch * 6 * ((ncol + CF::C - 1) / CF::C);
+  const long long nbp = (nb + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_zinv<typename CV::PL, T, CV::CW>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, U, A1, g,
+                     nb, tw);
+}
+template <int N, typename T, int V>
+static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2, const cplx<T>* tw, hipStream_t st) {
+  using CV = ColVar<N, V>;
+  using CF = ColCfg<typename CV::PL, T, CV::CW>;
+  const int nkx = N * g.Kx;
+  hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), dim3((nkx + CF::C - 1) / CF::C, g.batch * 6),
+                     dim3(CF::NT), 0, st, A1, A2, g, tw);
+}
+template <int N, typename T, int V>
+static void launch_xpass(const Geom& g, const cplx<T>* A2, cplx<T>* A3, const cplx<T>* tw, hipStream_t st) {
+  using PL = typename std::conditional<(V == 1 && N >= 64), PlanS<N>, Plan<N>>::type;
+  using RC = RowCfg<PL, T>;
+  const long long rows = (long long)g.batch * N * N;
+  hipLaunchKernelGGL((k_xpass<PL, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)), dim3(RC::NT), 0, st,
+                     A2, A3, g, rows, tw);
+}
+template <int N, typename T, int V>
+static void launch_yfwd(const Geom& g, const cplx<T>* A3, cplx<T>* A4, const cplx<T>* tw, hipStream_t st) {
+  using CV = ColVar<N, V>;
+  using CF = ColCfg<typename CV::PL, T, CV::CW>;
+  const int nkx = N * g.Kx;
+  hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), dim3((nkx + CF::C - 1) / CF::C, g.batch * 3),
+                     dim3(CF::NT), 0, st, A3, A4, g, tw);
+}
+template <int N, typename T, int V>
+static void launch_zfwd(const Geom& g, const cplx<T>* A4, const double2* U, double2* K, const double* nu,
+                        const cplx<T>* tw, hipStream_t st) {
+  using CV = ColVar<N, V>;
+  using CF = ColCfg<typename CV::PL, T, CV::CW>;
+  const int ncol = g.Kf * g.Kx;
+  hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch),
+                     dim3(CF::NT), 0, st, A4, U, K, g, nu, tw);
+}
 
 template <int N, typename T>
 static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
                         const RhsBufs& bufs, const void* twv, hipStream_t st) {
   using V = cplx<T>;
-  using PS = Plans3<N>;
-  using C1 = ColCfg<typename PS::zinv, T>;
-  using C2 = ColCfg<typename PS::yinv, T>;
-  using RC = RowCfg<typename PS::xpass, T>;
-  using C4 = ColCfg<typename PS::yfwd, T>;
-  using C5 = ColCfg<typename PS::zfwd, T>;
   const V* tw = (const V*)twv;
   V* A1 = (V*)bufs.a1;
   V* A2 = (V*)bufs.a2;
-  const int ncol = g.Kf * g.Kx;
-  const int nkx = N * g.Kx;
-#define NSK_MARK(id, ph) \
-  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph)
-  const long long nb1 = (long long)g.batch * 6 * ((ncol + C1::C - 1) / C1::C);
-  const long long nb1p = (nb1 + 7) / 8 * 8;
+  const int* tv = bufs.variant;
   NSK_MARK(PROF_P1, 0);
-  hipLaunchKernelGGL((k_zinv<typename PS::zinv, T>), dim3((unsigned)nb1p), dim3(C1::NT), 0, st, U, A1, g,
-                     nb1, tw);
+  switch (tv[0]) {
+    case 1: launch_zinv<N, T, 1>(g, U, A1, tw, st); break;
+    case 2: launch_zinv<N, T, 2>(g, U, A1, tw, st); break;
+    case 3: launch_zinv<N, T, 3>(g, U, A1, tw, st); break;
+    default: launch_zinv<N, T, 0>(g, U, A1, tw, st);
+  }
   NSK_MARK(PROF_P1, 1);
   NSK_MARK(PROF_P2, 0);
-  hipLaunchKernelGGL((k_yinv<typename PS::yinv, T>), dim3((nkx + C2::C - 1) / C2::C, g.batch * 6),
-                     dim3(C2::NT), 0, st, A1, A2, g, tw);
+  switch (tv[1]) {
+    case 1: launch_yinv<N, T, 1>(g, A1, A2, tw, st); break;
+    case 2: launch_yinv<N, T, 2>(g, A1, A2, tw, st); break;
+    case 3: launch_yinv<N, T, 3>(g, A1, A2, tw, st); break;
+    default: launch_yinv<N, T, 0>(g, A1, A2, tw, st);
+  }
   NSK_MARK(PROF_P2, 1);
-  const long long rows = (long long)g.batch * N * N;
   NSK_MARK(PROF_P3, 0);
-  hipLaunchKernelGGL((k_xpass<typename PS::xpass, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
-                     dim3(RC::NT), 0, st, A2, A1, g, rows, tw);
+  if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2, A1, tw, st);
+  else launch_xpass<N, T, 0>(g, A2, A1, tw, st);
   NSK_MARK(PROF_P3, 1);
   NSK_MARK(PROF_P4, 0);
-  hipLaunchKernelGGL((k_yfwd<typename PS::yfwd, T>), dim3((nkx + C4::C - 1) / C4::C, g.batch * 3),
-                     dim3(C4::NT), 0, st, A1, A2, g, tw);
+  switch (tv[3]) {
+    case 1: launch_yfwd<N, T, 1>(g, A1, A2, tw, st); break;
+    case 2: launch_yfwd<N, T, 2>(g, A1, A2, tw, st); break;
+    case 3: launch_yfwd<N, T, 3>(g, A1, A2, tw, st); break;
+    default: launch_yfwd<N, T, 0>(g, A1, A2, tw, st);
+  }
   NSK_MARK(PROF_P4, 1);
   NSK_MARK(PROF_P5, 0);
-  hipLaunchKernelGGL((k_zfwd<typename PS::zfwd, T>), dim3((ncol + C5::C - 1) / C5::C, g.batch),
-                     dim3(C5::NT), 0, st, A2, U, K, g, p.nu, tw);
+  switch (tv[4]) {
+    case 1: launch_zfwd<N, T, 1>(g, A2, U, K, p.nu, tw, st); break;
+    case 2: launch_zfwd<N, T, 2>(g, A2, U, K, p.nu, tw, st); break;
+    case 3: launch_zfwd<N, T, 3>(g, A2, U, K, p.nu, tw, st); break;
+    default: launch_zfwd<N, T, 0>(g, A2, U, K, p.nu, tw, st);
+  }
   NSK_MARK(PROF_P5, 1);
-#undef NSK_MARK
   return hipGetLastError();
 }
+#undef NSK_MARK
 
 template <typename T>
 static hipError_t dispatch3d(const Geom& g, const double2* U, double2* K, const RhsParams& p,

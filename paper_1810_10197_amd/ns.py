@@ -40,7 +40,9 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_set_time", "ns_diagnostics", "ns_refresh_rhs", "ns_mlp_set_weights",
            "ns_mlp_get_weights", "ns_mlp_forward", "ns_mlp_grad", "ns_mlp_train_batch",
            "ns_mlp_reset_optimizer", "ns_mlp_collect", "ns_mlp_rows", "ns_mlp_fit_stats",
-           "ns_mlp_train", "ns_profile_start", "ns_profile_stop", "ns_strerror", "ns_free"]
+           "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
+           "ns_profile_stop", "ns_strerror", "ns_free"]
+NS_NTUNE = 5
 PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other"]
 
 
@@ -97,6 +99,9 @@ _sig = {
     "ns_mlp_rows": (_I, [_P, _FP, _FP, _I, ctypes.POINTER(ctypes.c_longlong)]),
     "ns_mlp_fit_stats": (_I, [_P]),
     "ns_mlp_train": (_I, [_P, _I, _I, ctypes.c_float, ctypes.c_ulonglong, _FP]),
+    "ns_autotune": (_I, [_P, _I, _DP]),
+    "ns_tune_get": (_I, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "ns_tune_set": (_I, [_P, ctypes.POINTER(ctypes.c_int)]),
     "ns_profile_start": (_I, [_P]),
     "ns_profile_stop": (_I, [_P, ctypes.POINTER(NsKernelTimes)]),
     "ns_strerror": (ctypes.c_char_p, [_I]),
@@ -242,6 +247,21 @@ def ns_mlp_fit_stats(h):
 def ns_mlp_train(h, iters, batch, lr, seed, loss_out):
     return _check(_lib.ns_mlp_train(h, int(iters), int(batch), float(lr), int(seed),
                                     _fptr(loss_out)), "ns_mlp_train")
+
+
+def ns_autotune(h, reps, ms_out):
+    return _check(_lib.ns_autotune(h, int(reps), _dptr(ms_out)), "ns_autotune")
+
+
+def ns_tune_get(h):
+    v = (ctypes.c_int * NS_NTUNE)()
+    _check(_lib.ns_tune_get(h, v), "ns_tune_get")
+    return list(v)
+
+
+def ns_tune_set(h, variants):
+    v = (ctypes.c_int * NS_NTUNE)(*[int(x) for x in variants])
+    return _check(_lib.ns_tune_set(h, v), "ns_tune_set")
 
 
 def ns_profile_start(h):
@@ -405,6 +425,18 @@ class Solver:
 
     def refresh_rhs(self):
         ns_refresh_rhs(self.handle)
+
+    def autotune(self, reps=3):
+        """Pick the fastest launch variant of each pass; returns
+        (variants, ms[pass][variant])."""
+        ms = np.zeros(NS_NTUNE * 4)
+        ns_autotune(self.handle, reps, ms)
+        return ns_tune_get(self.handle), ms.reshape(NS_NTUNE, 4)
+
+    def tune(self, variants=None):
+        if variants is not None:
+            ns_tune_set(self.handle, variants)
+        return ns_tune_get(self.handle)
 
     def profile_start(self):
         ns_profile_start(self.handle)

@@ -61,14 +61,14 @@ def test_ensemble_members_equal_single_runs(ns):
     fields, nus = inputs.ensemble_members(B, n)
     sb = ns.Solver(dim=3, n=n, batch=B, nu=nus, rhs_precision="fp32")
     sb.set_state(fields)
-    stats = sb.integrate(0.3, 0.05, 1e-7, 1e-7)
+    stats = sb.integrate(0.3, 0.05, 1e-11, 1e-11)
     ub = sb.get_state().cpu().numpy()
     sb.close()
     assert len({st["h_next"] for st in stats}) == B     # every member has its own steps
     for m in range(B):
         s1 = ns.Solver(dim=3, n=n, nu=nus[m], rhs_precision="fp32")
         s1.set_state(fields[m][None])
-        st1 = s1.integrate(0.3, 0.05, 1e-7, 1e-7)[0]
+        st1 = s1.integrate(0.3, 0.05, 1e-11, 1e-11)[0]
         u1 = s1.get_state().cpu().numpy()[0]
         s1.close()
         assert (st1["n_accept"], st1["n_reject"], st1["n_rhs"]) == \
