@@ -24,6 +24,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rhs256_fp32_hbm_traffic.txt")
+TRAFFIC_SOURCES = ["fft_core.hpp", "pass_common.hpp", "rhs3d.hip"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None when the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1810_10197_amd", "csrc", f), "rb").read())
+    text = open(TRAFFIC_FILE).read().splitlines()
+    sha = [l.split()[1] for l in text if l.startswith("source_sha256:")]
+    if not sha or sha[0] != h.hexdigest()[:16]:
+        return None
+    for l in text:
+        parts = l.split()
+        if len(parts) == 3 and parts[0] == "traffic_bytes" and parts[1] == kernel:
+            return float(parts[2])
+    return None
 
 
 def pass_bytes(n, fp64=False):
@@ -75,6 +98,10 @@ def main():
     ap.add_argument("--dt", type=float, default=0.005)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated launch variants of the 5 passes (skips the autotuner)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -82,13 +109,27 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy * 1024 * 1024
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}))
+        return
     from paper_1810_10197_amd import inputs, ns
 
     n, nu = args.n, 1.0 / 1600
     atol = rtol = 1e-6
     s = ns.Solver(dim=3, n=n, batch=1, nu=nu, rhs_precision=args.prec)
     s.set_state(inputs.tgv3d(n)[None])
-    tune_variants, tune_ms = s.autotune(reps=3)
+    if args.variants:
+        tune_variants = s.tune([int(v) for v in args.variants.split(",")])
+        tune_ms = __import__("numpy").zeros((5, 4))
+    else:
+        tune_variants, tune_ms = s.autotune(reps=3)
     for _ in range(args.warmup):
         s.step_bs5(args.dt, atol, rtol)
     # pure right-hand-side rate (context): f(u_n) into the cached stage
@@ -145,7 +186,9 @@ def main():
                                "h=%g, atol=rtol=1e-6, %s FFTs, FP64 state" % (n, args.dt, args.prec),
                    "n": n, "batch": 1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom) if (n == 256 and not fp64) else None,
+                     "kernel": dom},
         "rhs_model_gb": model_bytes / 1e9,
         "rhs_passes_ms": rhs_ms,
         "rhs_model_gbs": model_bytes / (rhs_ms * 1e-3) / 1e9,
