@@ -16,6 +16,7 @@ right-hand side at the same size on the host, on a bounded sample.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -88,6 +89,217 @@ def cpu_baseline(n, nu, budget_s):
                       "(%.1f s; numpy.fft is single-threaded)" % (count, n, dt)}
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _initial_weights(ns, seed):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    w0 = np.zeros(ns.NS_MLP_NWEIGHTS, dtype=np.float32)
+    lim1, lim2, lim3 = np.sqrt(6.0 / 84), np.sqrt(6.0 / 128), np.sqrt(6.0 / 65)
+    w0[:1280] = rng.uniform(-lim1, lim1, 1280)                 # W1 (64 x 20)
+    w0[1344:1344 + 4096] = rng.uniform(-lim2, lim2, 4096)      # W2 (64 x 64)
+    w0[5504:5568] = rng.uniform(-lim3, lim3, 64)               # W3 (1 x 64)
+    w0[ns.NS_MLP_NPARAM + 20:] = 1.0                           # feature scale
+    return w0
+
+
+def collect_rows(ns, fields, nus, n, t_end, tols, h0=1e-3, chunks=1):
+    """(features, label) rows of accepted steps of Sec. 2.2.1-controlled
+    runs of the given members (FP32 right-hand side)."""
+    import numpy as np
+    import torch
+    B = len(nus)
+    s = ns.Solver(dim=3, n=n, batch=B, nu=nus, rhs_precision="fp32")
+    s.mlp_set_weights(np.zeros(ns.NS_MLP_NWEIGHTS, dtype=np.float32))
+    s.mlp_collect(True)
+    nrhs = 0
+    t0 = time.perf_counter()
+    for tol in tols:
+        s.set_state(fields)
+        s.set_time(np.zeros(B))
+        torch.cuda.synchronize()
+        h = h0
+        for c in range(chunks):
+            st = s.integrate(t_end * (c + 1) / chunks, h, tol, tol)
+            h = float(np.min([x["h_next"] for x in st]))
+            nrhs += sum(x["n_rhs"] for x in st)
+        log("collect n=%d B=%d tol=%g: %d rows" % (n, B, tol, s.mlp_rows(0)[2]))
+    x, y, _ = s.mlp_rows()
+    s.close()
+    return x, y, nrhs, time.perf_counter() - t0
+
+
+def train_proposer(ns, inputs, members=128, n=64, t_end=2.0, tols=(1e-5, 1e-7, 1e-9),
+                   iters=3000, batch=256, seed=1810, target=None):
+    """Proposer training: rows from the mixed ensemble (Taylor-Green and
+    random-phase fields, nu log-uniform in [1e-3, 1e-2]) integrated with the
+    Sec. 2.2.1 controller at several tolerances, plus (target = (n_list,
+    nu, T, tols)) runs of the target problem at reduced resolution; then Adam
+    on the GPU.  Returns (weights, info)."""
+    import numpy as np
+    fields, nus = inputs.ensemble_members(members, n)
+    xs, ys, nrhs, secs = collect_rows(ns, fields, nus, n, t_end, tols)
+    info = {"ensemble": {"members": members, "n": n, "t_end": t_end, "tolerances": list(tols),
+                         "rows": int(len(ys)), "member_rhs_evals": nrhs, "collect_s": secs,
+                         "member_rhs_per_s": nrhs / secs}}
+    X, Y = [xs], [ys]
+    if target:
+        tn, tnu, tT, ttols = target
+        for nn in tn:
+            x2, y2, r2, s2 = collect_rows(ns, inputs.tgv3d(nn)[None], [tnu], nn, tT, ttols,
+                                          chunks=int(math.ceil(tT)))
+            X.append(x2)
+            Y.append(y2)
+            info["target_n%d" % nn] = {"rows": int(len(y2)), "collect_s": s2}
+    X = np.concatenate(X)
+    Y = np.concatenate(Y)
+    s = ns.Solver(dim=3, n=8, nu=0.01, rhs_precision="fp32")
+    s.mlp_set_weights(_initial_weights(ns, seed))
+    s.mlp_push_rows(X, Y)
+    s.mlp_fit_stats()
+    t1 = time.perf_counter()
+    loss0 = s.mlp_train(1, batch, 1e-3, seed)
+    loss = loss0
+    for k in range(iters // 500):
+        loss = s.mlp_train(500, batch, 1e-3, seed + 1 + k)
+        log("train iter %d loss %.5f" % ((k + 1) * 500, loss))
+    w = s.mlp_get_weights()
+    s.close()
+    info.update({"rows": int(len(Y)), "train_iters": iters, "train_s": time.perf_counter() - t1,
+                 "loss_first": loss0, "loss_last": loss})
+    return w, info
+
+
+def study_mlp(args):
+    """What the trained proposer gains: held-out ensemble members integrated
+    with the Sec. 2.2.1 controller and with the proposer, same tolerance;
+    rejections, right-hand sides, wall time and final-state error against a
+    tight-tolerance run."""
+    import numpy as np
+    import torch
+    from paper_1810_10197_amd import inputs, ns
+    w, info = train_proposer(ns, inputs, members=args.members, n=64, iters=args.iters)
+    n, B = 64, 32
+    fields, nus = inputs.ensemble_members(B + args.members, n)
+    fields, nus = fields[args.members:], nus[args.members:]       # held out
+    res = {"training": info}
+    ref = ns.Solver(dim=3, n=n, batch=B, nu=nus, rhs_precision="fp64")
+    ref.set_state(fields)
+    ref.integrate(2.0, 1e-3, 1e-12, 1e-12)
+    uref = ref.get_state().cpu().numpy()
+    ref.close()
+    for tol in (1e-5, 1e-7):
+        for ctl in ("pi", "mlp"):
+            s = ns.Solver(dim=3, n=n, batch=B, nu=nus, rhs_precision="fp32")
+            s.mlp_set_weights(w)
+            s.set_state(fields)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.integrate(2.0, 1e-3, tol, tol, controller=ctl)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            u = s.get_state().cpu().numpy()
+            s.close()
+            err = float(np.max(np.linalg.norm((u - uref).reshape(B, -1), axis=1) /
+                               np.linalg.norm(uref.reshape(B, -1), axis=1)))
+            res["%s_tol%g" % (ctl, tol)] = {
+                "n_rhs": int(sum(x["n_rhs"] for x in st)),
+                "n_accept": int(sum(x["n_accept"] for x in st)),
+                "n_reject": int(sum(x["n_reject"] for x in st)),
+                "wall_s": dt, "max_rel_l2_err": err}
+            log("%s tol=%g: %s" % (ctl, tol, res["%s_tol%g" % (ctl, tol)]))
+    np.save(os.path.join(ROOT, "gpurun_out", "proposer_weights.npy"), w) \
+        if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    print(json.dumps({"study": "proposer_gain", "results": res}))
+
+
+def study_tts(args):
+    """Wall time to a fixed relative energy error at T on the Taylor-Green
+    vortex (nu = 1/1600): plain FP64 RK4 at fixed steps (the last one clipped
+    to land on T) versus BS5 (FP64 state; FP32 and FP64 right-hand sides) with
+    the Sec. 2.2.1 controller and with the trained proposer.  E_ref(T) from
+    FP64 RK4 at dt = 1e-3."""
+    import numpy as np
+    import torch
+    from paper_1810_10197_amd import inputs, ns
+    n, T, nu = args.n, args.t_end, 1.0 / 1600
+    u0 = inputs.tgv3d(n)[None]
+    out = {"study": "time_to_solution", "n": n, "T": T, "nu": nu}
+
+    def rk4_run(dt, prec):
+        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision=prec)
+        s.set_state(u0)
+        steps = max(1, int(math.ceil(T / dt - 1e-9)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s.step_rk4(dt if i < steps - 1 else T - (steps - 1) * dt)
+            if (i + 1) % 1000 == 0:
+                log("rk4 %s dt=%g step %d/%d" % (prec, dt, i + 1, steps))
+        e, _, _ = s.diagnostics()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.close()
+        return float(e[0]), wall, 4 * steps
+
+    eref, wref, _ = rk4_run(1e-3, "fp64")
+    out["E_ref"] = eref
+    out["ref_wall_s"] = wref
+    log("E_ref(T=%g) = %.15e (%.1f s)" % (T, eref, wref))
+    out["rk4_fp64"] = []
+    for dt in args.rk4_dts:
+        e, wall, nr = rk4_run(dt, "fp64")
+        rel = abs(e - eref) / eref
+        out["rk4_fp64"].append({"dt": dt, "rel_energy_err": rel, "wall_s": wall, "n_rhs": nr})
+        log("rk4 fp64 dt=%g err %.3e wall %.2f s" % (dt, rel, wall))
+    w = None
+    if args.weights and os.path.exists(args.weights):
+        w = np.load(args.weights)
+    if w is None:
+        w, info = train_proposer(ns, inputs, iters=args.iters, members=args.members,
+                                 target=((64, 128), nu, T, (1e-7, 1e-8, 1e-9, 1e-10)))
+        out["proposer_training"] = info
+        if args.weights:
+            np.save(args.weights, w)
+    arms = [(c, p) for p in args.bs5_precs for c in ("pi", "mlp")]
+    for ctl, prec in arms:
+        key = "bs5_%s_%s" % (ctl, prec)
+        out[key] = []
+        for tol in args.tols:
+            s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision=prec)
+            s.mlp_set_weights(w)
+            s.set_state(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            # unit-time chunks, each continuing with the step the controller
+            # proposed at the end of the previous one (progress lines between)
+            h, tot = 1e-3, {"n_rhs": 0, "n_accept": 0, "n_reject": 0}
+            nchunk = int(math.ceil(T - 1e-12))
+            for c in range(nchunk):
+                st = s.integrate(min(T, c + 1.0), h, tol, tol, controller=ctl)[0]
+                h = st["h_next"]
+                for k in tot:
+                    tot[k] += st[k]
+                log("%s tol=%g t=%g rhs %d rej %d" % (ctl, tol, st["t"], tot["n_rhs"], tot["n_reject"]))
+            e, _, _ = s.diagnostics()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            s.close()
+            rel = abs(float(e[0]) - eref) / eref
+            out[key].append({"tol": tol, "rel_energy_err": rel, "wall_s": wall, **tot})
+            log("%s tol=%g err %.3e wall %.2f s rhs %d rej %d" % (key, tol, rel, wall, tot["n_rhs"],
+                                                                 tot["n_reject"]))
+
+    def cheapest(runs, target):
+        ok = [r for r in runs if r["rel_energy_err"] <= target]
+        return min(ok, key=lambda r: r["wall_s"]) if ok else None
+    out["target"] = args.target
+    out["best"] = {k: cheapest(out[k], args.target) for k in ["rk4_fp64"] + ["bs5_%s_%s" % a for a in arms]}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,13 +314,28 @@ def main():
                     help="comma-separated launch variants of the 5 passes (skips the autotuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter scale)")
+    ap.add_argument("--study", choices=["tts", "mlp"], default=None,
+                    help="tts: wall time to a fixed energy error, BS5 (+proposer) vs FP64 RK4; "
+                         "mlp: what the trained proposer gains on held-out ensemble members")
+    ap.add_argument("--t-end", type=float, default=10.0)
+    ap.add_argument("--target", type=float, default=1e-6)
+    ap.add_argument("--rk4-dts", type=float, nargs="*", default=[0.02, 0.01, 0.005, 0.0025])
+    ap.add_argument("--tols", type=float, nargs="*", default=[1e-4, 1e-5, 1e-6, 1e-7, 1e-8])
+    ap.add_argument("--weights", default=None, help="proposer weights (.npy) for --study tts")
+    ap.add_argument("--bs5-precs", nargs="*", default=["fp32", "fp64"])
+    ap.add_argument("--members", type=int, default=128)
+    ap.add_argument("--iters", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solver would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.study == "tts":
+        return study_tts(args)
+    if args.study == "mlp":
+        return study_mlp(args)
     if args.calibrate_copy:
         nbytes = args.calibrate_copy * 1024 * 1024
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

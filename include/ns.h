@@ -189,6 +189,9 @@ int ns_mlp_collect(ns_solver* s, int enable);
 /* Number of rows recorded (host); copies min(count, capacity, max_rows) rows
  * to x_host[.][20] / y_host[.] when they are not NULL. */
 int ns_mlp_rows(ns_solver* s, float* x_host, float* y_host, int max_rows, long long* count_host);
+/* Append n rows (host x_host[n][20], y_host[n]) to the ring, e.g. rows
+ * recorded by other solvers. */
+int ns_mlp_push_rows(ns_solver* s, const float* x_host, const float* y_host, int n);
 /* Set the feature mean and scale from the recorded rows. */
 int ns_mlp_fit_stats(ns_solver* s);
 /* iters Adam steps on minibatches of `batch` recorded rows drawn with

@@ -816,6 +816,23 @@ int ns_mlp_rows(ns_solver* s, float* x_host, float* y_host, int max_rows, long l
   return NS_OK;
 }
 
+int ns_mlp_push_rows(ns_solver* s, const float* x_host, const float* y_host, int n) {
+  if (!s || !x_host || !y_host || n < 0) return NS_ERR_ARG;
+  long long cnt = 0;
+  int rc = ring_count(s, &cnt);
+  if (rc) return rc;
+  for (long long i = 0; i < n;) {                // contiguous runs up to the ring's end
+    const long long slot = (cnt + i) % RING_CAP;
+    const long long len = (n - i) < (RING_CAP - slot) ? (n - i) : (RING_CAP - slot);
+    NS_HIP(hipMemcpy(s->ring_x + slot * 20, x_host + i * 20, sizeof(float) * 20 * len, hipMemcpyHostToDevice));
+    NS_HIP(hipMemcpy(s->ring_y + slot, y_host + i, sizeof(float) * len, hipMemcpyHostToDevice));
+    i += len;
+  }
+  cnt += n;
+  NS_HIP(hipMemcpy(s->ring_n, &cnt, 8, hipMemcpyHostToDevice));
+  return NS_OK;
+}
+
 int ns_mlp_fit_stats(ns_solver* s) {
   if (!s) return NS_ERR_ARG;
   long long cnt = 0;

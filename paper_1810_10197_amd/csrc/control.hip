@@ -7,9 +7,10 @@
 //   fac = 0.8 err^(-1/5) clamped to [0.01, dmax], dmax = 1 if the attempt
 //         is accepted right after a rejection, 2 otherwise; err = 0 gives dmax
 //   accept iff err <= 1; the next step is hc * fac, or with the learned
-//   proposer (after an accepted step) hc * clamp(exp(y), 0.01, dmax)
+//   proposer (after an accepted step) hc * clamp(exp(y), fac/2, min(2 fac, dmax)),
+//   so the controller stays the fallback when the proposer is wrong
 //   the next attempt is clipped to land on t_end; 50 consecutive
-//   rejections stop the member.
+//   rejections, or a step too small to advance t, stop the member.
 #include "ns_internal.hpp"
 
 namespace nsk {
@@ -56,9 +57,12 @@ __global__ void k_control(CtlState c, const double* __restrict__ red, double M, 
     if (use_mlp) {
       const float y = mlp_y[m];
       if (isfinite(y)) {
+        // the controller's own factor bounds the proposal: [fac/2, min(2 fac, dmax)]
+        const double fac = step_factor_dev(err, prev_rej);
+        const double dmax = prev_rej ? 1.0 : 2.0;
+        const double lo = 0.5 * fac, hi = 2.0 * fac < dmax ? 2.0 * fac : dmax;
         double g = exp((double)y);
-        const double gmax = prev_rej ? 1.0 : 2.0;
-        g = g < 0.01 ? 0.01 : (g > gmax ? gmax : g);
+        g = g < lo ? lo : (g > hi ? hi : g);
         hnew = hc * g;
       }
     }
@@ -78,6 +82,11 @@ __global__ void k_control(CtlState c, const double* __restrict__ red, double M, 
     }
   }
   c.h[m] = hnew;
+  // a step that no longer advances t (t + h == t) can never reach t_end
+  if (!c.done[m] && !(c.t[m] + hnew > c.t[m])) {
+    c.done[m] = 1;
+    c.fail[m] = 1;
+  }
   if (!c.done[m]) {
     const int last = hnew >= t_end - c.t[m];
     c.last[m] = last;

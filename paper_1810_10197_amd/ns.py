@@ -39,7 +39,8 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_rhs", "ns_step_rk4", "ns_step_bs5", "ns_integrate", "ns_get_time",
            "ns_set_time", "ns_diagnostics", "ns_refresh_rhs", "ns_mlp_set_weights",
            "ns_mlp_get_weights", "ns_mlp_forward", "ns_mlp_grad", "ns_mlp_train_batch",
-           "ns_mlp_reset_optimizer", "ns_mlp_collect", "ns_mlp_rows", "ns_mlp_fit_stats",
+           "ns_mlp_reset_optimizer", "ns_mlp_collect", "ns_mlp_rows", "ns_mlp_push_rows",
+           "ns_mlp_fit_stats",
            "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
            "ns_profile_stop", "ns_strerror", "ns_free"]
 NS_NTUNE = 5
@@ -97,6 +98,7 @@ _sig = {
     "ns_mlp_reset_optimizer": (_I, [_P]),
     "ns_mlp_collect": (_I, [_P, _I]),
     "ns_mlp_rows": (_I, [_P, _FP, _FP, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "ns_mlp_push_rows": (_I, [_P, _FP, _FP, _I]),
     "ns_mlp_fit_stats": (_I, [_P]),
     "ns_mlp_train": (_I, [_P, _I, _I, ctypes.c_float, ctypes.c_ulonglong, _FP]),
     "ns_autotune": (_I, [_P, _I, _DP]),
@@ -238,6 +240,12 @@ def ns_mlp_rows(h, x_out, y_out, max_rows):
     _check(_lib.ns_mlp_rows(h, _fptr(x_out), _fptr(y_out), int(max_rows), ctypes.byref(cnt)),
            "ns_mlp_rows")
     return cnt.value
+
+
+def ns_mlp_push_rows(h, x, y):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    return _check(_lib.ns_mlp_push_rows(h, _fptr(x), _fptr(y), int(y.size)), "ns_mlp_push_rows")
 
 
 def ns_mlp_fit_stats(h):
@@ -399,6 +407,9 @@ class Solver:
         if n:
             ns_mlp_rows(self.handle, x, y, n)
         return x, y, cnt
+
+    def mlp_push_rows(self, x, y):
+        ns_mlp_push_rows(self.handle, x, y)
 
     def mlp_fit_stats(self):
         ns_mlp_fit_stats(self.handle)

@@ -89,17 +89,19 @@ def test_adam_step_matches_oracle(solver):
     assert np.abs(got - pref).max() <= 2e-5
 
 
-def test_mlp_controller_matches_oracle_proposer(ns):
-    """Network with W = 0 and b3 = log(1.5): after every accepted step the
-    next step is 1.5 h (1 h right after a rejection)."""
+@pytest.mark.parametrize("b3", [math.log(1.5), -5.0, 5.0])
+def test_mlp_controller_matches_oracle_proposer(ns, b3):
+    """Network with W = 0 and output bias b3: after every accepted step the
+    proposal is exp(b3), clamped around the controller's factor (the large
+    |b3| cases run on the bounds)."""
     n, nu = 16, 0.01
-    announce("mlp controller n=%d" % n)
+    announce("mlp controller n=%d b3=%g" % (n, b3))
     w = np.zeros(ns.NS_MLP_NWEIGHTS, dtype=np.float32)
-    w[mlp.NPARAM - 1] = math.log(1.5)
+    w[mlp.NPARAM - 1] = b3
     w[mlp.NPARAM + 20:] = 1.0
     u0 = inputs.random_isotropic(n, 12)
     rhs = lambda u: spectral.rhs_ns3d(u, nu)
-    y = float(np.float32(math.log(1.5)))
+    y = float(np.float32(b3))
     ref = control.integrate(rhs, u0, 0.6, 0.05, 1e-9, 1e-9, proposer=lambda u, h, e: y)
     s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp64")
     s.mlp_set_weights(w)
@@ -135,3 +137,18 @@ def test_collected_rows_are_pi_trajectory(ns):
     for i in range(cnt):
         assert np.abs(x[i] - rows[i][0]).max() <= 1e-5 * max(1.0, np.abs(rows[i][0]).max())
         assert y[i] == pytest.approx(math.log(rows[i + 1][1] / rows[i][1]), abs=1e-6)
+
+
+def test_pushed_rows_append_to_ring(ns):
+    """Rows pushed from the host follow the recorded ones in ring order."""
+    announce("mlp push rows")
+    rng = np.random.default_rng(5)
+    s = ns.Solver(dim=3, n=8, nu=0.01, rhs_precision="fp32")
+    x1, y1 = rng.standard_normal((37, 20)).astype(np.float32), rng.standard_normal(37).astype(np.float32)
+    x2, y2 = rng.standard_normal((5, 20)).astype(np.float32), rng.standard_normal(5).astype(np.float32)
+    s.mlp_push_rows(x1, y1)
+    s.mlp_push_rows(x2, y2)
+    x, y, cnt = s.mlp_rows()
+    s.close()
+    assert cnt == 42
+    assert np.array_equal(x, np.concatenate([x1, x2])) and np.array_equal(y, np.concatenate([y1, y2]))
