@@ -11,7 +11,9 @@
 // output comes out in natural order.
 //
 // Twiddles come from a table of exp(-2 pi i m / TWN), m < TWN, computed on
-// the host in double precision (std::cos/std::sin) and rounded once.  The
+// the host in double precision (std::cos/std::sin) and rounded once; a pass
+// with radix R loads log2(R) entries per butterfly and multiplies them
+// together for the rest (see Tw below).  The
 // radix-8/16 butterfly constants are cos/sin of multiples of pi/8, written
 // from their half-angle closed forms: cos(pi/4) = sqrt(2)/2,
 // cos(pi/8) = sqrt(2+sqrt(2))/2, sin(pi/8) = sqrt(2-sqrt(2))/2.
@@ -143,23 +145,77 @@ template <> struct PlanS<256>  : PlanT<256, 8, 3, 8, 8, 4> {};
 template <> struct PlanS<512>  : PlanT<512, 8, 3, 8, 8, 8> {};
 template <> struct PlanS<1024> : PlanT<1024, 16, 3, 16, 16, 4> {};
 
-// Butterflies of one pass on the thread's registers: radix R, span NS.
-template <int N, int E, int R, int NS, int DIR, typename V>
-__device__ __forceinline__ void pass_compute(V (&v)[E], int t, const V* __restrict__ tw) {
-  constexpr int TT = N / E;
-  constexpr int S = E / R;
+// log2 and highest set bit for 1 <= x < 32, written without recursion so that
+// they fold to constants inside unrolled loops.
+__host__ __device__ constexpr int ilog2(int x) {
+  return x >= 16 ? 4 : (x >= 8 ? 3 : (x >= 4 ? 2 : (x >= 2 ? 1 : 0)));
+}
+__host__ __device__ constexpr int highbit(int x) {
+  return x >= 16 ? 16 : (x >= 8 ? 8 : (x >= 4 ? 4 : (x >= 2 ? 2 : x)));
+}
+
+// Twiddles of the passes after the first.  Pass p (radix R, span NS) scales
+// input r of butterfly j by b^r, b = w_N^(jm N / (NS R)), jm = j mod NS.  A
+// thread loads only the bases b^(2^q), q < log2 R, of each of its butterflies
+// (one table entry each, loaded once at the start of the transform, before
+// any exchange, so that their latency overlaps the first pass) and forms the
+// other powers as products of at most log2(R) - 1 of them.
+template <class P, typename V> struct Tw {
+  static constexpr int S1 = P::P >= 2 ? P::E / P::R1 : 1, L1 = P::P >= 2 ? ilog2(P::R1) : 1;
+  static constexpr int S2 = P::P >= 3 ? P::E / P::R2 : 1, L2 = P::P >= 3 ? ilog2(P::R2) : 1;
+  V b1[S1][L1];
+  V b2[S2][L2];
+};
+
+template <class P, typename V>
+__device__ __forceinline__ void tw_load(Tw<P, V>& w, int t, const V* __restrict__ tab) {
+  constexpr int N = P::N, TT = P::TT;
+  if constexpr (P::P >= 2) {
+    constexpr int R = P::R1, NS = P::R0;
+#pragma unroll
+    for (int s = 0; s < Tw<P, V>::S1; ++s) {
+      const int e = ((t + TT * s) & (NS - 1)) * (N / (NS * R));
+#pragma unroll
+      for (int q = 0; q < Tw<P, V>::L1; ++q) w.b1[s][q] = tab[(e << q) * (TWN / N)];
+    }
+  }
+  if constexpr (P::P >= 3) {
+    constexpr int R = P::R2, NS = P::R0 * P::R1;
+#pragma unroll
+    for (int s = 0; s < Tw<P, V>::S2; ++s) {
+      const int e = ((t + TT * s) & (NS - 1)) * (N / (NS * R));
+#pragma unroll
+      for (int q = 0; q < Tw<P, V>::L2; ++q) w.b2[s][q] = tab[(e << q) * (TWN / N)];
+    }
+  }
+}
+
+// v[r] *= b^r (DIR > 0: conj(b)^r), r = 1..R-1, from the bases b^(2^q).
+template <int R, int DIR, typename V, int L>
+__device__ __forceinline__ void twiddle_mul(V* v, const V (&b)[L]) {
+  V w[R];
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const int hb = highbit(r);
+    w[r] = r == hb ? b[ilog2(r)] : cmul(w[hb], w[r - hb]);
+    const V x = v[r], c = w[r];
+    v[r] = DIR > 0 ? mk<V>(x.x * c.x + x.y * c.y, x.y * c.x - x.x * c.y) : cmul(x, c);
+  }
+}
+
+// Butterflies of one pass on the thread's registers: radix R, twiddle bases b
+// (one set per butterfly; none for the first pass).
+template <int E, int R, int DIR, typename V>
+__device__ __forceinline__ void pass_first(V (&v)[E]) {
+#pragma unroll
+  for (int s = 0; s < E / R; ++s) Dft<R, DIR, V>::run(&v[s * R]);
+}
+template <int E, int R, int DIR, typename V, int S, int L>
+__device__ __forceinline__ void pass_tw(V (&v)[E], const V (&b)[S][L]) {
+  static_assert(S == E / R, "one twiddle set per butterfly");
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    if constexpr (NS > 1) {
-      const int j = t + TT * s;
-      const int jm = j & (NS - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        V w = tw[(jm * r * (N / (NS * R))) * (TWN / N)];
-        if constexpr (DIR > 0) w.y = -w.y;
-        v[s * R + r] = cmul(v[s * R + r], w);
-      }
-    }
+    twiddle_mul<R, DIR>(&v[s * R], b[s]);
     Dft<R, DIR, V>::run(&v[s * R]);
   }
 }
@@ -222,25 +278,32 @@ template <bool WAVE> __device__ __forceinline__ void group_sync() {
 // Whole transform on registers: v holds the inputs at in_pos on entry and the
 // outputs at out_pos on exit.  buf is this transform's LDS scratch
 // (LdsLen<N, PAD> values); every thread of the block (WAVE: of the wavefront)
-// must call this, since it synchronises them.
+// must call this, since it synchronises them.  w holds the thread's twiddle
+// bases (tw_load); the overload without it loads them first.
 template <class P, int DIR, typename V, bool PAD = false, bool WAVE = false>
-__device__ __forceinline__ void fft_regs(V (&v)[P::E], int t, V* buf, const V* __restrict__ tw) {
+__device__ __forceinline__ void fft_regs(V (&v)[P::E], int t, V* buf, const Tw<P, V>& w) {
   constexpr int N = P::N;
   constexpr int E = P::E;
-  pass_compute<N, E, P::R0, 1, DIR>(v, t, tw);
+  pass_first<E, P::R0, DIR>(v);
   if constexpr (P::P >= 2) {
     pass_write<N, E, P::R0, 1, V, PAD>(v, t, buf);
     group_sync<WAVE>();
     pass_read<N, E, P::R1, V, PAD>(v, t, buf);
-    pass_compute<N, E, P::R1, P::R0, DIR>(v, t, tw);
+    pass_tw<E, P::R1, DIR>(v, w.b1);
   }
   if constexpr (P::P >= 3) {
     group_sync<WAVE>();
     pass_write<N, E, P::R1, P::R0, V, PAD>(v, t, buf);
     group_sync<WAVE>();
     pass_read<N, E, P::R2, V, PAD>(v, t, buf);
-    pass_compute<N, E, P::R2, P::R0 * P::R1, DIR>(v, t, tw);
+    pass_tw<E, P::R2, DIR>(v, w.b2);
   }
+}
+template <class P, int DIR, typename V, bool PAD = false, bool WAVE = false>
+__device__ __forceinline__ void fft_regs(V (&v)[P::E], int t, V* buf, const V* __restrict__ tw) {
+  Tw<P, V> w;
+  tw_load<P>(w, t, tw);
+  fft_regs<P, DIR, V, PAD, WAVE>(v, t, buf, w);
 }
 
 // Register index that holds output element (N - pos) mod N, where pos is the

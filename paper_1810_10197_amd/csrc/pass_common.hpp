@@ -1,5 +1,7 @@
 // Launch shapes and small helpers shared by the 3D and 2D pass kernels.
 #pragma once
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "ns_internal.hpp"
 
@@ -41,6 +43,35 @@ template <class PL, typename T> struct RowCfg {
   static constexpr int LD = LdsLen<N, true>::value;
   static constexpr int NT = RPB * TT;
 };
+
+// The retained band |k| <= K of a length-N axis in FFT order is k <= K or
+// k >= N - K; the rest (the gap) is zero on input and dropped on output.  A
+// register of a transform holds element c + t in thread t < TT (c fixed per
+// register), so whether it meets the band is known at compile time except
+// where the range straddles a band edge.  Bits: 1 low part, 2 gap, 4 high part.
+enum { BAND_LO = 1, BAND_GAP = 2, BAND_HI = 4 };
+__host__ __device__ constexpr int band_bits(int c, int tt, int n, int k) {
+  const int a = c, b = c + tt - 1;
+  const int lo = a <= k ? BAND_LO : 0;
+  const int hi = b >= n - k ? BAND_HI : 0;
+  const int g0 = a > k ? a : k + 1, g1 = b < n - k - 1 ? b : n - k - 1;
+  return lo | hi | (g0 <= g1 ? BAND_GAP : 0);
+}
+
+// Element c + t of a transform register (in_pos: c = i TT; out_pos: c =
+// TT s + r N/RL).
+template <class PL> __host__ __device__ constexpr int in_base(int i) { return i * PL::TT; }
+template <class PL> __host__ __device__ constexpr int out_base(int i) {
+  return PL::TT * (i / PL::RL) + (i % PL::RL) * (PL::N / PL::RL);
+}
+
+// Pointer plus a 32-bit byte offset: with a block-uniform base this maps to
+// loads and stores that take the base in scalar registers and only the
+// offset per lane.
+template <typename P> __device__ __forceinline__ P* byte_at(P* base, unsigned off) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
+}
 
 template <typename V> __device__ __forceinline__ V shfl_c(V v, int src, int width) {
   return mk<V>(__shfl(v.x, src, width), __shfl(v.y, src, width));

@@ -31,61 +31,95 @@ namespace nsk {
 
 static_assert(TWN == TWN_TABLE, "twiddle table length");
 
+// The band limit K = (n - 1)/3 of the 2/3 rule is a compile-time constant of
+// every kernel (n is), so registers that only ever hold gap elements are
+// neither loaded nor stored, and those that always hold band elements need no
+// per-lane test.  Addresses are a block-uniform base plus a 32-bit per-lane
+// byte offset; what a register adds on top is uniform again.
+
 // ---------------------------------------------------------------- P1
+// Column loads of P1 from the compact FP64 state: component pa (and pb for
+// the curl) at every kz' the thread's registers hold, zero in the gap, with
+// kz per register.  No branches on lanes (band tests fold or become
+// selects), so that all of a thread's loads are in flight together.
+template <class PL, bool PAIR>
+__device__ __forceinline__ void zinv_loads(const double2* pa, const double2* pb, unsigned lane, int colc, int t,
+                                           double2 (&a)[PL::E], double2 (&b)[PL::E], int (&kzs)[PL::E]) {
+  constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX, TT = PL::TT;
+  const double2 zero2 = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < PL::E; ++i) {
+    const int c = in_base<PL>(i);
+    const int bd = band_bits(c, TT, N, K);
+    if (bd == BAND_GAP) {
+      a[i] = zero2; b[i] = zero2; kzs[i] = 0;
+      continue;
+    }
+    long long rowb = 0;
+    unsigned off = lane;
+    bool use = true;
+    if (bd == BAND_LO) {
+      rowb = c;
+      kzs[i] = c + t;
+    } else if (bd == BAND_HI) {
+      rowb = c - N + KF;
+      kzs[i] = c + t - N;
+    } else {
+      const int e = c + t;
+      use = (e <= K) || (e >= N - K);
+      const int kz = e <= K ? e : e - N;
+      kzs[i] = kz;
+      off = (unsigned)(colc + (use ? (kz >= 0 ? kz : kz + KF) : 0) * NCOL) * 16u;
+    }
+    const double2 x = *byte_at(pa + rowb * NCOL, off);
+    a[i] = use ? x : zero2;
+    if (PAIR) {
+      const double2 y = *byte_at(pb + rowb * NCOL, off);
+      b[i] = use ? y : zero2;
+    } else {
+      b[i] = zero2;
+    }
+  }
+}
+
 // Logical block id = (member, column tile, field) with the field fastest: the
 // six blocks of one tile run on one XCD back to back and read u_hat once from
 // HBM, the rest from L2.
 template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const double2* __restrict__ U,
-                                                             cplx<T>* __restrict__ A1, Geom g,
-                                                             long long nblocks,
+                                                             cplx<T>* __restrict__ A1, long long nblocks,
                                                              const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
+  constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
+  constexpr long long MR = (long long)NCOL * KF;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
-  constexpr int E = CF::E, C = CF::C;
+  constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
   const long long L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nblocks) return;                     // uniform per block
-  const int ncol = g.Kf * g.Kx;
-  const int ntiles = (ncol + C - 1) / C;
+  constexpr int ntiles = (NCOL + C - 1) / C;
   const int f = (int)(L % 6);
   const long long q = L / 6;
   const int tile = (int)(q % ntiles);
   const int m = (int)(q / ntiles);
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
   const int col = tile * C + lc;
-  const bool valid = col < ncol;
-  int kx = 0, ky = 0, kyp = 0;
-  if (valid) {
-    kyp = col / g.Kx;
-    kx = col - kyp * g.Kx;
-    ky = kyp <= g.K ? kyp : kyp - g.Kf;
-  }
-  const long long cs = g.mr;
-  const double2* Um = U + (long long)m * 3 * cs + (valid ? col : 0);
-  // Loads without branches (clamped addresses, zeroed by selects) so that all
-  // of a thread's loads are in flight together.
+  const bool valid = col < NCOL;
+  const int colc = valid ? col : 0;
+  const int kyp = colc / KX;
+  const int kx = colc - kyp * KX;
+  const int ky = kyp <= K ? kyp : kyp - KF;
+  Tw<PL, V> w;
+  tw_load<PL>(w, t, tw);
+  // components read by field f: u_f, or the pair (a, b) of omega_f = i (ka b - kb a)
+  const int ca = f < 3 ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
+  const int cb = f == 3 ? 1 : (f == 4 ? 2 : 0);
+  const double2* Um = U + (long long)m * 3 * MR;
+  const unsigned lane = (unsigned)(colc + t * NCOL) * 16u;
   double2 a[E], b[E];
-  bool use[E];
   int kzs[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = in_pos<PL>(t, i);
-    const bool ret = (e <= g.K) || (e >= N - g.K);
-    use[i] = valid && ret;
-    const int kz = e <= g.K ? e : e - N;
-    kzs[i] = kz;
-    const int kzp = ret ? (kz >= 0 ? kz : kz + g.Kf) : 0;
-    const double2* pp = Um + (long long)kzp * ncol;
-    if (f < 3) {
-      a[i] = pp[f * cs];
-    } else {
-      // omega_hat = i k x u_hat: (ky, kz, kx) pair with (u_z, u_y), (u_x, u_z), (u_y, u_x)
-      a[i] = pp[(f == 3 ? 2 : (f == 4 ? 0 : 1)) * cs];
-      b[i] = pp[(f == 3 ? 1 : (f == 4 ? 2 : 0)) * cs];
-    }
-  }
+  if (f < 3) zinv_loads<PL, false>(Um + ca * MR, Um, lane, colc, t, a, b, kzs);
+  else zinv_loads<PL, true>(Um + ca * MR, Um + cb * MR, lane, colc, t, a, b, kzs);
   V v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -99,14 +133,14 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const double2*
       const double wr = ka * a[i].x - kb * b[i].x, wi = ka * a[i].y - kb * b[i].y;
       vx = -wi; vy = wr;
     }
-    v[i] = use[i] ? mk<V>((T)vx, (T)vy) : mk<V>((T)0, (T)0);
+    v[i] = mk<V>((T)vx, (T)vy);
   }
-  fft_regs<PL, +1>(v, t, lds + lc * CF::LD, tw);
+  fft_regs<PL, +1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
-    const long long nkx = (long long)N * g.Kx;
-    V* out = A1 + ((long long)(m * 6 + f) * g.Kf + kyp) * nkx + kx;
+    V* out = A1 + (long long)(m * 6 + f) * KF * N * KX;
+    const unsigned lo = (unsigned)((kyp * N + t) * KX + kx) * (unsigned)sizeof(V);
 #pragma unroll
-    for (int i = 0; i < E; ++i) out[(long long)out_pos<PL>(t, i) * g.Kx] = v[i];
+    for (int i = 0; i < E; ++i) *byte_at(out + out_base<PL>(i) * KX, lo) = v[i];
   }
 }
 
@@ -114,34 +148,49 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const double2*
 // Columns (z, kx) of one (member, field): 2K+1 non-zero ky' -> N values of y.
 template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
-                                                             cplx<T>* __restrict__ A2, Geom g,
+                                                             cplx<T>* __restrict__ A2,
                                                              const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
+  constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
-  constexpr int E = CF::E, C = CF::C;
+  constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
   const long long bf = blockIdx.y;                // member * 6 + field
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int nkx = N * g.Kx;
   const int cz = blockIdx.x * C + lc;
-  const bool valid = cz < nkx;
-  const V* in = A1 + bf * g.Kf * nkx + (valid ? cz : 0);
+  const bool valid = cz < NKX;
+  const int czc = valid ? cz : 0;
+  Tw<PL, V> w;
+  tw_load<PL>(w, t, tw);
+  const V* in = A1 + bf * KF * NKX;
+  const unsigned lane = (unsigned)(czc + t * NKX) * (unsigned)sizeof(V);
   V v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const int e = in_pos<PL>(t, i);
-    const bool ret = (e <= g.K) || (e >= N - g.K);
-    const int kyp = e <= g.K ? e : (ret ? e - N + g.Kf : 0);
-    const V x = in[(long long)kyp * nkx];
-    v[i] = (valid && ret) ? x : mk<V>((T)0, (T)0);
+    const int c = in_base<PL>(i);
+    const int bd = band_bits(c, TT, N, K);
+    const V zero = mk<V>((T)0, (T)0);
+    if (bd == BAND_GAP) {
+      v[i] = zero;
+    } else if (bd == BAND_LO) {
+      v[i] = *byte_at(in + (long long)c * NKX, lane);
+    } else if (bd == BAND_HI) {
+      v[i] = *byte_at(in + (long long)(c - N + KF) * NKX, lane);
+    } else {
+      const int e = c + t;
+      const bool ret = (e <= K) || (e >= N - K);
+      const int kyp = e <= K ? e : (ret ? e - N + KF : 0);
+      const V x = *byte_at(in, (unsigned)(czc + kyp * NKX) * (unsigned)sizeof(V));
+      v[i] = ret ? x : zero;
+    }
   }
-  fft_regs<PL, +1>(v, t, lds + lc * CF::LD, tw);
+  fft_regs<PL, +1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
-    const int z = cz / g.Kx, kx = cz - z * g.Kx;
-    V* out = A2 + (bf * N + z) * (long long)nkx + kx;
+    const int z = cz / KX, kx = cz - z * KX;
+    V* out = A2 + bf * N * NKX;
+    const unsigned lo = (unsigned)(z * NKX + t * KX + kx) * (unsigned)sizeof(V);
 #pragma unroll
-    for (int i = 0; i < E; ++i) out[(long long)out_pos<PL>(t, i) * g.Kx] = v[i];
+    for (int i = 0; i < E; ++i) *byte_at(out + out_base<PL>(i) * KX, lo) = v[i];
   }
 }
 
@@ -159,67 +208,77 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
 //     from the partner thread through a cross-lane shuffle; keep kx <= K.
 template <class PL, typename T>
 __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2,
-                                                              cplx<T>* __restrict__ A3, Geom g,
-                                                              long long nrows,
+                                                              cplx<T>* __restrict__ A3, long long nrows,
                                                               const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
+  constexpr int N = PL::N, K = (N - 1) / 3, KX = K + 1;
+  constexpr long long RPM = (long long)N * N;
   using V = cplx<T>;
   using RC = RowCfg<PL, T>;
   constexpr int E = RC::E, TT = RC::TT;
   __shared__ V lds[RC::RPB * RC::LD];
-  const int grp = threadIdx.x / TT, t = threadIdx.x - grp * TT;
+  const int grp = threadIdx.x / TT, t = threadIdx.x % TT;
   const long long row = (long long)blockIdx.x * RC::RPB + grp;
   const bool valid = row < nrows;
-  const long long rpm = (long long)N * N;
-  const long long m = valid ? row / rpm : 0, rr = valid ? row - m * rpm : 0;
-  const int K = g.K, Kx = g.Kx;
+  const long long m = valid ? row / RPM : 0, rr = valid ? row - m * RPM : 0;
   const T zero = (T)0;
   V* buf = lds + grp * RC::LD;
+  Tw<PL, V> w;
+  tw_load<PL>(w, t, tw);
 
   V z0[E], z1[E], z2[E];
   {
-    // Loads without branches: every lane reads a clamped in-row address and
-    // zeroes what lies outside the retained band with selects, so a whole
-    // pair's loads are in flight together.  Z = A + iB at k <= K and
-    // conj(A) + i conj(B) at N - k (s = +1 / -1 below).
-    const V* base = A2 + (m * 6 * rpm + rr) * Kx;
-    int kk[E];
-    T sg[E];
-    bool use[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int pos = in_pos<PL>(t, i);
-      const bool lo = pos <= K, hi = pos >= N - K;
-      use[i] = valid && (lo || hi);
-      const int k0 = lo ? pos : N - pos;
-      kk[i] = k0 <= K ? k0 : K;
-      sg[i] = lo ? (T)1 : (T)-1;
-    }
+    // Z = A + iB at k <= K and conj(A) + i conj(B) at N - k.  Registers in
+    // the low band read A[c + t], those in the high band A[N - c - t]; both
+    // are a per-lane base plus a compile-time offset.
+    const V* base = A2 + (m * 6 * RPM + rr) * KX;
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-      V a[E], b[E];
-      const V* pa = base + (long long)(2 * p) * rpm * Kx;
-      const V* pb = pa + rpm * Kx;
-#pragma unroll
-      for (int i = 0; i < E; ++i) {
-        a[i] = pa[kk[i]];
-        b[i] = pb[kk[i]];
-      }
+      const V* pa = base + (long long)(2 * p) * RPM * KX;
+      const V* pb = pa + RPM * KX;
+      const V* pa_lo = pa + t;
+      const V* pb_lo = pb + t;
+      const V* pa_hi = pa + (N - t);
+      const V* pb_hi = pb + (N - t);
       V* z = p == 0 ? z0 : (p == 1 ? z1 : z2);
 #pragma unroll
       for (int i = 0; i < E; ++i) {
-        const T ay = kk[i] == 0 ? zero : a[i].y, by = kk[i] == 0 ? zero : b[i].y;
-        const V r = mk<V>(a[i].x - sg[i] * by, sg[i] * ay + b[i].x);
-        z[i] = use[i] ? r : mk<V>(zero, zero);
+        const int c = in_base<PL>(i);
+        const int bd = band_bits(c, TT, N, K);
+        V r;
+        if (bd == BAND_GAP) {
+          r = mk<V>(zero, zero);
+        } else if (bd == BAND_LO) {
+          const V a = pa_lo[c], b = pb_lo[c];
+          if (c == 0) {                           // k = 0 of a real field is real
+            const T ay = t == 0 ? zero : a.y, by = t == 0 ? zero : b.y;
+            r = mk<V>(a.x - by, ay + b.x);
+          } else {
+            r = mk<V>(a.x - b.y, a.y + b.x);
+          }
+        } else if (bd == BAND_HI) {
+          const V a = pa_hi[-c], b = pb_hi[-c];
+          r = mk<V>(a.x + b.y, b.x - a.y);
+        } else {
+          const int pos = c + t;
+          const bool lo = pos <= K, hi = pos >= N - K;
+          const int k0 = lo ? pos : N - pos;
+          const int kk = k0 <= K ? k0 : K;
+          const V a = pa[kk], b = pb[kk];
+          const T sg = lo ? (T)1 : (T)-1;
+          const T ay = kk == 0 ? zero : a.y, by = kk == 0 ? zero : b.y;
+          const V x = mk<V>(a.x - sg * by, sg * ay + b.x);
+          r = (lo || hi) ? x : mk<V>(zero, zero);
+        }
+        z[i] = valid ? r : mk<V>(zero, zero);
       }
     }
   }
   static_assert(64 % TT == 0, "a row's threads must lie in one wavefront");
-  fft_regs<PL, +1, V, true, true>(z0, t, buf, tw);
+  fft_regs<PL, +1, V, true, true>(z0, t, buf, w);
   group_sync<true>();
-  fft_regs<PL, +1, V, true, true>(z1, t, buf, tw);
+  fft_regs<PL, +1, V, true, true>(z1, t, buf, w);
   group_sync<true>();
-  fft_regs<PL, +1, V, true, true>(z2, t, buf, tw);
+  fft_regs<PL, +1, V, true, true>(z2, t, buf, w);
 
   V nxy[E], nz[E];
 #pragma unroll
@@ -229,28 +288,30 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
     nz[out_to_in<PL>(i)] = mk<V>(ux * wy - uy * wx, zero);
   }
   group_sync<true>();
-  fft_regs<PL, -1, V, true, true>(nxy, t, buf, tw);
+  fft_regs<PL, -1, V, true, true>(nxy, t, buf, w);
   group_sync<true>();
-  fft_regs<PL, -1, V, true, true>(nz, t, buf, tw);
+  fft_regs<PL, -1, V, true, true>(nz, t, buf, w);
 
   const int partner = (TT - t) & (TT - 1);
-  V* out = A3 + ((m * 3) * N + (rr % N)) * (long long)N * Kx + (rr / N) * (long long)Kx;
-  const long long cstride = rpm * Kx;
+  V* out = A3 + ((m * 3) * N + (rr % N)) * (long long)N * KX + (rr / N) * (long long)KX + t;
+  constexpr long long CST = RPM * KX;
   const T half = (T)0.5;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
+    const int c = out_base<PL>(i);
+    const int bd = band_bits(c, TT, N, K);
+    if (!(bd & BAND_LO)) continue;               // kx > K for every thread: dropped
     const V own = nxy[mirror_reg<PL>(i, true)];
     V pv = own;
     if constexpr (TT > 1) {
       const V sh = shfl_c(nxy[mirror_reg<PL>(i, false)], partner, TT);
       if (t != 0) pv = sh;
     }
-    const int pos = out_pos<PL>(t, i);
-    if (valid && pos <= K) {
+    if (valid && (bd == BAND_LO || c + t <= K)) {
       const V zk = nxy[i];
-      out[pos] = mk<V>(half * (zk.x + pv.x), half * (zk.y - pv.y));
-      out[cstride + pos] = mk<V>(half * (zk.y + pv.y), half * (pv.x - zk.x));
-      out[2 * cstride + pos] = nz[i];
+      out[c] = mk<V>(half * (zk.x + pv.x), half * (zk.y - pv.y));
+      out[CST + c] = mk<V>(half * (zk.y + pv.y), half * (pv.x - zk.x));
+      out[2 * CST + c] = nz[i];
     }
   }
 }
@@ -259,31 +320,44 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
 // Columns (z, kx) of one (member, component): N values of y -> 2K+1 retained ky.
 template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3,
-                                                             cplx<T>* __restrict__ A4, Geom g,
+                                                             cplx<T>* __restrict__ A4,
                                                              const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
+  constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
-  constexpr int E = CF::E, C = CF::C;
+  constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
   const long long bc = blockIdx.y;                // member * 3 + component
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int nkx = N * g.Kx;
   const int cz = blockIdx.x * C + lc;
-  const bool valid = cz < nkx;
-  const V* in = A3 + bc * N * (long long)nkx + (valid ? cz : 0);
+  const bool valid = cz < NKX;
+  const int czc = valid ? cz : 0;
+  Tw<PL, V> w;
+  tw_load<PL>(w, t, tw);
+  const V* in = A3 + bc * N * NKX;
+  const unsigned lane = (unsigned)(czc + t * NKX) * (unsigned)sizeof(V);
   V v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = in[(long long)in_pos<PL>(t, i) * nkx];
-  fft_regs<PL, -1>(v, t, lds + lc * CF::LD, tw);
+  for (int i = 0; i < E; ++i) v[i] = *byte_at(in + (long long)in_base<PL>(i) * NKX, lane);
+  fft_regs<PL, -1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
-    const int z = cz / g.Kx, kx = cz - z * g.Kx;
-    V* out = A4 + (bc * N + z) * (long long)g.Kf * g.Kx + kx;
+    const int z = cz / KX, kx = cz - z * KX;
+    V* out = A4 + bc * N * KF * KX;
+    const unsigned lo = (unsigned)(z * KF * KX + t * KX + kx) * (unsigned)sizeof(V);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const int e = out_pos<PL>(t, i);
-      if (e <= g.K) out[(long long)e * g.Kx] = v[i];
-      else if (e >= N - g.K) out[(long long)(e - N + g.Kf) * g.Kx] = v[i];
+      const int c = out_base<PL>(i);
+      const int bd = band_bits(c, TT, N, K);
+      if (bd == BAND_GAP) continue;
+      if (bd == BAND_LO) {
+        *byte_at(out + c * KX, lo) = v[i];
+      } else if (bd == BAND_HI) {
+        *byte_at(out + (c - N + KF) * KX, lo) = v[i];
+      } else {
+        const int e = c + t;
+        if (e <= K) *byte_at(out + c * KX, lo) = v[i];
+        else if (e >= N - K) *byte_at(out + (c - N + KF) * KX, lo) = v[i];
+      }
     }
   }
 }
@@ -292,41 +366,56 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>*
 template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>* __restrict__ A4,
                                                            const double2* __restrict__ U,
-                                                           double2* __restrict__ Kout, Geom g,
+                                                           double2* __restrict__ Kout,
                                                            const double* __restrict__ nu,
                                                            const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
+  constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
+  constexpr long long MR = (long long)NCOL * KF;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
-  constexpr int E = CF::E, C = CF::C;
+  constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int ncol = g.Kf * g.Kx;
   const int col = blockIdx.x * C + lc;
   const int m = blockIdx.y;
-  const bool valid = col < ncol;
+  const bool valid = col < NCOL;
+  const int colc = valid ? col : 0;
+  Tw<PL, V> w;
+  tw_load<PL>(w, t, tw);
+  const unsigned lane = (unsigned)(colc + t * NCOL) * (unsigned)sizeof(V);
   V o[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();                // LDS reuse across fields
-    const V* in = A4 + ((long long)(m * 3 + c) * N) * ncol + (valid ? col : 0);
+    const V* in = A4 + (long long)(m * 3 + c) * N * NCOL;
 #pragma unroll
-    for (int i = 0; i < E; ++i) o[c][i] = in[(long long)in_pos<PL>(t, i) * ncol];
-    fft_regs<PL, -1>(o[c], t, lds + lc * CF::LD, tw);
+    for (int i = 0; i < E; ++i) o[c][i] = *byte_at(in + (long long)in_base<PL>(i) * NCOL, lane);
+    fft_regs<PL, -1>(o[c], t, lds + lc * CF::LD, w);
   }
   if (!valid) return;
-  const int kyp = col / g.Kx;
-  const int kx = col - kyp * g.Kx;
-  const int ky = kyp <= g.K ? kyp : kyp - g.Kf;
+  const int kyp = col / KX;
+  const int kx = col - kyp * KX;
+  const int ky = kyp <= K ? kyp : kyp - KF;
   const double scale = 1.0 / ((double)N * (double)N * (double)N);
   const double num = nu[m];
-  const long long cs = g.mr;
+  const double2* Um = U + (long long)m * 3 * MR;
+  double2* Km = Kout + (long long)m * 3 * MR;
+  const unsigned lo = (unsigned)(col + t * NCOL) * 16u;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const int e = out_pos<PL>(t, i);
-    if (!((e <= g.K) || (e >= N - g.K))) continue;
-    const int kz = e <= g.K ? e : e - N;
-    const long long idx = (long long)m * 3 * cs + (long long)(kz >= 0 ? kz : kz + g.Kf) * ncol + col;
+    const int c = out_base<PL>(i);
+    const int bd = band_bits(c, TT, N, K);
+    if (bd == BAND_GAP) continue;
+    const int e = c + t;
+    if (bd != BAND_LO && bd != BAND_HI && !((e <= K) || (e >= N - K))) continue;
+    const int kz = e <= K ? e : e - N;
+    // row kz' of this register: c + t (low band) or c + t - N + 2K+1 (high)
+    const long long rowb = bd == BAND_LO ? c : (bd == BAND_HI ? c - N + KF : 0);
+    const unsigned off = (bd == BAND_LO || bd == BAND_HI)
+                             ? lo
+                             : (unsigned)(col + (kz >= 0 ? kz : kz + KF) * NCOL) * 16u;
+    const double2* up = Um + rowb * NCOL;
+    double2* kp = Km + rowb * NCOL;
     const double n0x = (double)o[0][i].x * scale, n0y = (double)o[0][i].y * scale;
     const double n1x = (double)o[1][i].x * scale, n1y = (double)o[1][i].y * scale;
     const double n2x = (double)o[2][i].x * scale, n2y = (double)o[2][i].y * scale;
@@ -335,7 +424,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
     if (k2 == 0.0) {
       f0 = make_double2(0.0, 0.0); f1 = f0; f2 = f0;
     } else {
-      const double2 u0 = U[idx], u1 = U[idx + cs], u2 = U[idx + 2 * cs];
+      const double2 u0 = *byte_at(up, off), u1 = *byte_at(up + MR, off), u2 = *byte_at(up + 2 * MR, off);
       const double px = (kx * n0x + ky * n1x + kz * n2x) / k2;
       const double py = (kx * n0y + ky * n1y + kz * n2y) / k2;
       const double vk = num * k2;
@@ -343,9 +432,9 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
       f1 = make_double2(n1x - ky * px - vk * u1.x, n1y - ky * py - vk * u1.y);
       f2 = make_double2(n2x - kz * px - vk * u2.x, n2y - kz * py - vk * u2.y);
     }
-    Kout[idx] = f0;
-    Kout[idx + cs] = f1;
-    Kout[idx + 2 * cs] = f2;
+    *byte_at(kp, off) = f0;
+    *byte_at(kp + MR, off) = f1;
+    *byte_at(kp + 2 * MR, off) = f2;
   }
 }
 
@@ -369,8 +458,8 @@ static void launch_zinv(const Geom& g, const double2* U, cplx<T>* A1, const cplx
   const int ncol = g.Kf * g.Kx;
   const long long nb = (long long)g.batch * 6 * ((ncol + CF::C - 1) / CF::C);
   const long long nbp = (nb + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_zinv<typename CV::PL, T, CV::CW>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, U, A1, g,
-                     nb, tw);
+  hipLaunchKernelGGL((k_zinv<typename CV::PL, T, CV::CW>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, U, A1, nb,
+                     tw);
 }
 template <int N, typename T, int V>
 static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2, const cplx<T>* tw, hipStream_t st) {
@@ -378,7 +467,7 @@ static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2, const cpl
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int nkx = N * g.Kx;
   hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), dim3((nkx + CF::C - 1) / CF::C, g.batch * 6),
-                     dim3(CF::NT), 0, st, A1, A2, g, tw);
+                     dim3(CF::NT), 0, st, A1, A2, tw);
 }
 template <int N, typename T, int V>
 static void launch_xpass(const Geom& g, const cplx<T>* A2, cplx<T>* A3, const cplx<T>* tw, hipStream_t st) {
@@ -386,7 +475,7 @@ static void launch_xpass(const Geom& g, const cplx<T>* A2, cplx<T>* A3, const cp
   using RC = RowCfg<PL, T>;
   const long long rows = (long long)g.batch * N * N;
   hipLaunchKernelGGL((k_xpass<PL, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)), dim3(RC::NT), 0, st,
-                     A2, A3, g, rows, tw);
+                     A2, A3, rows, tw);
 }
 template <int N, typename T, int V>
 static void launch_yfwd(const Geom& g, const cplx<T>* A3, cplx<T>* A4, const cplx<T>* tw, hipStream_t st) {
@@ -394,7 +483,7 @@ static void launch_yfwd(const Geom& g, const cplx<T>* A3, cplx<T>* A4, const cpl
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int nkx = N * g.Kx;
   hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), dim3((nkx + CF::C - 1) / CF::C, g.batch * 3),
-                     dim3(CF::NT), 0, st, A3, A4, g, tw);
+                     dim3(CF::NT), 0, st, A3, A4, tw);
 }
 template <int N, typename T, int V>
 static void launch_zfwd(const Geom& g, const cplx<T>* A4, const double2* U, double2* K, const double* nu,
@@ -403,7 +492,7 @@ static void launch_zfwd(const Geom& g, const cplx<T>* A4, const double2* U, doub
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = g.Kf * g.Kx;
   hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch),
-                     dim3(CF::NT), 0, st, A4, U, K, g, nu, tw);
+                     dim3(CF::NT), 0, st, A4, U, K, nu, tw);
 }
 
 template <int N, typename T>
