@@ -1,18 +1,23 @@
 """Benchmark: right-hand-side evaluations per second of the BS5-stepped
 pseudo-spectral Navier--Stokes solver on one MI355X.
 
-Workload: 3D Taylor--Green vortex at 256^3, nu = 1/1600, FFTs and nonlinear
-term in FP32, state / stage combinations / error norm in FP64.  One step is
-one BS5 attempt through the C ABI (seven right-hand sides, the stage
+Default workload: 3D Taylor--Green vortex at 256^3, nu = 1/1600, FFTs and
+nonlinear term in FP32, state / stage combinations / error norm in FP64.  One
+step is one BS5 attempt through the C ABI (seven right-hand sides, the stage
 combinations, the fused error-norm + diagnostics reduction, the controller's
 accept test and the commit), with the inputs already resident in HBM.
-value = right-hand-side evaluations per second over the whole timed region.
+value = right-hand-side evaluations per second over the whole timed region
+(member evaluations for an ensemble).  --workload ensemble runs 128 members at
+64^3 (Taylor--Green and random-phase fields, nu log-uniform), --workload rt2d
+the 2D Boussinesq Rayleigh--Taylor problem at 1024^2.
 
 The dominant kernel's roofline figure divides its algorithmic bytes per launch
-(reads + writes of the pruned pass model) by its average
-launch duration, measured with HIP events recorded on the solver's stream
-inside the timed region.  The CPU baseline times the FP64 NumPy oracle's
-right-hand side at the same size on the host, on a bounded sample.
+(reads + writes of the pruned pass model in pass_bytes) by its average launch
+duration, from HIP events recorded around every launch on the launch's stream
+in a second run of the same steps (the events themselves cost about a tenth of
+the step time, so the timed region that gives value runs without them).  The
+CPU baseline times the FP64 NumPy oracle's right-hand side at the same size on
+the host, on a bounded sample.
 """
 import argparse
 import json
@@ -51,9 +56,10 @@ def measured_traffic(kernel):
 
 
 def pass_bytes(n, fp64=False):
-    """Algorithmic HBM bytes per launch of each right-hand-side pass (one
+    """Algorithmic HBM bytes of each right-hand-side pass per evaluation (one
     member): reads + writes of the retained-mode pencil model.  cb = bytes per
-    complex value in the rhs precision, 16 bytes per FP64 state value."""
+    complex value in the rhs precision, 16 bytes per FP64 state value.  The
+    y/x/y passes run in slabs of z planes; one launch covers its slab's share."""
     K = (n - 1) // 3
     Kf, Kx = 2 * K + 1, K + 1
     mr = Kf * Kf * Kx
@@ -67,6 +73,17 @@ def pass_bytes(n, fp64=False):
         "yfwd": 3 * c2 * cb + 3 * c1 * cb,
         "zfwd": 3 * c1 * cb + 3 * mr * 16 + 3 * mr * 16,
     }
+
+
+def pass_bytes_2d(n, fp64=False):
+    """Same for the 2D Boussinesq passes (state u, v, rho; four transformed
+    fields): Q1 y-inverse, Q2 x-pass, Q3 y-forward + epilogue."""
+    K = (n - 1) // 3
+    Kf, Kx = 2 * K + 1, K + 1
+    mr = Kf * Kx
+    cb = 16 if fp64 else 8
+    col = 4 * n * Kx * cb
+    return {"zinv": 3 * mr * 16 + col, "xpass": 2 * col, "zfwd": col + 2 * 3 * mr * 16}
 
 
 def cpu_baseline(n, nu, budget_s):
@@ -311,7 +328,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variants", default=None,
-                    help="comma-separated launch variants of the 5 passes (skips the autotuner)")
+                    help="comma-separated launch variants of the 5 passes and the slab (skips the autotuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter scale)")
     ap.add_argument("--study", choices=["tts", "mlp"], default=None,
@@ -324,6 +341,9 @@ def main():
     ap.add_argument("--weights", default=None, help="proposer weights (.npy) for --study tts")
     ap.add_argument("--bs5-precs", nargs="*", default=["fp32", "fp64"])
     ap.add_argument("--members", type=int, default=128)
+    ap.add_argument("--workload", choices=["tgv", "ensemble", "rt2d"], default="tgv",
+                    help="tgv: 3D Taylor-Green at --n; ensemble: --members x 64^3; rt2d: 2D "
+                         "Boussinesq at 1024^2")
     ap.add_argument("--iters", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -346,19 +366,54 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}))
         return
+    return bench_throughput(args)
+
+
+def bench_throughput(args):
+    import numpy as np
+    import torch
     from paper_1810_10197_amd import inputs, ns
 
-    n, nu = args.n, 1.0 / 1600
+    wl = args.workload
+    fp64 = args.prec == "fp64"
+    if wl == "tgv":
+        n, batch, dim = args.n, 1, 3
+        nu = 1.0 / 1600
+        s = ns.Solver(dim=3, n=n, batch=1, nu=nu, rhs_precision=args.prec)
+        s.set_state(inputs.tgv3d(n)[None])
+        cfg = {"workload": "3D Taylor-Green vortex %d^3, nu=1/1600, BS5 attempts at h=%g, "
+                           "atol=rtol=1e-6, %s FFTs, FP64 state" % (n, args.dt, args.prec),
+               "n": n, "batch": 1}
+        h = args.dt
+    elif wl == "ensemble":
+        n, batch, dim = 64, args.members, 3
+        fields, nus = inputs.ensemble_members(batch, n)
+        nu = float(np.min(nus))
+        s = ns.Solver(dim=3, n=n, batch=batch, nu=nus, rhs_precision=args.prec)
+        s.set_state(fields)
+        cfg = {"workload": "ensemble of %d independent 64^3 runs (Taylor-Green and random-phase "
+                           "fields, nu log-uniform in [1e-3, 1e-2]), BS5 attempts at h=%g, "
+                           "atol=rtol=1e-6, %s FFTs, FP64 state" % (batch, args.dt, args.prec),
+               "n": n, "batch": batch}
+        h = args.dt
+    else:
+        n, batch, dim = 1024, 1, 2
+        nu = 1e-4
+        s = ns.Solver(dim=2, n=n, batch=1, nu=nu, rhs_precision=args.prec, scalar=True, ri=0.5,
+                      kappa=1e-4)
+        s.set_state(inputs.rayleigh_taylor2d(n)[None])
+        cfg = {"workload": "2D Boussinesq Rayleigh-Taylor 1024^2 (tanh interface, Ri=0.5, "
+                           "nu=kappa=1e-4), BS5 attempts at h=%g, atol=rtol=1e-6, %s FFTs, "
+                           "FP64 state" % (args.dt, args.prec), "n": n, "batch": 1}
+        h = args.dt
     atol = rtol = 1e-6
-    s = ns.Solver(dim=3, n=n, batch=1, nu=nu, rhs_precision=args.prec)
-    s.set_state(inputs.tgv3d(n)[None])
     if args.variants:
         tune_variants = s.tune([int(v) for v in args.variants.split(",")])
-        tune_ms = __import__("numpy").zeros((5, 4))
+        tune_ms = np.zeros((ns.NS_NTUNE, ns.NS_TUNE_MAXV))
     else:
         tune_variants, tune_ms = s.autotune(reps=3)
     for _ in range(args.warmup):
-        s.step_bs5(args.dt, atol, rtol)
+        s.step_bs5(h, atol, rtol)
     # pure right-hand-side rate (context): f(u_n) into the cached stage
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -366,40 +421,68 @@ def main():
     for _ in range(nr):
         s.refresh_rhs()
     torch.cuda.synchronize()
-    rhs_only = nr / (time.perf_counter() - t0)
+    rhs_only = nr * batch / (time.perf_counter() - t0)
 
+    # timed region: BS5 attempts, no events
     torch.cuda.synchronize()
-    s.profile_start()
     t0 = time.perf_counter()
     rejected = 0
     for _ in range(args.steps):
-        st, _ = s.step_bs5(args.dt, atol, rtol)
+        st, _ = s.step_bs5(h, atol, rtol)
         rejected += int(st == ns.NS_STEP_REJECTED)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # the same steps again with HIP events around every launch: per-kernel
+    # durations for the roofline
+    torch.cuda.synchronize()
+    s.profile_start()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step_bs5(h, atol, rtol)
+    torch.cuda.synchronize()
+    elapsed_ev = time.perf_counter() - t1
     prof = s.profile_stop()
     s.close()
 
-    rhs_evals = 7 * args.steps
+    rhs_evals = 7 * args.steps * batch
     value = rhs_evals / elapsed
-    fp64 = args.prec == "fp64"
-    pb = pass_bytes(n, fp64)
+    pb = pass_bytes(n, fp64) if dim == 3 else pass_bytes_2d(n, fp64)
+    pb = {k: v * batch for k, v in pb.items()}
+    n_rhs = prof["zinv"][1]                       # one first-pass launch per evaluation
     per_kernel = {}
     for name in ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce"]:
         ms, cnt = prof[name]
         if cnt:
             per_kernel[name] = {"avg_us": 1000.0 * ms / cnt, "launches": cnt}
             if name in pb:
-                per_kernel[name]["gbs"] = pb[name] / (ms / cnt * 1e-3) / 1e9
-    rhs_passes = ["zinv", "yinv", "xpass", "yfwd", "zfwd"]
-    dom = max(rhs_passes, key=lambda k: per_kernel[k]["avg_us"])
+                per_launch_bytes = pb[name] * n_rhs / cnt
+                per_kernel[name]["us_per_rhs"] = 1000.0 * ms / n_rhs
+                per_kernel[name]["bytes_per_launch"] = per_launch_bytes
+                per_kernel[name]["gbs"] = per_launch_bytes / (ms / cnt * 1e-3) / 1e9
+    rhs_passes = [k for k in ["zinv", "yinv", "xpass", "yfwd", "zfwd"] if k in pb]
+    if dim == 3:
+        # wall time per evaluation: z passes plus the y/x/y slab phase (its
+        # passes may overlap on two streams, so the phase is timed as a unit
+        # and is the roofline's unit when it dominates)
+        slab_ms, slab_cnt = prof["slab"]
+        slab_us = 1000.0 * slab_ms / max(slab_cnt, 1)
+        ph_bytes = pb["yinv"] + pb["xpass"] + pb["yfwd"]
+        per_kernel["yxy_phase"] = {"us_per_rhs": slab_us, "bytes_per_rhs": ph_bytes,
+                                   "gbs": ph_bytes / (slab_us * 1e-6) / 1e9}
+        rhs_ms = (per_kernel["zinv"]["us_per_rhs"] + slab_us + per_kernel["zfwd"]["us_per_rhs"]) / 1000.0
+        units = ["zinv", "yxy_phase", "zfwd"]
+    else:
+        rhs_ms = sum(per_kernel[k]["us_per_rhs"] for k in rhs_passes) / 1000.0
+        units = rhs_passes
+    dom = max(units, key=lambda k: per_kernel[k]["us_per_rhs"])
     achieved = per_kernel[dom]["gbs"]
-    rhs_ms = sum(per_kernel[k]["avg_us"] for k in rhs_passes) / 1000.0
     model_bytes = sum(pb.values())
+    unit = "RHS evals/s" if batch == 1 else "member RHS evals/s"
     out = {
-        "metric": "RHS evals/s at 256^3 (BS5 step, FP32 RHS / FP64 state)",
+        "metric": "RHS evals/s at 256^3 (BS5 step, FP32 RHS / FP64 state)" if wl == "tgv" and n == 256
+        else "RHS evals/s (BS5 step, %s RHS / FP64 state)" % args.prec.upper(),
         "value": value,
-        "unit": "RHS evals/s",
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -407,25 +490,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if not fp64 else "f64",
+        "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
-        "config": {"workload": "3D Taylor-Green vortex %d^3, nu=1/1600, BS5 attempts at "
-                               "h=%g, atol=rtol=1e-6, %s FFTs, FP64 state" % (n, args.dt, args.prec),
-                   "n": n, "batch": 1},
+        "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom) if (n == 256 and not fp64) else None,
+                     "traffic": measured_traffic(dom) if (wl == "tgv" and n == 256 and not fp64) else None,
                      "kernel": dom},
         "rhs_model_gb": model_bytes / 1e9,
         "rhs_passes_ms": rhs_ms,
         "rhs_model_gbs": model_bytes / (rhs_ms * 1e-3) / 1e9,
+        "rhs_model_frac": model_bytes / (rhs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "rhs_only_per_s": rhs_only,
+        "value_with_events": rhs_evals / elapsed_ev,
         "rejected_steps": rejected,
         "autotune": {"variants": tune_variants,
-                     "ms": [[round(x, 4) for x in row] for row in tune_ms.tolist()]},
+                     "ms": [[round(x, 4) for x in row] for row in np.asarray(tune_ms).tolist()]},
         "kernels": per_kernel,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and wl == "tgv":
         out["cpu_baseline"] = cpu_baseline(n, nu, args.cpu_budget)
     print(json.dumps(out))
 

@@ -200,13 +200,15 @@ int ns_mlp_fit_stats(ns_solver* s);
 int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long long seed,
                  float* loss_host);
 
-/* Kernel timing with HIP events recorded on the solver's stream around every
- * kernel launch while profiling is on (a tracing aid; the events add a few
- * microseconds per launch).  Index: 0..4 the five right-hand-side passes
- * (z-inverse, y-inverse, x-pass, y-forward, z-forward), 5 stage
- * combinations, 6 reductions, 7 other.  stop synchronises the stream and
- * fills total milliseconds and launch counts per index. */
-#define NS_NPROF 8
+/* Kernel timing with HIP events recorded around every kernel launch, on the
+ * stream of the launch, while profiling is on (a tracing aid; the events add
+ * a few microseconds per launch).  Index: 0..4 the five right-hand-side
+ * passes (z-inverse, y-inverse, x-pass, y-forward, z-forward), 5 stage
+ * combinations, 6 reductions, 7 other, 8 the whole y/x/y slab phase of a 3D
+ * evaluation (wall time on the solver's stream; its passes may overlap on two
+ * streams).  stop synchronises and fills total milliseconds and launch counts
+ * per index. */
+#define NS_NPROF 9
 typedef struct ns_kernel_times {
   double ms[NS_NPROF];
   long long count[NS_NPROF];
@@ -214,16 +216,22 @@ typedef struct ns_kernel_times {
 int ns_profile_start(ns_solver* s);
 int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
 
-/* Autotuner of the 3D right-hand side: each of the NS_NTUNE passes
- * (z-inverse, y-inverse, x-pass, y-forward, z-forward) has launch variants
- * (radix plan: wide = few passes, narrow = at most 8 values per thread;
- * column tile: 16 or 32 columns per block).  ns_autotune times every variant
- * of every pass on the current state (reps evaluations each, HIP events on the
- * solver's stream) and keeps the fastest; ms_host (NS_NTUNE x 4 doubles, may
- * be NULL) receives the average milliseconds (0 for variants a pass lacks).
- * tune_get / tune_set read or restore the choice (e.g. from a cache).  2D
- * solvers accept the calls and ignore the choice. */
-#define NS_NTUNE 5
+/* Autotuner of the 3D right-hand side.  Parameters 0-4 are launch variants of
+ * the five passes (z-inverse, y-inverse, x-pass, y-forward, z-forward): radix
+ * plan (wide = few passes, narrow = at most 8 values per thread) and column
+ * tile (16 or 32 columns per block).  Parameter 5 is the slab schedule of
+ * the y/x/y passes: variant v < 5 runs them over slabs of n >> v planes of z
+ * (at least 1) through slab buffers that are reused, so that small slabs stay
+ * in the memory-side cache; v >= 5 uses slabs of n >> (v - 4) planes that
+ * alternate between two streams and two buffers, so that one slab's passes
+ * overlap the next one's.  ns_autotune times every variant of every
+ * parameter on the current state (reps evaluations each, HIP events; the
+ * slab schedule by the wall time of the y/x/y phase) and keeps the fastest; ms_host (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL) receives the
+ * average milliseconds (0 for variants a parameter lacks).  tune_get /
+ * tune_set read or restore the choice (e.g. from a cache).  2D solvers accept
+ * the calls and ignore the choice. */
+#define NS_NTUNE 6
+#define NS_TUNE_MAXV 9
 int ns_autotune(ns_solver* s, int reps, double* ms_host);
 int ns_tune_get(ns_solver* s, int* variant_host);
 int ns_tune_set(ns_solver* s, const int* variant_host);

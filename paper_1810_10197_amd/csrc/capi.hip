@@ -117,7 +117,7 @@ Layout make_layout(const ns_config* c) {
   const int fp64 = c->rhs_precision == NS_FP64;
   const size_t scratch = c->dim == 3 ? nsk::rhs3d_scratch_bytes(g, fp64) : nsk::rhs2d_scratch_bytes(g, fp64);
   const size_t cb = fp64 ? 16 : 8;
-  const size_t a1 = c->dim == 3 ? B * 6 * g.n * g.Kf * g.Kx * cb : scratch / 2;
+  const size_t a1 = c->dim == 3 ? scratch : scratch / 2;    // 3D: one region, carved by the passes
   L.a1 = take(a1);
   L.a2 = take(scratch - a1);
   L.total = off;
@@ -183,11 +183,11 @@ struct ns_solver {
 
 static constexpr size_t PROF_POOL = 16384;
 
-static void prof_hook(void* ctx, int id, int phase) {
+static void prof_hook(void* ctx, int id, int phase, hipStream_t st) {
   ns_solver* s = (ns_solver*)ctx;
   if (!s->prof_on || s->prof_used >= s->prof_ev.size()) return;
   if (phase == 0 && s->prof_used + 2 > s->prof_ev.size()) return;   // no room for the pair
-  if (hipEventRecord(s->prof_ev[s->prof_used], s->st) != hipSuccess) return;
+  if (hipEventRecord(s->prof_ev[s->prof_used], st) != hipSuccess) return;
   s->prof_id[s->prof_used] = id * 2 + phase;
   ++s->prof_used;
 }
@@ -239,9 +239,9 @@ static int bs5_stages(ns_solver* s, const double* h, double atol, double rtol) {
       c.coef[c.nterms] = a;
       ++c.nterms;
     }
-    prof_hook(s, nsk::PROF_COMBINE, 0);
+    prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
     NS_HIP(nsk::combine(s->g, s->u, c, h, s->U, s->st));
-    prof_hook(s, nsk::PROF_COMBINE, 1);
+    prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
     int rc = rhs(s, s->U, s->k[i]);
     if (rc) return rc;
   }
@@ -261,9 +261,9 @@ static int bs5_stages(ns_solver* s, const double* h, double atol, double rtol) {
   ra.atol = atol;
   ra.rtol = rtol;
   ra.kf2 = forcing_kf2(s);
-  prof_hook(s, nsk::PROF_REDUCE, 0);
+  prof_hook(s, nsk::PROF_REDUCE, 0, s->st);
   NS_HIP(nsk::reduce_state(s->g, ra, s->red_part, s->red_out, s->st));
-  prof_hook(s, nsk::PROF_REDUCE, 1);
+  prof_hook(s, nsk::PROF_REDUCE, 1, s->st);
   return NS_OK;
 }
 
@@ -396,6 +396,18 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->rb.hook = prof_hook;
   s->rb.hook_ctx = s;
   for (int i = 0; i < NS_NTUNE; ++i) s->rb.variant[i] = 0;
+  s->rb.side = nullptr;
+  s->rb.fork = s->rb.join = nullptr;
+  if (s->g.dim == 3) {
+    s->rb.variant[5] = nsk::default_slab_variant(s->g, s->fp64);
+    // second stream (default priority) and ordering events of the two-stream slab schedule
+    if (hipStreamCreateWithFlags(&s->rb.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->rb.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->rb.join, hipEventDisableTiming) != hipSuccess) {
+      ns_free(s);
+      return NS_ERR_HIP;
+    }
+  }
   nsk::CtlState& c = s->ctl;
   c.t = (double*)(w + L.ctl_d[0]);
   c.h = (double*)(w + L.ctl_d[1]);
@@ -513,9 +525,9 @@ int ns_step_rk4(ns_solver* s, double h) {
     c.nterms = 1;
     c.src[0] = s->k[i - 1];
     c.coef[0] = stage_a[i - 1];
-    prof_hook(s, nsk::PROF_COMBINE, 0);
+    prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
     NS_HIP(nsk::combine(s->g, s->u, c, s->h_d, s->U, s->st));
-    prof_hook(s, nsk::PROF_COMBINE, 1);
+    prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
     rc = rhs(s, s->U, s->k[i]);
     if (rc) return rc;
   }
@@ -526,9 +538,9 @@ int ns_step_rk4(ns_solver* s, double h) {
     c.src[j] = s->k[j];
     c.coef[j] = b[j];
   }
-  prof_hook(s, nsk::PROF_COMBINE, 0);
+  prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
   NS_HIP(nsk::combine(s->g, s->u, c, s->h_d, s->U, s->st));
-  prof_hook(s, nsk::PROF_COMBINE, 1);
+  prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
   std::swap(s->u, s->U);
   if (s->gexec) {                              // the captured graph holds the old pointers
     (void)hipGraphExecDestroy(s->gexec);
@@ -870,12 +882,14 @@ int ns_tune_get(ns_solver* s, int* v) {
   return NS_OK;
 }
 
+static int tune_nvariants(int p) {
+  return p == 2 ? nsk::NVARIANT_ROW : (p == 5 ? nsk::NVARIANT_SLAB : nsk::NVARIANT_COL);
+}
+
 int ns_tune_set(ns_solver* s, const int* v) {
   if (!s || !v) return NS_ERR_ARG;
-  for (int i = 0; i < NS_NTUNE; ++i) {
-    const int nv = i == 2 ? nsk::NVARIANT_ROW : nsk::NVARIANT_COL;
-    if (v[i] < 0 || v[i] >= nv) return NS_ERR_ARG;
-  }
+  for (int i = 0; i < NS_NTUNE; ++i)
+    if (v[i] < 0 || v[i] >= tune_nvariants(i)) return NS_ERR_ARG;
   for (int i = 0; i < NS_NTUNE; ++i) s->rb.variant[i] = v[i];
   if (s->gexec) {                              // captured with the old launches
     (void)hipGraphExecDestroy(s->gexec);
@@ -888,12 +902,15 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
   if (!s || reps < 1) return NS_ERR_ARG;
   if (!s->have_state) return NS_ERR_STATE;
   if (ms_host)
-    for (int i = 0; i < NS_NTUNE * 4; ++i) ms_host[i] = 0.0;
+    for (int i = 0; i < NS_NTUNE * NS_TUNE_MAXV; ++i) ms_host[i] = 0.0;
   if (s->g.dim != 3) return NS_OK;
   const bool was_on = s->prof_on;
   int rc = NS_OK;
-  for (int p = 0; p < NS_NTUNE && !rc; ++p) {
-    const int nv = p == 2 ? nsk::NVARIANT_ROW : nsk::NVARIANT_COL;
+  // the slab first (it changes what the passes read from), then every pass
+  const int order[NS_NTUNE] = {5, 0, 1, 2, 3, 4};
+  for (int q = 0; q < NS_NTUNE && !rc; ++q) {
+    const int p = order[q];
+    const int nv = tune_nvariants(p);
     double best = 1e300;
     int best_v = s->rb.variant[p];
     for (int v = 0; v < nv && !rc; ++v) {
@@ -908,8 +925,14 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
         rc = rc ? rc : rc2;
         break;
       }
-      const double ms = kt.count[p] ? kt.ms[p] / (double)kt.count[p] : 1e300;
-      if (ms_host) ms_host[p * 4 + v] = ms;
+      // a pass: per launch; the slab schedule: wall time of the y/x/y phase
+      double ms = 1e300;
+      if (p == 5) {
+        if (kt.count[nsk::PROF_SLAB]) ms = kt.ms[nsk::PROF_SLAB] / (double)kt.count[nsk::PROF_SLAB];
+      } else if (kt.count[p]) {
+        ms = kt.ms[p] / (double)kt.count[p];
+      }
+      if (ms_host) ms_host[p * NS_TUNE_MAXV + v] = ms;
       if (ms < best) {
         best = ms;
         best_v = v;
@@ -984,6 +1007,9 @@ void ns_free(ns_solver* s) {
   if (!s) return;
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
   if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
+  if (s->rb.side) (void)hipStreamDestroy(s->rb.side);
+  if (s->rb.fork) (void)hipEventDestroy(s->rb.fork);
+  if (s->rb.join) (void)hipEventDestroy(s->rb.join);
   for (auto& e : s->prof_ev) (void)hipEventDestroy(e);
   delete s;
 }

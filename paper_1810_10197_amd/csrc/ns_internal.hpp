@@ -27,9 +27,10 @@ struct RhsParams {
 };
 
 // Optional timing hook called around every kernel launch: phase 0 before,
-// 1 after; id is one of the PROF_* values.
-typedef void (*HookFn)(void* ctx, int id, int phase);
-enum { PROF_P1 = 0, PROF_P2, PROF_P3, PROF_P4, PROF_P5, PROF_COMBINE, PROF_REDUCE, PROF_OTHER, NPROF };
+// 1 after, on the stream of the launch; id is one of the PROF_* values
+// (PROF_SLAB brackets the whole y/x/y slab phase on the solver's stream).
+typedef void (*HookFn)(void* ctx, int id, int phase, hipStream_t st);
+enum { PROF_P1 = 0, PROF_P2, PROF_P3, PROF_P4, PROF_P5, PROF_COMBINE, PROF_REDUCE, PROF_OTHER, PROF_SLAB, NPROF };
 
 // Scratch for one RHS evaluation (rhs precision T).
 struct RhsBufs {
@@ -37,9 +38,19 @@ struct RhsBufs {
   void* a2;           // after the second inverse pass
   HookFn hook;        // may be null
   void* hook_ctx;
-  int variant[5];     // launch variant of each 3D pass (the autotuner's choice)
+  int variant[6];     // launch variant of each 3D pass, then the slab schedule (the autotuner's choice)
+  hipStream_t side;   // second stream of the two-stream slab schedule (default priority)
+  hipEvent_t fork, join;   // order `side` after / before the solver's stream
 };
-constexpr int NVARIANT_COL = 4, NVARIANT_ROW = 2;
+constexpr int NVARIANT_COL = 4, NVARIANT_ROW = 2, NVARIANT_SLAB = 9;
+// 3D slab schedule of the y/x/y passes, variant v: v < 5 one stream with
+// slabs of n >> v planes; v >= 5 slabs of n >> (v - 4) planes alternating
+// between two streams and two slab buffers, so that the passes of one slab
+// overlap those of the next.  The default is the largest one-stream slab
+// whose buffers fit in 96 MiB.
+int slab_planes(const Geom& g, int v);
+bool slab_two_streams(int v);
+int default_slab_variant(const Geom& g, int fp64);
 
 // k = f(U) on compact FP64 buffers for every member (3D: rhs3d.hip,
 // 2D: rhs2d.hip).  tw: table of TWN twiddles in the rhs precision.

@@ -274,7 +274,7 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   const long long nb1 = (long long)g.batch * nfield * ((g.Kx + CF::C - 1) / CF::C);
   const long long nb1p = (nb1 + 7) / 8 * 8;
 #define NSK_MARK(id, ph) \
-  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph)
+  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, st)
   NSK_MARK(PROF_P1, 0);
   hipLaunchKernelGGL((k2_yinv<PL, T>), dim3((unsigned)nb1p), dim3(CF::NT), 0, st, U, B1, g, nfield, nb1,
                      tw);

@@ -17,12 +17,16 @@
 //   P5 z-forward  n values of z -> the 2K+1 retained kz, then the projection,
 //                 the viscous term and the cast to FP64, fused
 //
-// Intermediate layouts (T complex), chosen so that every column pass tiles a
-// contiguous run of columns:
-//   A1 [m][6][ky'][z][kx]   written by P1, read by P2 (columns (z, kx))
-//   A2 [m][6][z][y][kx]     written by P2, read by P3 (rows (z, y))
-//   A3 [m][3][y][z][kx]     written by P3 (reuses A1), read by P4 (columns (z, kx))
-//   A4 [m][3][z][ky'][kx]   written by P4 (reuses A2), read by P5 (columns (ky', kx))
+// P2, P3 and P4 only couple values of one z plane, so they run over slabs of
+// Zs planes (z0 .. z0+Zs-1) through two slab buffers that are reused for
+// every slab: small enough, they stay in the memory-side cache between the
+// three passes instead of going to HBM and back.  Intermediate layouts (T
+// complex), chosen so that every column pass tiles a contiguous run of
+// columns:
+//   A1  [m][6][ky'][z][kx]   written by P1, read by P2 (columns (z, kx))
+//   A2s [m][6][zl][y][kx]    slab: written by P2, read by P3 (rows (zl, y))
+//   A3s [m][3][y][zl][kx]    slab: written by P3, read by P4 (columns (zl, kx))
+//   A4  [m][3][z][ky'][kx]   written by P4, read by P5 (columns (ky', kx))
 #include <type_traits>
 
 #include "pass_common.hpp"
@@ -145,10 +149,11 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const double2*
 }
 
 // ---------------------------------------------------------------- P2
-// Columns (z, kx) of one (member, field): 2K+1 non-zero ky' -> N values of y.
+// Columns (zl, kx) of one (member, field) in the slab z0 .. z0+zs-1: 2K+1
+// non-zero ky' -> N values of y.
 template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
-                                                             cplx<T>* __restrict__ A2,
+                                                             cplx<T>* __restrict__ A2s, int z0, int zs,
                                                              const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
   using V = cplx<T>;
@@ -157,12 +162,12 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
   __shared__ V lds[C * CF::LD];
   const long long bf = blockIdx.y;                // member * 6 + field
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int cz = blockIdx.x * C + lc;
-  const bool valid = cz < NKX;
+  const int cz = blockIdx.x * C + lc;             // slab column zl * KX + kx
+  const bool valid = cz < zs * KX;
   const int czc = valid ? cz : 0;
   Tw<PL, V> w;
   tw_load<PL>(w, t, tw);
-  const V* in = A1 + bf * KF * NKX;
+  const V* in = A1 + bf * KF * NKX + z0 * KX;
   const unsigned lane = (unsigned)(czc + t * NKX) * (unsigned)sizeof(V);
   V v[E];
 #pragma unroll
@@ -186,9 +191,9 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
   }
   fft_regs<PL, +1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
-    const int z = cz / KX, kx = cz - z * KX;
-    V* out = A2 + bf * N * NKX;
-    const unsigned lo = (unsigned)(z * NKX + t * KX + kx) * (unsigned)sizeof(V);
+    const int zl = cz / KX, kx = cz - zl * KX;
+    V* out = A2s + bf * zs * NKX;
+    const unsigned lo = (unsigned)(zl * NKX + t * KX + kx) * (unsigned)sizeof(V);
 #pragma unroll
     for (int i = 0; i < E; ++i) *byte_at(out + out_base<PL>(i) * KX, lo) = v[i];
   }
@@ -207,19 +212,20 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
 //  4. n_x, n_y are split from Z(k) and conj(Z(N-k)), the mirror value coming
 //     from the partner thread through a cross-lane shuffle; keep kx <= K.
 template <class PL, typename T>
-__global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2,
-                                                              cplx<T>* __restrict__ A3, long long nrows,
+__global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2s,
+                                                              cplx<T>* __restrict__ A3s, int zs,
                                                               const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N, K = (N - 1) / 3, KX = K + 1;
-  constexpr long long RPM = (long long)N * N;
   using V = cplx<T>;
   using RC = RowCfg<PL, T>;
   constexpr int E = RC::E, TT = RC::TT;
   __shared__ V lds[RC::RPB * RC::LD];
   const int grp = threadIdx.x / TT, t = threadIdx.x % TT;
+  const long long RPM = (long long)zs * N;        // rows (zl, y) per member in the slab
+  const long long m = blockIdx.y;
   const long long row = (long long)blockIdx.x * RC::RPB + grp;
-  const bool valid = row < nrows;
-  const long long m = valid ? row / RPM : 0, rr = valid ? row - m * RPM : 0;
+  const bool valid = row < RPM;
+  const long long rr = valid ? row : 0;
   const T zero = (T)0;
   V* buf = lds + grp * RC::LD;
   Tw<PL, V> w;
@@ -230,7 +236,7 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
     // Z = A + iB at k <= K and conj(A) + i conj(B) at N - k.  Registers in
     // the low band read A[c + t], those in the high band A[N - c - t]; both
     // are a per-lane base plus a compile-time offset.
-    const V* base = A2 + (m * 6 * RPM + rr) * KX;
+    const V* base = A2s + (m * 6 * RPM + rr) * KX;
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
       const V* pa = base + (long long)(2 * p) * RPM * KX;
@@ -293,8 +299,8 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
   fft_regs<PL, -1, V, true, true>(nz, t, buf, w);
 
   const int partner = (TT - t) & (TT - 1);
-  V* out = A3 + ((m * 3) * N + (rr % N)) * (long long)N * KX + (rr / N) * (long long)KX + t;
-  constexpr long long CST = RPM * KX;
+  V* out = A3s + ((m * 3) * N + (rr % N)) * (long long)zs * KX + (rr / N) * (long long)KX + t;
+  const long long CST = RPM * KX;
   const T half = (T)0.5;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -317,33 +323,35 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
 }
 
 // ---------------------------------------------------------------- P4
-// Columns (z, kx) of one (member, component): N values of y -> 2K+1 retained ky.
+// Columns (zl, kx) of one (member, component) in the slab: N values of y ->
+// 2K+1 retained ky, written to plane z0 + zl of A4.
 template <class PL, typename T, int CW>
-__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3,
-                                                             cplx<T>* __restrict__ A4,
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3s,
+                                                             cplx<T>* __restrict__ A4, int z0, int zs,
                                                              const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
+  constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
   const long long bc = blockIdx.y;                // member * 3 + component
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
+  const int nkxs = zs * KX;                       // row length of the slab buffer
   const int cz = blockIdx.x * C + lc;
-  const bool valid = cz < NKX;
+  const bool valid = cz < nkxs;
   const int czc = valid ? cz : 0;
   Tw<PL, V> w;
   tw_load<PL>(w, t, tw);
-  const V* in = A3 + bc * N * NKX;
-  const unsigned lane = (unsigned)(czc + t * NKX) * (unsigned)sizeof(V);
+  const V* in = A3s + bc * N * nkxs;
+  const unsigned lane = (unsigned)(czc + t * nkxs) * (unsigned)sizeof(V);
   V v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = *byte_at(in + (long long)in_base<PL>(i) * NKX, lane);
+  for (int i = 0; i < E; ++i) v[i] = *byte_at(in + (long long)in_base<PL>(i) * nkxs, lane);
   fft_regs<PL, -1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
-    const int z = cz / KX, kx = cz - z * KX;
-    V* out = A4 + bc * N * KF * KX;
-    const unsigned lo = (unsigned)(z * KF * KX + t * KX + kx) * (unsigned)sizeof(V);
+    const int zl = cz / KX, kx = cz - zl * KX;
+    V* out = A4 + (bc * N + z0) * KF * KX;
+    const unsigned lo = (unsigned)(zl * KF * KX + t * KX + kx) * (unsigned)sizeof(V);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int c = out_base<PL>(i);
@@ -448,8 +456,8 @@ template <int N, int V> struct ColVar {
   static constexpr int CW = (V & 1) && N >= 64 ? 32 : 16;
 };
 
-#define NSK_MARK(id, ph) \
-  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph)
+#define NSK_MARK(id, ph, stream) \
+  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, stream)
 
 template <int N, typename T, int V>
 static void launch_zinv(const Geom& g, const double2* U, cplx<T>* A1, const cplx<T>* tw, hipStream_t st) {
@@ -462,28 +470,31 @@ static void launch_zinv(const Geom& g, const double2* U, cplx<T>* A1, const cplx
                      tw);
 }
 template <int N, typename T, int V>
-static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2, const cplx<T>* tw, hipStream_t st) {
+static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2s, int z0, int zs, const cplx<T>* tw,
+                        hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
-  const int nkx = N * g.Kx;
-  hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), dim3((nkx + CF::C - 1) / CF::C, g.batch * 6),
-                     dim3(CF::NT), 0, st, A1, A2, tw);
+  const int ncol = zs * g.Kx;
+  hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch * 6),
+                     dim3(CF::NT), 0, st, A1, A2s, z0, zs, tw);
 }
 template <int N, typename T, int V>
-static void launch_xpass(const Geom& g, const cplx<T>* A2, cplx<T>* A3, const cplx<T>* tw, hipStream_t st) {
+static void launch_xpass(const Geom& g, const cplx<T>* A2s, cplx<T>* A3s, int zs, const cplx<T>* tw,
+                         hipStream_t st) {
   using PL = typename std::conditional<(V == 1 && N >= 64), PlanS<N>, Plan<N>>::type;
   using RC = RowCfg<PL, T>;
-  const long long rows = (long long)g.batch * N * N;
-  hipLaunchKernelGGL((k_xpass<PL, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)), dim3(RC::NT), 0, st,
-                     A2, A3, rows, tw);
+  const long long rows = (long long)zs * N;       // per member
+  hipLaunchKernelGGL((k_xpass<PL, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB), g.batch), dim3(RC::NT),
+                     0, st, A2s, A3s, zs, tw);
 }
 template <int N, typename T, int V>
-static void launch_yfwd(const Geom& g, const cplx<T>* A3, cplx<T>* A4, const cplx<T>* tw, hipStream_t st) {
+static void launch_yfwd(const Geom& g, const cplx<T>* A3s, cplx<T>* A4, int z0, int zs, const cplx<T>* tw,
+                        hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
-  const int nkx = N * g.Kx;
-  hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), dim3((nkx + CF::C - 1) / CF::C, g.batch * 3),
-                     dim3(CF::NT), 0, st, A3, A4, tw);
+  const int ncol = zs * g.Kx;
+  hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch * 3),
+                     dim3(CF::NT), 0, st, A3s, A4, z0, zs, tw);
 }
 template <int N, typename T, int V>
 static void launch_zfwd(const Geom& g, const cplx<T>* A4, const double2* U, double2* K, const double* nu,
@@ -495,50 +506,111 @@ static void launch_zfwd(const Geom& g, const cplx<T>* A4, const double2* U, doub
                      dim3(CF::NT), 0, st, A4, U, K, nu, tw);
 }
 
+// Scratch regions of one evaluation (T complex), each 256-byte aligned: A1,
+// A4, slab buffer 0 (up to n planes) and slab buffer 1 (up to n/2 planes,
+// used by the two-stream schedule).
+struct Scratch3d {
+  size_t a1, a4, a2s[2], a3s[2], total;
+};
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+static Scratch3d scratch3d(const Geom& g, int fp64) {
+  const size_t cb = fp64 ? 16 : 8;
+  const size_t n = (size_t)g.n, B = (size_t)g.batch, plane = (size_t)g.Kf * g.Kx;
+  const size_t p2 = B * 6 * n * g.Kx * cb, p3 = B * 3 * n * g.Kx * cb;   // per z plane
+  Scratch3d s;
+  s.a1 = 0;
+  s.a4 = al256(B * 6 * n * plane * cb);
+  s.a2s[0] = s.a4 + al256(B * 3 * n * plane * cb);
+  s.a3s[0] = s.a2s[0] + al256(p2 * n);
+  s.a2s[1] = s.a3s[0] + al256(p3 * n);
+  s.a3s[1] = s.a2s[1] + al256(p2 * (n / 2));
+  s.total = s.a3s[1] + al256(p3 * (n / 2));
+  return s;
+}
+
+bool slab_two_streams(int v) { return v >= 5; }
+
+int slab_planes(const Geom& g, int v) {
+  const int sh = v < 0 ? 0 : (v >= 5 ? v - 4 : v);
+  const int zs = g.n >> sh;
+  return zs < 1 ? 1 : zs;
+}
+
+int default_slab_variant(const Geom& g, int fp64) {
+  const size_t per_plane = (size_t)g.batch * 9 * g.n * g.Kx * (fp64 ? 16 : 8);
+  int v = 0;
+  while (v < 4 && (size_t)slab_planes(g, v) * per_plane > ((size_t)96 << 20)) ++v;
+  return v;
+}
+
 template <int N, typename T>
 static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
                         const RhsBufs& bufs, const void* twv, hipStream_t st) {
   using V = cplx<T>;
   const V* tw = (const V*)twv;
-  V* A1 = (V*)bufs.a1;
-  V* A2 = (V*)bufs.a2;
+  const Scratch3d sc = scratch3d(g, sizeof(T) == 8);
+  char* base = (char*)bufs.a1;
+  V* A1 = (V*)(base + sc.a1);
+  V* A4 = (V*)(base + sc.a4);
   const int* tv = bufs.variant;
-  NSK_MARK(PROF_P1, 0);
+  const bool two = slab_two_streams(tv[5]) && bufs.side && N >= 2;
+  const int zs = slab_planes(g, tv[5]);
+  NSK_MARK(PROF_P1, 0, st);
   switch (tv[0]) {
     case 1: launch_zinv<N, T, 1>(g, U, A1, tw, st); break;
     case 2: launch_zinv<N, T, 2>(g, U, A1, tw, st); break;
     case 3: launch_zinv<N, T, 3>(g, U, A1, tw, st); break;
     default: launch_zinv<N, T, 0>(g, U, A1, tw, st);
   }
-  NSK_MARK(PROF_P1, 1);
-  NSK_MARK(PROF_P2, 0);
-  switch (tv[1]) {
-    case 1: launch_yinv<N, T, 1>(g, A1, A2, tw, st); break;
-    case 2: launch_yinv<N, T, 2>(g, A1, A2, tw, st); break;
-    case 3: launch_yinv<N, T, 3>(g, A1, A2, tw, st); break;
-    default: launch_yinv<N, T, 0>(g, A1, A2, tw, st);
+  NSK_MARK(PROF_P1, 1, st);
+  NSK_MARK(PROF_SLAB, 0, st);
+  if (two) {
+    hipError_t e = hipEventRecord(bufs.fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(bufs.side, bufs.fork, 0);
+    if (e != hipSuccess) return e;
   }
-  NSK_MARK(PROF_P2, 1);
-  NSK_MARK(PROF_P3, 0);
-  if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2, A1, tw, st);
-  else launch_xpass<N, T, 0>(g, A2, A1, tw, st);
-  NSK_MARK(PROF_P3, 1);
-  NSK_MARK(PROF_P4, 0);
-  switch (tv[3]) {
-    case 1: launch_yfwd<N, T, 1>(g, A1, A2, tw, st); break;
-    case 2: launch_yfwd<N, T, 2>(g, A1, A2, tw, st); break;
-    case 3: launch_yfwd<N, T, 3>(g, A1, A2, tw, st); break;
-    default: launch_yfwd<N, T, 0>(g, A1, A2, tw, st);
+  int slab = 0;
+  for (int z0 = 0; z0 < N; z0 += zs, ++slab) {
+    const int nz = N - z0 < zs ? N - z0 : zs;
+    const int b = two ? (slab & 1) : 0;
+    hipStream_t ss = b ? bufs.side : st;
+    V* A2s = (V*)(base + sc.a2s[b]);
+    V* A3s = (V*)(base + sc.a3s[b]);
+    NSK_MARK(PROF_P2, 0, ss);
+    switch (tv[1]) {
+      case 1: launch_yinv<N, T, 1>(g, A1, A2s, z0, nz, tw, ss); break;
+      case 2: launch_yinv<N, T, 2>(g, A1, A2s, z0, nz, tw, ss); break;
+      case 3: launch_yinv<N, T, 3>(g, A1, A2s, z0, nz, tw, ss); break;
+      default: launch_yinv<N, T, 0>(g, A1, A2s, z0, nz, tw, ss);
+    }
+    NSK_MARK(PROF_P2, 1, ss);
+    NSK_MARK(PROF_P3, 0, ss);
+    if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2s, A3s, nz, tw, ss);
+    else launch_xpass<N, T, 0>(g, A2s, A3s, nz, tw, ss);
+    NSK_MARK(PROF_P3, 1, ss);
+    NSK_MARK(PROF_P4, 0, ss);
+    switch (tv[3]) {
+      case 1: launch_yfwd<N, T, 1>(g, A3s, A4, z0, nz, tw, ss); break;
+      case 2: launch_yfwd<N, T, 2>(g, A3s, A4, z0, nz, tw, ss); break;
+      case 3: launch_yfwd<N, T, 3>(g, A3s, A4, z0, nz, tw, ss); break;
+      default: launch_yfwd<N, T, 0>(g, A3s, A4, z0, nz, tw, ss);
+    }
+    NSK_MARK(PROF_P4, 1, ss);
   }
-  NSK_MARK(PROF_P4, 1);
-  NSK_MARK(PROF_P5, 0);
+  if (two) {
+    hipError_t e = hipEventRecord(bufs.join, bufs.side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, bufs.join, 0);
+    if (e != hipSuccess) return e;
+  }
+  NSK_MARK(PROF_SLAB, 1, st);
+  NSK_MARK(PROF_P5, 0, st);
   switch (tv[4]) {
-    case 1: launch_zfwd<N, T, 1>(g, A2, U, K, p.nu, tw, st); break;
-    case 2: launch_zfwd<N, T, 2>(g, A2, U, K, p.nu, tw, st); break;
-    case 3: launch_zfwd<N, T, 3>(g, A2, U, K, p.nu, tw, st); break;
-    default: launch_zfwd<N, T, 0>(g, A2, U, K, p.nu, tw, st);
+    case 1: launch_zfwd<N, T, 1>(g, A4, U, K, p.nu, tw, st); break;
+    case 2: launch_zfwd<N, T, 2>(g, A4, U, K, p.nu, tw, st); break;
+    case 3: launch_zfwd<N, T, 3>(g, A4, U, K, p.nu, tw, st); break;
+    default: launch_zfwd<N, T, 0>(g, A4, U, K, p.nu, tw, st);
   }
-  NSK_MARK(PROF_P5, 1);
+  NSK_MARK(PROF_P5, 1, st);
   return hipGetLastError();
 }
 #undef NSK_MARK
@@ -563,12 +635,6 @@ hipError_t rhs3d_compact(const Geom& g, int fp64, const double2* U, double2* K, 
   return fp64 ? dispatch3d<double>(g, U, K, p, b, tw, st) : dispatch3d<float>(g, U, K, p, b, tw, st);
 }
 
-size_t rhs3d_scratch_bytes(const Geom& g, int fp64) {
-  const size_t cb = fp64 ? 16 : 8;
-  const size_t n = (size_t)g.n, B = (size_t)g.batch;
-  const size_t a1 = B * 6 * n * (size_t)g.Kf * g.Kx * cb;     // also holds A3
-  const size_t a2 = B * 6 * n * n * (size_t)g.Kx * cb;        // also holds A4
-  return a1 + a2;
-}
+size_t rhs3d_scratch_bytes(const Geom& g, int fp64) { return scratch3d(g, fp64).total; }
 
 }  // namespace nsk

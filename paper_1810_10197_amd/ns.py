@@ -43,8 +43,9 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_mlp_fit_stats",
            "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
            "ns_profile_stop", "ns_strerror", "ns_free"]
-NS_NTUNE = 5
-PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other"]
+NS_NTUNE = 6
+NS_TUNE_MAXV = 9
+PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other", "slab"]
 
 
 class NsConfig(ctypes.Structure):
@@ -63,8 +64,11 @@ class NsStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+NS_NPROF = 9
+
+
 class NsKernelTimes(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_longlong * 8)]
+    _fields_ = [("ms", ctypes.c_double * NS_NPROF), ("count", ctypes.c_longlong * NS_NPROF)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -440,9 +444,9 @@ class Solver:
     def autotune(self, reps=3):
         """Pick the fastest launch variant of each pass; returns
         (variants, ms[pass][variant])."""
-        ms = np.zeros(NS_NTUNE * 4)
+        ms = np.zeros(NS_NTUNE * NS_TUNE_MAXV)
         ns_autotune(self.handle, reps, ms)
-        return ns_tune_get(self.handle), ms.reshape(NS_NTUNE, 4)
+        return ns_tune_get(self.handle), ms.reshape(NS_NTUNE, NS_TUNE_MAXV)
 
     def tune(self, variants=None):
         if variants is not None:
@@ -456,7 +460,7 @@ class Solver:
         """{kernel name: (total ms, launches)} since profile_start."""
         out = NsKernelTimes()
         ns_profile_stop(self.handle, out)
-        return {PROF_NAMES[i]: (out.ms[i], out.count[i]) for i in range(8)}
+        return {PROF_NAMES[i]: (out.ms[i], out.count[i]) for i in range(len(PROF_NAMES))}
 
     def synchronize(self):
         self.stream.synchronize()

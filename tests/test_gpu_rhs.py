@@ -125,21 +125,22 @@ def test_inviscid_energy_conservation_fp32_512(ns):
 
 @pytest.mark.parametrize("n", [64, 256])
 def test_every_launch_variant_matches_oracle(ns, n):
-    """Each autotuner variant (radix plan, column tile) of each pass is a
-    correct right-hand side; the tuner then keeps one of them."""
+    """Each autotuner variant (radix plan, column tile) of each pass, and each
+    slab size of the y/x/y passes, is a correct right-hand side; the tuner
+    then keeps one of them."""
     announce("launch variants n=%d" % n)
     nu = 0.013
     u = inputs.random_isotropic(n, 300 + n)
     ref = spectral.rhs_ns3d(u, nu)
     s = solver(ns, n, "fp32", nu=nu)
-    for v in range(4):
-        s.tune([v, v, v % 2, v, v])
+    for v in range(9):
+        s.tune([v % 4, v % 4, v % 2, v % 4, v % 4, v])
         got = s.rhs(u[None]).cpu().numpy()[0]
         errs = per_field_rel_l2(got, ref)
         assert max(errs) <= 5e-6, (v, errs)
     s.set_state(u[None])
     variants, ms = s.autotune(reps=2)
-    assert all(ms[p][variants[p]] == min(x for x in ms[p] if x > 0) for p in range(5))
+    assert all(ms[p][variants[p]] == min(x for x in ms[p] if x > 0) for p in range(6))
     got = s.rhs(u[None]).cpu().numpy()[0]
     assert max(per_field_rel_l2(got, ref)) <= 5e-6
     s.close()
