@@ -232,6 +232,139 @@ def study_mlp(args):
     print(json.dumps({"study": "proposer_gain", "results": res}))
 
 
+def study_e1(args):
+    """Sec. 3.1 first test: Taylor-Green vortex at Re = 280 (nu = 1/280), 64^3,
+    T = 9.4, FP64 throughout.  Reference eps(t) from RK4 at dt = 1e-4 (sampled
+    every 5 steps, piecewise-quadratic interpolation between samples); each
+    arm's error is max |eps - eps_ref| over its step times, its cost the number
+    of right-hand sides.  Arms: RK4 and BS5 at fixed steps, BS5 and DP5 with
+    the Sec. 2.2.1 controller (the attempt loop runs on the host here so that
+    eps is read after every accepted step)."""
+    import numpy as np
+    import torch
+    from paper_1810_10197_amd import inputs, ns
+    n, nu, T = args.n if args.n != 256 else 64, 1.0 / 280, 9.4
+    u0 = inputs.tgv3d(n)[None]
+    out = {"study": "tgv_re280", "n": n, "T": T, "nu": nu, "precision": "fp64"}
+
+    def solver():
+        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp64")
+        s.set_state(u0)
+        return s
+
+    def eps_now(s):
+        return float(s.diagnostics()[1][0])
+
+    def rk4_run(dt, every=1):
+        s = solver()
+        steps = max(1, int(math.ceil(T / dt - 1e-9)))
+        ts, es = [0.0], [eps_now(s)]
+        for i in range(steps):
+            h = dt if i < steps - 1 else T - (steps - 1) * dt
+            s.step_rk4(h)
+            if (i + 1) % every == 0 or i == steps - 1:
+                ts.append(min(T, (i + 1) * dt))
+                es.append(eps_now(s))
+            if (i + 1) % 20000 == 0:
+                log("rk4 dt=%g step %d/%d" % (dt, i + 1, steps))
+        s.close()
+        return np.array(ts), np.array(es), 4 * steps
+
+    t0 = time.perf_counter()
+    tref, eref, _ = rk4_run(1e-4, every=5)
+    out["ref_wall_s"] = time.perf_counter() - t0
+    log("reference: %d samples, %.1f s" % (len(tref), out["ref_wall_s"]))
+
+    def eps_ref(t):
+        # quadratic through the three samples around t
+        j = int(np.clip(np.searchsorted(tref, t) - 1, 1, len(tref) - 2))
+        x, y = tref[j - 1:j + 2], eref[j - 1:j + 2]
+        return (y[0] * (t - x[1]) * (t - x[2]) / ((x[0] - x[1]) * (x[0] - x[2]))
+                + y[1] * (t - x[0]) * (t - x[2]) / ((x[1] - x[0]) * (x[1] - x[2]))
+                + y[2] * (t - x[0]) * (t - x[1]) / ((x[2] - x[0]) * (x[2] - x[1])))
+
+    def err_of(ts, es):
+        d = [abs(e - eps_ref(t)) for t, e in zip(ts, es)]
+        return float(max(d)) if all(math.isfinite(x) for x in d) else float("inf")
+
+    out["rk4"] = []
+    for dt in args.e1_dts:
+        ts, es, nr = rk4_run(dt)
+        out["rk4"].append({"dt": dt, "n_rhs": nr, "max_eps_err": err_of(ts, es)})
+        log("rk4 dt=%g rhs %d err %.3e" % (dt, nr, out["rk4"][-1]["max_eps_err"]))
+
+    out["bs5_fixed"] = []
+    for dt in args.e1_dts:
+        s = solver()
+        steps = max(1, int(math.ceil(T / dt - 1e-9)))
+        ts, es = [0.0], [eps_now(s)]
+        for i in range(steps):
+            h = dt if i < steps - 1 else T - (steps - 1) * dt
+            s.step_bs5(h, 1.0, 1.0, force=True)
+            ts.append(min(T, (i + 1) * dt))
+            es.append(eps_now(s))
+        s.close()
+        out["bs5_fixed"].append({"dt": dt, "n_rhs": 7 * steps + 1, "max_eps_err": err_of(ts, es)})
+        log("bs5 fixed dt=%g err %.3e" % (dt, out["bs5_fixed"][-1]["max_eps_err"]))
+
+    def adaptive(method, tol, h0=0.01):
+        # Sec. 2.2.1: fac = 0.8 err^(-1/5) clamped to [0.01, 2] (1 for the step
+        # accepted right after a rejection), accept iff err <= 1, last step
+        # clipped to T
+        s = solver()
+        step = s.step_bs5 if method == "bs5" else s.step_dp5
+        per = 7 if method == "bs5" else 6
+        t, h, prev_rej = 0.0, h0, False
+        ts, es = [0.0], [eps_now(s)]
+        att = rej = consec = 0
+        while t < T and consec < 50:
+            last = h >= T - t
+            hc = T - t if last else h
+            _, errs = step(hc, tol, tol)
+            err = float(errs[0])
+            att += 1
+            ok = math.isfinite(err) and err <= 1.0
+            fmax = 1.0 if (ok and prev_rej) else 2.0
+            fac = 0.01 if not math.isfinite(err) else (fmax if err == 0.0 else
+                                                       min(fmax, max(0.01, 0.8 * err ** -0.2)))
+            if ok:
+                t = T if last else t + hc
+                ts.append(t)
+                es.append(eps_now(s))
+                prev_rej = False
+                consec = 0
+            else:
+                rej += 1
+                consec += 1
+                prev_rej = True
+            h = hc * fac
+        s.close()
+        return {"tol": tol, "n_rhs": per * att + 1, "attempts": att, "rejected": rej,
+                "max_eps_err": err_of(ts, es) if t >= T else float("inf")}
+
+    for method in ("bs5", "dp5"):
+        key = "%s_adaptive" % method
+        out[key] = []
+        for tol in args.e1_tols:
+            r = adaptive(method, tol)
+            out[key].append(r)
+            log("%s tol=%g rhs %d rej %d err %.3e" % (method, tol, r["n_rhs"], r["rejected"],
+                                                       r["max_eps_err"]))
+
+    # RHS of RK4 needed for the error each adaptive run reached (log-log
+    # interpolation along the RK4 sweep), and the ratio to the adaptive count
+    rk = sorted(out["rk4"], key=lambda r: r["max_eps_err"])
+    le = np.log([r["max_eps_err"] for r in rk])
+    lr = np.log([r["n_rhs"] for r in rk])
+    for key in ("bs5_adaptive", "dp5_adaptive", "bs5_fixed"):
+        for r in out[key]:
+            e = r["max_eps_err"]
+            if le[0] <= math.log(e) <= le[-1]:
+                r["rk4_rhs_same_err"] = float(np.exp(np.interp(math.log(e), le, lr)))
+                r["rk4_over_this"] = r["rk4_rhs_same_err"] / r["n_rhs"]
+    print(json.dumps(out))
+
+
 def study_tts(args):
     """Wall time to a fixed relative energy error at T on the Taylor-Green
     vortex (nu = 1/1600): plain FP64 RK4 at fixed steps (the last one clipped
@@ -331,15 +464,19 @@ def main():
                     help="comma-separated launch variants of the 5 passes and the slab (skips the autotuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter scale)")
-    ap.add_argument("--study", choices=["tts", "mlp"], default=None,
+    ap.add_argument("--study", choices=["tts", "mlp", "e1"], default=None,
                     help="tts: wall time to a fixed energy error, BS5 (+proposer) vs FP64 RK4; "
-                         "mlp: what the trained proposer gains on held-out ensemble members")
+                         "mlp: what the trained proposer gains on held-out ensemble members; "
+                         "e1: Taylor-Green at Re=280, 64^3, RHS counts at equal dissipation error")
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--rk4-dts", type=float, nargs="*", default=[0.02, 0.01, 0.005, 0.0025])
     ap.add_argument("--tols", type=float, nargs="*", default=[1e-4, 1e-5, 1e-6, 1e-7, 1e-8])
     ap.add_argument("--weights", default=None, help="proposer weights (.npy) for --study tts")
     ap.add_argument("--bs5-precs", nargs="*", default=["fp32", "fp64"])
+    ap.add_argument("--e1-dts", type=float, nargs="*", default=[0.1, 0.05, 0.02, 0.01, 0.005, 0.0025])
+    ap.add_argument("--e1-tols", type=float, nargs="*",
+                    default=[1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10])
     ap.add_argument("--members", type=int, default=128)
     ap.add_argument("--workload", choices=["tgv", "ensemble", "rt2d"], default="tgv",
                     help="tgv: 3D Taylor-Green at --n; ensemble: --members x 64^3; rt2d: 2D "
@@ -356,6 +493,8 @@ def main():
         return study_tts(args)
     if args.study == "mlp":
         return study_mlp(args)
+    if args.study == "e1":
+        return study_e1(args)
     if args.calibrate_copy:
         nbytes = args.calibrate_copy * 1024 * 1024
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

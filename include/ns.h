@@ -68,6 +68,7 @@ extern "C" {
 #define NS_FORCE_COMMIT 1       /* ns_step_bs5: commit whatever err is */
 #define NS_INTEGRATE_HOST 0x100 /* ns_integrate: launch each attempt's kernels
                                    individually instead of replaying a graph */
+#define NS_METHOD_DP5 0x200     /* ns_integrate: the DP5 pair instead of BS5 */
 
 #define NS_MLP_NPARAM 5569      /* W1 64x20, b1 64, W2 64x64, b2 64, W3 1x64, b3 1 */
 #define NS_MLP_NWEIGHTS 5609    /* parameters + feature mean [20] + feature scale [20] */
@@ -131,6 +132,13 @@ int ns_step_rk4(ns_solver* s, double h);
 int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags,
                 double* err_host);
 
+/* The same with the Dormand--Prince 5(4) pair of Appendix A.1, Eq. (7): seven
+ * stages, FSAL (six new right-hand sides per attempt), embedded b_hat of
+ * order 4, so the controller's exponent is again 1/5.  Arguments, error norm
+ * and commit rule as ns_step_bs5. */
+int ns_step_dp5(ns_solver* s, double h, double atol, double rtol, int flags,
+                double* err_host);
+
 /* Adaptive BS5 integration of every member from its current time to t_end
  * (Sec. 2.2.1): h0 is the first trial step, the factor
  * 0.8 err^(-1/5) clamped to [0.01, 2] (1 right after a rejection) sets the
@@ -139,10 +147,12 @@ int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags,
  * counters); one attempt -- stages, error norm, decision, commit, forcing --
  * is captured once as a HIP graph and replayed until every member is done.
  * controller: NS_CTRL_PI or NS_CTRL_MLP (needs weights, see
- * ns_mlp_set_weights: after an accepted step the network's proposal replaces
- * the factor, clamped to [0.01, 2] (1 after a rejection); after a rejection,
- * or if the proposal is not finite, the Sec. 2.2.1 factor is used), optionally
- * or-ed with NS_INTEGRATE_HOST.  stats_host[batch] (host, may be NULL)
+ * ns_mlp_set_weights: after an accepted step the network's proposal exp(y)
+ * replaces the Sec. 2.2.1 factor fac, clamped to [fac/2, min(2 fac, dmax)]
+ * with dmax = 2 (1 right after a rejection), so the controller stays the
+ * fallback; after a rejection, or if the proposal is not finite, fac is used),
+ * optionally or-ed with NS_INTEGRATE_HOST and with NS_METHOD_DP5 (the DP5 pair
+ * of ns_step_dp5 instead of BS5).  stats_host[batch] (host, may be NULL)
  * receives the counters.  Returns NS_ERR_STEPFAIL after 50 consecutive
  * rejections of a member (that member keeps its last accepted state). */
 int ns_integrate(ns_solver* s, double t_end, double h0, double atol,

@@ -17,8 +17,9 @@ using nsk::Geom;
 namespace {
 
 // Butcher tableaux as exact rationals p/q (each converted once, correctly
-// rounded).  RK4: the classical method.  BS5: Appendix A.3, Eq. (8); its last
-// row of A equals b (FSAL) and bh is the embedded error estimator b_hat.
+// rounded).  RK4: the classical method.  BS5: Appendix A.3, Eq. (8), and DP5:
+// Appendix A.1, Eq. (7); in both the last row of A equals b (FSAL) and bh is
+// the embedded error estimator b_hat (order 4).
 struct Q { double p, q; };
 constexpr double rq(Q v) { return v.p / v.q; }
 
@@ -38,6 +39,31 @@ const Q BS5_B[8] = {{587, 8064}, {0, 1}, {4440339, 15491840}, {24353, 124800},
                     {387, 44800}, {2152, 5985}, {7267, 94080}, {0, 1}};
 const Q BS5_BH[8] = {{2479, 34992}, {0, 1}, {123, 416}, {612941, 3411720},
                      {43, 1440}, {2272, 6561}, {79937, 1113912}, {3293, 556956}};
+
+const Q DP5_A[7][6] = {
+    {{0, 1}},
+    {{1, 5}},
+    {{3, 40}, {9, 40}},
+    {{44, 45}, {-56, 15}, {32, 9}},
+    {{19372, 6561}, {-25360, 2187}, {64448, 6561}, {-212, 729}},
+    {{9017, 3168}, {-355, 33}, {46732, 5247}, {49, 176}, {-5103, 18656}},
+    {{35, 384}, {0, 1}, {500, 1113}, {125, 192}, {-2187, 6784}, {11, 84}},
+};
+const Q DP5_B[7] = {{35, 384}, {0, 1}, {500, 1113}, {125, 192}, {-2187, 6784}, {11, 84}, {0, 1}};
+const Q DP5_BH[7] = {{5179, 57600}, {0, 1}, {7571, 16695}, {393, 640},
+                     {-92097, 339200}, {187, 2100}, {1, 40}};
+
+// An embedded FSAL pair: `stages` stages, A row-major with row length lda.
+struct Pair {
+  int stages;
+  const Q* A;
+  int lda;
+  const Q* b;
+  const Q* bh;
+  double a(int i, int j) const { return rq(A[i * lda + j]); }
+};
+const Pair PAIR_BS5 = {8, &BS5_A[0][0], 7, BS5_B, BS5_BH};
+const Pair PAIR_DP5 = {7, &DP5_A[0][0], 6, DP5_B, DP5_BH};
 
 constexpr int RING_CAP = 65536;        // training rows
 constexpr int TRAIN_MAX = 1024;        // rows per gradient evaluation
@@ -173,7 +199,7 @@ struct ns_solver {
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_st = nullptr;   // private stream: graphs cannot be captured on the null stream
   double g_atol = -1, g_rtol = -1, g_tend = 0;
-  int g_ctrl = -1, g_collect = -1;
+  int g_ctrl = -1, g_collect = -1, g_method = -1;
   // kernel timing (ns_profile_start/stop)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -225,15 +251,17 @@ static double forcing_kf2(const ns_solver* s) {
   return s->cfg.force_kf > 0.0 ? s->cfg.force_kf * s->cfg.force_kf : -1.0;
 }
 
-// Stages 2..8 of a BS5 attempt and the fused error / diagnostics reduction,
-// with the per-member steps in h.  Leaves u_{n+1} in U, f(u_{n+1}) in k[7],
-// the reduction in red_out.  Needs a valid k[0].
-static int bs5_stages(ns_solver* s, const double* h, double atol, double rtol) {
-  for (int i = 1; i < 8; ++i) {
+// Stages 2..S of an attempt of the pair P (BS5: S = 8, DP5: S = 7) and the
+// fused error / diagnostics reduction, with the per-member steps in h.
+// Leaves u_{n+1} in U, f(u_{n+1}) in k[S-1], the reduction in red_out.  Needs
+// a valid k[0].
+static int embedded_stages(ns_solver* s, const Pair& P, const double* h, double atol, double rtol) {
+  const int S = P.stages;
+  for (int i = 1; i < S; ++i) {
     Combo c;
     c.nterms = 0;
     for (int j = 0; j < i; ++j) {
-      const double a = rq(BS5_A[i][j]);
+      const double a = P.a(i, j);
       if (a == 0.0) continue;
       c.src[c.nterms] = s->k[j];
       c.coef[c.nterms] = a;
@@ -248,10 +276,10 @@ static int bs5_stages(ns_solver* s, const double* h, double atol, double rtol) {
   nsk::ReduceArgs ra;
   ra.uo = s->u;
   ra.un = s->U;
-  ra.fk = s->k[7];
+  ra.fk = s->k[S - 1];
   ra.delta.nterms = 0;
-  for (int j = 0; j < 8; ++j) {
-    const double e = rq(BS5_B[j]) - rq(BS5_BH[j]);
+  for (int j = 0; j < S; ++j) {
+    const double e = rq(P.b[j]) - rq(P.bh[j]);
     if (e == 0.0) continue;
     ra.delta.src[ra.delta.nterms] = s->k[j];
     ra.delta.coef[ra.delta.nterms] = e;
@@ -308,22 +336,23 @@ static void errs_from_reductions(ns_solver* s, std::vector<double>& errs) {
   }
 }
 
-// Commit the candidate for members with accept[m] != 0: u <- U, k1 <- k8.
-static int commit_host(ns_solver* s, const std::vector<int>& accept) {
+// Commit the candidate for members with accept[m] != 0: u <- U, k1 <- k_S
+// (the last stage, FSAL).
+static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
   int nacc = 0;
   for (int a : accept) nacc += a ? 1 : 0;
   s->maskbuf = accept;
   NS_HIP(hipMemcpyAsync(s->mask_d, s->maskbuf.data(), sizeof(int) * s->g.batch, hipMemcpyHostToDevice, s->st));
   if (nacc == s->g.batch) {
     std::swap(s->u, s->U);
-    std::swap(s->k[0], s->k[7]);
+    std::swap(s->k[0], s->k[last]);
     if (s->gexec) {                            // the captured graph holds the old pointers
       (void)hipGraphExecDestroy(s->gexec);
       s->gexec = nullptr;
     }
   } else if (nacc > 0) {
     NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->mask_d, s->st));
-    NS_HIP(nsk::masked_copy(s->g, s->k[7], s->k[0], s->mask_d, s->st));
+    NS_HIP(nsk::masked_copy(s->g, s->k[last], s->k[0], s->mask_d, s->st));
   }
   if (nacc > 0) return apply_forcing(s, s->mask_d);
   return NS_OK;
@@ -332,8 +361,8 @@ static int commit_host(ns_solver* s, const std::vector<int>& accept) {
 // One attempt of ns_integrate, all on the device: stages, reduction, the
 // proposer's features (and proposal), the controller, row collection, the
 // masked commit and the forcing.  Captured once into a graph.
-static int integrate_attempt(ns_solver* s, double atol, double rtol, double t_end, int use_mlp) {
-  int rc = bs5_stages(s, s->ctl.hc, atol, rtol);
+static int integrate_attempt(ns_solver* s, const Pair& P, double atol, double rtol, double t_end, int use_mlp) {
+  int rc = embedded_stages(s, P, s->ctl.hc, atol, rtol);
   if (rc) return rc;
   const double M = (double)s->g.full;
   const bool need_x = use_mlp || s->collect;
@@ -341,12 +370,13 @@ static int integrate_attempt(ns_solver* s, double atol, double rtol, double t_en
     NS_HIP(nsk::mlp_propose(s->red_out, s->ctl.errhist, M, s->g.ncomp, s->mw, use_mlp, s->mx, s->my,
                             s->g.batch, s->st));
   const int extra = s->cfg.force_kf > 0.0 ? 1 : 0;
-  NS_HIP(nsk::control_step(s->ctl, s->red_out, M, s->g.ncomp, t_end, s->g.batch, s->my, use_mlp, extra, s->st));
+  NS_HIP(nsk::control_step(s->ctl, s->red_out, M, s->g.ncomp, t_end, s->g.batch, s->my, use_mlp, P.stages - 1,
+                           extra, s->st));
   if (s->collect)
     NS_HIP(nsk::collect_rows(s->ctl, s->mx, s->pend_x, s->pend_h, s->pend_ok, s->ring_x, s->ring_y, s->ring_n,
                              RING_CAP, s->g.batch, s->st));
   NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->ctl.accept, s->st));
-  NS_HIP(nsk::masked_copy(s->g, s->k[7], s->k[0], s->ctl.accept, s->st));
+  NS_HIP(nsk::masked_copy(s->g, s->k[P.stages - 1], s->k[0], s->ctl.accept, s->st));
   if (s->cfg.force_kf > 0.0) {
     rc = apply_forcing(s, s->ctl.accept);
     if (rc) return rc;
@@ -551,14 +581,15 @@ int ns_step_rk4(ns_solver* s, double h) {
   return apply_forcing(s, nullptr);
 }
 
-int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags, double* err_host) {
+static int step_embedded(ns_solver* s, const Pair& P, double h, double atol, double rtol, int flags,
+                         double* err_host) {
   if (!s || !std::isfinite(h) || h < 0.0 || !(atol >= 0.0) || !(rtol >= 0.0) || atol + rtol <= 0.0)
     return NS_ERR_ARG;
   if (!s->have_state) return NS_ERR_STATE;
   int rc = ensure_k1(s);
   if (rc) return rc;
   NS_HIP(nsk::fill(s->h_d, h, s->g.batch, s->st));
-  rc = bs5_stages(s, s->h_d, atol, rtol);
+  rc = embedded_stages(s, P, s->h_d, atol, rtol);
   if (rc) return rc;
   rc = fetch_reductions(s);
   if (rc) return rc;
@@ -572,9 +603,17 @@ int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags, dou
     else any_rej = true;
     if (err_host) err_host[m] = errs[m];
   }
-  rc = commit_host(s, acc);
+  rc = commit_host(s, acc, P.stages - 1);
   if (rc) return rc;
   return any_rej ? NS_STEP_REJECTED : NS_OK;
+}
+
+int ns_step_bs5(ns_solver* s, double h, double atol, double rtol, int flags, double* err_host) {
+  return step_embedded(s, PAIR_BS5, h, atol, rtol, flags, err_host);
+}
+
+int ns_step_dp5(ns_solver* s, double h, double atol, double rtol, int flags, double* err_host) {
+  return step_embedded(s, PAIR_DP5, h, atol, rtol, flags, err_host);
 }
 
 int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol, int controller,
@@ -583,6 +622,8 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
     return NS_ERR_ARG;
   const int ctrl = controller & 0xff;
   const bool use_graph = !(controller & NS_INTEGRATE_HOST);
+  const int method = (controller & NS_METHOD_DP5) ? 1 : 0;
+  const Pair& P = method ? PAIR_DP5 : PAIR_BS5;
   if (ctrl != NS_CTRL_PI && ctrl != NS_CTRL_MLP) return NS_ERR_ARG;
   if (ctrl == NS_CTRL_MLP && !s->mlp_loaded) return NS_ERR_STATE;
   if (!s->have_state) return NS_ERR_STATE;
@@ -628,7 +669,7 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
   s->st = s->cap_st;
   if (!status && use_graph) {
     const bool stale = !s->gexec || s->g_atol != atol || s->g_rtol != rtol || s->g_tend != t_end ||
-                       s->g_ctrl != ctrl || s->g_collect != (int)s->collect;
+                       s->g_ctrl != ctrl || s->g_collect != (int)s->collect || s->g_method != method;
     if (stale) {
       if (s->gexec) {
         (void)hipGraphExecDestroy(s->gexec);
@@ -639,7 +680,7 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
       if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         status = NS_ERR_HIP;
       } else {
-        rc = integrate_attempt(s, atol, rtol, t_end, use_mlp);
+        rc = integrate_attempt(s, P, atol, rtol, t_end, use_mlp);
         hipError_t ec = hipStreamEndCapture(s->st, &graph);
         if (rc) status = rc;
         else if (ec != hipSuccess) status = NS_ERR_HIP;
@@ -655,6 +696,7 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
         s->g_rtol = rtol;
         s->g_tend = t_end;
         s->g_ctrl = ctrl;
+        s->g_method = method;
         s->g_collect = (int)s->collect;
       }
     }
@@ -668,7 +710,7 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
     if (use_graph) {
       if (hipGraphLaunch(s->gexec, s->st) != hipSuccess) { status = NS_ERR_HIP; break; }
     } else {
-      rc = integrate_attempt(s, atol, rtol, t_end, use_mlp);
+      rc = integrate_attempt(s, P, atol, rtol, t_end, use_mlp);
       if (rc) { status = rc; break; }
     }
     if (hipMemcpyAsync(done_pinned + (size_t)slot * B, s->ctl.done, sizeof(int) * B, hipMemcpyDeviceToHost,

@@ -25,7 +25,8 @@ __device__ __forceinline__ double step_factor_dev(double err, bool cap_at_one) {
 }
 
 __global__ void k_control(CtlState c, const double* __restrict__ red, double M, int ncomp, double t_end,
-                          int batch, const float* __restrict__ mlp_y, int use_mlp, int extra_rhs) {
+                          int batch, const float* __restrict__ mlp_y, int use_mlp, int stage_rhs,
+                          int extra_rhs) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= batch) return;
   c.accept[m] = 0;
@@ -46,7 +47,7 @@ __global__ void k_control(CtlState c, const double* __restrict__ red, double M, 
   const bool prev_rej = c.prev_rej[m] != 0;
   const double hc = c.hc[m];
   double hnew = hc * step_factor_dev(err, ok && prev_rej);
-  c.nrhs[m] += 7;
+  c.nrhs[m] += stage_rhs;                      // new stages of the attempt (FSAL first stage reused)
   c.err[m] = err;
   c.hacc[m] = hc;
   c.clipped[m] = c.last[m];
@@ -150,9 +151,9 @@ __global__ void k_force_alpha(const double* __restrict__ red, const int* __restr
 }
 
 hipError_t control_step(const CtlState& c, const double* red, double M, int ncomp, double t_end, int batch,
-                        const float* mlp_y, int use_mlp, int extra_rhs, hipStream_t st) {
+                        const float* mlp_y, int use_mlp, int stage_rhs, int extra_rhs, hipStream_t st) {
   hipLaunchKernelGGL(k_control, dim3((batch + 63) / 64), dim3(64), 0, st, c, red, M, ncomp, t_end, batch, mlp_y,
-                     use_mlp, extra_rhs);
+                     use_mlp, stage_rhs, extra_rhs);
   return hipGetLastError();
 }
 

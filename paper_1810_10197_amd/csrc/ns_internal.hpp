@@ -141,7 +141,7 @@ struct CtlState {         // one entry per member, device memory
   long long* nrhs;
 };
 hipError_t control_step(const CtlState& c, const double* red, double M, int ncomp, double t_end, int batch,
-                        const float* mlp_y, int use_mlp, int extra_rhs, hipStream_t st);
+                        const float* mlp_y, int use_mlp, int stage_rhs, int extra_rhs, hipStream_t st);
 hipError_t control_start(const CtlState& c, double t_end, int batch, hipStream_t st);
 hipError_t collect_rows(const CtlState& c, const float* xnew, float* pend_x, double* pend_h, int* pend_ok,
                         float* ring_x, float* ring_y, long long* ring_count, int cap, int batch,

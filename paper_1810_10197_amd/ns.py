@@ -32,11 +32,12 @@ NS_CTRL_PI = 0
 NS_CTRL_MLP = 1
 NS_FORCE_COMMIT = 1
 NS_INTEGRATE_HOST = 0x100
+NS_METHOD_DP5 = 0x200
 NS_MLP_NPARAM = 5569
 NS_MLP_NWEIGHTS = 5609
 
 EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_set_nu",
-           "ns_rhs", "ns_step_rk4", "ns_step_bs5", "ns_integrate", "ns_get_time",
+           "ns_rhs", "ns_step_rk4", "ns_step_bs5", "ns_step_dp5", "ns_integrate", "ns_get_time",
            "ns_set_time", "ns_diagnostics", "ns_refresh_rhs", "ns_mlp_set_weights",
            "ns_mlp_get_weights", "ns_mlp_forward", "ns_mlp_grad", "ns_mlp_train_batch",
            "ns_mlp_reset_optimizer", "ns_mlp_collect", "ns_mlp_rows", "ns_mlp_push_rows",
@@ -89,6 +90,7 @@ _sig = {
     "ns_rhs": (_I, [_P, _P, _P]),
     "ns_step_rk4": (_I, [_P, _D]),
     "ns_step_bs5": (_I, [_P, _D, _D, _D, _I, _DP]),
+    "ns_step_dp5": (_I, [_P, _D, _D, _D, _I, _DP]),
     "ns_integrate": (_I, [_P, _D, _D, _D, _D, _I, ctypes.POINTER(NsStats)]),
     "ns_get_time": (_I, [_P, _DP]),
     "ns_set_time": (_I, [_P, _DP]),
@@ -180,6 +182,12 @@ def ns_step_rk4(h, dt):
 def ns_step_bs5(h, dt, atol, rtol, flags, err_out):
     return _check(_lib.ns_step_bs5(h, float(dt), float(atol), float(rtol), int(flags),
                                    _dptr(err_out)), "ns_step_bs5",
+                  ok=(NS_OK, NS_STEP_REJECTED))
+
+
+def ns_step_dp5(h, dt, atol, rtol, flags, err_out):
+    return _check(_lib.ns_step_dp5(h, float(dt), float(atol), float(rtol), int(flags),
+                                   _dptr(err_out)), "ns_step_dp5",
                   ok=(NS_OK, NS_STEP_REJECTED))
 
 
@@ -352,11 +360,20 @@ class Solver:
         st = ns_step_bs5(self.handle, h, atol, rtol, NS_FORCE_COMMIT if force else 0, errs)
         return st, errs
 
-    def integrate(self, t_end, h0, atol, rtol, controller="pi", graph=True):
+    def step_dp5(self, h, atol, rtol, force=False):
+        errs = np.zeros(self.batch)
+        st = ns_step_dp5(self.handle, h, atol, rtol, NS_FORCE_COMMIT if force else 0, errs)
+        return st, errs
+
+    def integrate(self, t_end, h0, atol, rtol, controller="pi", graph=True, method="bs5"):
         stats = (NsStats * self.batch)()
         ctl = {"pi": NS_CTRL_PI, "mlp": NS_CTRL_MLP}[controller]
         if not graph:
             ctl |= NS_INTEGRATE_HOST
+        if method == "dp5":
+            ctl |= NS_METHOD_DP5
+        elif method != "bs5":
+            raise ValueError("method must be 'bs5' or 'dp5'")
         ns_integrate(self.handle, t_end, h0, atol, rtol, ctl, stats)
         return [s.as_dict() for s in stats]
 

@@ -1,10 +1,12 @@
 """GPU parity of the steppers (Sec. 2.2), the embedded error norm and
 controller (Sec. 2.2.1) and the diagnostics (Sec. 3.1) against the oracle."""
+import math
+
 import numpy as np
 import pytest
 
 from gpu_util import announce, per_field_rel_l2
-from oracle import control, diagnostics, spectral, stepping
+from oracle import control, diagnostics, spectral, stepping, tableaux
 from paper_1810_10197_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -59,6 +61,42 @@ def test_bs5_attempt_and_error(ns, n, prec, tol):
     s.close()
 
 
+@pytest.mark.parametrize("n,prec,tol", [(16, "fp64", 1e-13), (32, "fp32", 1e-6)])
+def test_dp5_attempt_and_error(ns, n, prec, tol):
+    """One DP5 attempt against the oracle's (same h as the BS5 test)."""
+    announce("dp5 attempt n=%d %s" % (n, prec))
+    nu, h, atol, rtol = 0.01, 0.1, 1e-7, 1e-7
+    u0 = inputs.random_isotropic(n, 19)
+    rhs = lambda u: spectral.rhs_ns3d(u, nu)
+    s = mk(ns, n, prec, nu)
+    s.set_state(u0[None])
+    st, errs = s.step_dp5(h, atol, rtol, force=True)
+    ref = stepping.embedded_attempt(rhs, u0, h, atol, rtol, tableaux.DP5)
+    got = s.get_state().cpu().numpy()[0]
+    assert max(per_field_rel_l2(got, ref["u_new"])) <= tol
+    etol = 1e-9 if prec == "fp64" else 1e-3
+    assert abs(errs[0] / ref["err"] - 1) <= etol, (errs[0], ref["err"])
+    s.close()
+
+
+def test_dp5_linear_decay_closed_form(ns):
+    """z-independent Taylor-Green field: f = -2 nu u, so three DP5 attempts
+    multiply the state by R(-2 nu h)^3, R the pair's stability polynomial
+    (Taylor through z^5 plus z^6/600)."""
+    n, nu, h = 16, 0.05, 0.7
+    announce("dp5 linear decay n=%d" % n)
+    u0 = inputs.tgv2d_in3d(n)
+    s = mk(ns, n, "fp64", nu)
+    s.set_state(u0[None])
+    for _ in range(3):
+        s.step_dp5(h, 1e-6, 1e-6, force=True)
+    got = s.get_state().cpu().numpy()[0]
+    s.close()
+    z = -2 * nu * h
+    R = sum(z ** j / math.factorial(j) for j in range(6)) + z ** 6 / 600
+    assert np.abs(got - R ** 3 * u0).max() <= 1e-14 * np.abs(u0).max()
+
+
 def test_bs5_rejection_keeps_state(ns):
     n, nu = 16, 0.01
     announce("bs5 rejection n=%d" % n)
@@ -109,6 +147,26 @@ def test_integrate_matches_oracle_controller(ns):
     assert stats["n_accept"] == ref["n_accept"]
     assert stats["n_reject"] == ref["n_reject"]
     assert stats["n_rhs"] == ref["n_rhs"]
+    assert stats["t"] == 0.6
+    assert np.abs(got - ref["u"]).max() <= 1e-12 * np.abs(ref["u"]).max()
+    s.close()
+
+
+def test_integrate_dp5_matches_oracle_controller(ns):
+    """Adaptive DP5 (graph replay) with the Sec. 2.2.1 controller: same
+    accepted/rejected sequence, right-hand-side count and final state as the
+    oracle (FP64 RHS)."""
+    n, nu = 16, 0.01
+    announce("integrate dp5 n=%d fp64" % n)
+    u0 = inputs.random_isotropic(n, 23)
+    rhs = lambda u: spectral.rhs_ns3d(u, nu)
+    ref = control.integrate(rhs, u0, t_end=0.6, h0=0.3, atol=1e-8, rtol=1e-8, tab=tableaux.DP5)
+    s = mk(ns, n, "fp64", nu)
+    s.set_state(u0[None])
+    stats = s.integrate(0.6, 0.3, 1e-8, 1e-8, method="dp5")[0]
+    got = s.get_state().cpu().numpy()[0]
+    assert (stats["n_accept"], stats["n_reject"], stats["n_rhs"]) == \
+        (ref["n_accept"], ref["n_reject"], ref["n_rhs"])
     assert stats["t"] == 0.6
     assert np.abs(got - ref["u"]).max() <= 1e-12 * np.abs(ref["u"]).max()
     s.close()

@@ -19,6 +19,9 @@ RH_BS5 = [F(1, factorial(j)) for j in range(5)] + [
 R_RK4 = [F(1, factorial(j)) for j in range(5)]
 # R - R_hat as one polynomial, so that its value keeps full relative accuracy
 D_BS5 = [a - b for a, b in zip(R_BS5 + [F(0)], RH_BS5)]
+# DP5 (Appendix A.1): the b solution's stability polynomial is the Taylor
+# polynomial through z^5 plus z^6/600 (the published value for this pair).
+R_DP5 = [F(1, factorial(j)) for j in range(6)] + [F(1, 600)]
 
 
 def peval(c, z):
@@ -52,6 +55,22 @@ def test_linear_tgv_rk4_and_bs5_closed_form(h):
         expect = np.sqrt(2 * (abs(D) * amp / sc) ** 2 / m)
         assert abs(res["err"] - expect) < 1e-6 * expect
         assert res["errs"][2] == 0.0
+        u = res["u_new"]
+
+
+@pytest.mark.parametrize("h", [0.3, 1.0])
+def test_linear_tgv_dp5_closed_form(h):
+    """DP5 on the 2D TGV: each attempt multiplies the state by R_DP5(-2 nu h);
+    the last stage is f(u_{n+1}) (FSAL)."""
+    n, nu = 8, 0.05
+    u0 = inputs.tgv2d_in3d(n)
+    rhs = lambda u: spectral.rhs_ns3d(u, nu)
+    z = -2 * nu * h
+    u = u0.copy()
+    for step in range(3):
+        res = stepping.embedded_attempt(rhs, u, h, 1e-7, 1e-5, tableaux.DP5)
+        assert np.abs(res["u_new"] - peval(R_DP5, z) * u).max() < 1e-15
+        assert np.abs(res["k"][-1] - (-2 * nu) * res["u_new"]).max() < 1e-15
         u = res["u_new"]
 
 
