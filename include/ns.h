@@ -210,13 +210,13 @@ int ns_mlp_fit_stats(ns_solver* s);
 int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long long seed,
                  float* loss_host);
 
-/* Kernel timing with HIP events recorded around every kernel launch, on the
- * stream of the launch, while profiling is on (a tracing aid; the events add
- * a few microseconds per launch).  Index: 0..4 the five right-hand-side
- * passes (z-inverse, y-inverse, x-pass, y-forward, z-forward), 5 stage
- * combinations, 6 reductions, 7 other, 8 the whole y/x/y slab phase of a 3D
- * evaluation (wall time on the solver's stream; its passes may overlap on two
- * streams).  stop synchronises and fills total milliseconds and launch counts
+/* Kernel timing with HIP events recorded around kernel launches while
+ * profiling is on (a tracing aid; the events add a few microseconds per
+ * launch).  Index: 0..4 the five right-hand-side passes (z-inverse,
+ * y-inverse, x-pass, y-forward, z-forward; in 3D the y/x/y launches are not
+ * timed one by one), 5 stage combinations, 6 reductions, 7 other, 8 the
+ * whole y/x/y slab phase of a 3D evaluation (wall time on the solver's
+ * stream; its launches may overlap on two streams).  stop synchronises and fills total milliseconds and launch counts
  * per index. */
 #define NS_NPROF 9
 typedef struct ns_kernel_times {
@@ -235,9 +235,11 @@ int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
  * in the memory-side cache; v >= 5 uses slabs of n >> (v - 4) planes that
  * alternate between two streams and two buffers, so that one slab's passes
  * overlap the next one's.  ns_autotune times every variant of every
- * parameter on the current state (reps evaluations each, HIP events; the
- * slab schedule by the wall time of the y/x/y phase) and keeps the fastest; ms_host (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL) receives the
- * average milliseconds (0 for variants a parameter lacks).  tune_get /
+ * parameter on the current state (reps evaluations each, HIP events: the z
+ * passes per launch, the y/x/y passes and the slab schedule by the wall time
+ * of the y/x/y phase per evaluation) and keeps the fastest; ms_host
+ * (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL) receives the average
+ * milliseconds (0 for variants a parameter lacks).  tune_get /
  * tune_set read or restore the choice (e.g. from a cache).  2D solvers accept
  * the calls and ignore the choice. */
 #define NS_NTUNE 6

@@ -967,9 +967,10 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
         rc = rc ? rc : rc2;
         break;
       }
-      // a pass: per launch; the slab schedule: wall time of the y/x/y phase
+      // z passes: per launch; the y/x/y passes and the slab schedule: wall
+      // time of the y/x/y phase per evaluation
       double ms = 1e300;
-      if (p == 5) {
+      if (p == 1 || p == 2 || p == 3 || p == 5) {
         if (kt.count[nsk::PROF_SLAB]) ms = kt.ms[nsk::PROF_SLAB] / (double)kt.count[nsk::PROF_SLAB];
       } else if (kt.count[p]) {
         ms = kt.ms[p] / (double)kt.count[p];

@@ -42,21 +42,38 @@ __device__ __forceinline__ long long full_offset(const Geom& g, const Modes& md)
   return (long long)iy * nh + md.kx;
 }
 
-__global__ void k_combine(const double2* __restrict__ base, Combo c, const double* __restrict__ h,
-                          double2* __restrict__ out, long long epm, long long total) {
+// Grid of the element-wise kernels: one element per thread, blockIdx.y =
+// member (no per-element division to find the member).
+static dim3 member_grid(long long per_member, int batch) {
+  long long gx = (per_member + 255) / 256;
+  if (gx > 65535) gx = 65535;
+  if (gx < 1) gx = 1;
+  return dim3((unsigned)gx, (unsigned)batch);
+}
+
+// out = base + h_m sum_j coef_j src_j with NT terms known at compile time, so
+// that every term's load is in flight at once.
+template <int NT>
+__global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ base, Combo c,
+                                                 const double* __restrict__ h, double2* __restrict__ out,
+                                                 long long epm) {
+  const long long off = (long long)blockIdx.y * epm;
+  const double hm = h[blockIdx.y];
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const double hm = h[i / epm];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < epm; i += stride) {
+    double2 v[NT > 0 ? NT : 1];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) v[j] = c.src[j][off + i];
+    double2 r = base ? base[off + i] : make_double2(0.0, 0.0);
     double sx = 0.0, sy = 0.0;
-    for (int j = 0; j < c.nterms; ++j) {
-      const double2 v = c.src[j][i];
-      sx += c.coef[j] * v.x;
-      sy += c.coef[j] * v.y;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      sx += c.coef[j] * v[j].x;
+      sy += c.coef[j] * v[j].y;
     }
-    double2 r = base ? base[i] : make_double2(0.0, 0.0);
     r.x += hm * sx;
     r.y += hm * sy;
-    out[i] = r;
+    out[off + i] = r;
   }
 }
 
@@ -69,9 +86,15 @@ static unsigned grid_for(long long total, int bs) {
 
 hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
                    double2* out, hipStream_t st) {
-  const long long total = g.epm * g.batch;
-  hipLaunchKernelGGL(k_combine, dim3(grid_for(total, 256)), dim3(256), 0, st, base, c, h, out,
-                     g.epm, total);
+  const dim3 grid = member_grid(g.epm, g.batch);
+  switch (c.nterms) {
+#define NSK_COMBINE(k) \
+    case k: hipLaunchKernelGGL(k_combine<k>, grid, dim3(256), 0, st, base, c, h, out, g.epm); break;
+    NSK_COMBINE(0) NSK_COMBINE(1) NSK_COMBINE(2) NSK_COMBINE(3) NSK_COMBINE(4)
+    NSK_COMBINE(5) NSK_COMBINE(6) NSK_COMBINE(7) NSK_COMBINE(8) NSK_COMBINE(9)
+#undef NSK_COMBINE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -142,25 +165,53 @@ size_t reduce_scratch_bytes(const Geom& g) {
   return (size_t)reduce_blocks(g) * g.batch * NRED * sizeof(double);
 }
 
-__global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, Geom g, double* __restrict__ partials,
-                                                int nblk, int nvel) {
+// Partial sums of one member (blockIdx.y) over a fixed set of elements.  N
+// and DIM are compile-time so that decoding an element index into (component,
+// kz', ky', kx) divides by constants; NT >= 0 is the number of error terms
+// (loads all in flight), NT < 0 takes it from the arguments.
+template <int N, int DIM, int NT>
+__global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, double* __restrict__ partials, int nblk,
+                                                int nvel, int epm) {
+  constexpr int K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1;
+  constexpr int MRC = DIM == 3 ? KX * KF * KF : KX * KF;
   const int m = blockIdx.y;
   double acc[NRED];
 #pragma unroll
   for (int q = 0; q < NRED; ++q) acc[q] = 0.0;
-  const long long base = (long long)m * g.epm;
+  const long long base = (long long)m * epm;
   const double hm = a.h ? a.h[m] : 0.0;
-  const double kdiv = g.K > 0 ? (double)g.K : 1.0;
-  for (long long i = (long long)blockIdx.x * RBS + threadIdx.x; i < g.epm; i += (long long)nblk * RBS) {
+  const int nt = NT >= 0 ? NT : a.delta.nterms;
+  for (int i = blockIdx.x * RBS + threadIdx.x; i < epm; i += nblk * RBS) {
     const long long gi = base + i;
-    const Modes md = decode(g, i);
+    const int c = i / MRC;
+    int q = i - c * MRC;
+    const int kx = q % KX;
+    q /= KX;
+    const int kyp = q % KF;
+    const int ky = kyp <= K ? kyp : kyp - KF;
+    int kz = 0;
+    if (DIM == 3) {
+      const int kzp = q / KF;
+      kz = kzp <= K ? kzp : kzp - KF;
+    }
     const double2 un = a.un[gi];
-    if (a.delta.nterms > 0) {
+    if (nt > 0) {
       double dx = 0.0, dy = 0.0;
-      for (int j = 0; j < a.delta.nterms; ++j) {
-        const double2 v = a.delta.src[j][gi];
-        dx += a.delta.coef[j] * v.x;
-        dy += a.delta.coef[j] * v.y;
+      if (NT > 0) {
+        double2 v[NT > 0 ? NT : 1];
+#pragma unroll
+        for (int j = 0; j < (NT > 0 ? NT : 0); ++j) v[j] = a.delta.src[j][gi];
+#pragma unroll
+        for (int j = 0; j < (NT > 0 ? NT : 0); ++j) {
+          dx += a.delta.coef[j] * v[j].x;
+          dy += a.delta.coef[j] * v[j].y;
+        }
+      } else {
+        for (int j = 0; j < nt; ++j) {
+          const double2 v = a.delta.src[j][gi];
+          dx += a.delta.coef[j] * v.x;
+          dy += a.delta.coef[j] * v.y;
+        }
       }
       dx *= hm;
       dy *= hm;
@@ -168,21 +219,21 @@ __global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, Geom g, double* __
       const double mo = sqrt(uo.x * uo.x + uo.y * uo.y), mn = sqrt(un.x * un.x + un.y * un.y);
       const double sc = a.atol + a.rtol * (mo > mn ? mo : mn);
       const double r = (dx * dx + dy * dy) / (sc * sc);
-      acc[0] += md.c == 0 ? r : 0.0;
-      acc[1] += md.c == 1 ? r : 0.0;
-      acc[2] += md.c == 2 ? r : 0.0;
+      acc[0] += c == 0 ? r : 0.0;
+      acc[1] += c == 1 ? r : 0.0;
+      acc[2] += c == 2 ? r : 0.0;
     }
-    if (md.c < nvel) {
-      const double w = md.kx == 0 ? 1.0 : 2.0;
+    if (c < nvel) {
+      const double w = kx == 0 ? 1.0 : 2.0;
       const double e = 0.5 * w * (un.x * un.x + un.y * un.y);
       acc[3] += e;
       if (a.fk) {
         const double2 f = a.fk[gi];
         acc[4] -= w * (un.x * f.x + un.y * f.y);
       }
-      const int k2i = md.kx * md.kx + md.ky * md.ky + md.kz * md.kz;
+      const int k2i = kx * kx + ky * ky + kz * kz;
       const double kmag = sqrt((double)k2i);
-      int bin = (int)floor((16.0 * kmag) / kdiv);
+      int bin = (int)floor((16.0 * kmag) / (double)(K > 0 ? K : 1));
       bin = bin > NBINS - 1 ? NBINS - 1 : bin;
 #pragma unroll
       for (int b = 0; b < NBINS; ++b) acc[5 + b] += (b == bin) ? e : 0.0;
@@ -226,11 +277,48 @@ __global__ __launch_bounds__(RBS) void k_reduce_final(const double* __restrict__
   }
 }
 
+template <int N, int DIM>
+static void launch_reduce(const Geom& g, const ReduceArgs& a, double* partials, int nblk, int nvel,
+                          hipStream_t st) {
+  const dim3 grid(nblk, g.batch);
+  const int epm = (int)g.epm;
+  switch (a.delta.nterms) {
+    case 0: hipLaunchKernelGGL((k_reduce<N, DIM, 0>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm); break;
+    case 6: hipLaunchKernelGGL((k_reduce<N, DIM, 6>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm); break;
+    case 7: hipLaunchKernelGGL((k_reduce<N, DIM, 7>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm); break;
+    default: hipLaunchKernelGGL((k_reduce<N, DIM, -1>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm);
+  }
+}
+
 hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, double* out,
                         hipStream_t st) {
   const int nblk = reduce_blocks(g);
   const int nvel = g.dim == 3 ? 3 : 2;
-  hipLaunchKernelGGL(k_reduce, dim3(nblk, g.batch), dim3(RBS), 0, st, a, g, partials, nblk, nvel);
+  if (g.epm > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (g.dim == 3) {
+    switch (g.n) {
+      case 8: launch_reduce<8, 3>(g, a, partials, nblk, nvel, st); break;
+      case 16: launch_reduce<16, 3>(g, a, partials, nblk, nvel, st); break;
+      case 32: launch_reduce<32, 3>(g, a, partials, nblk, nvel, st); break;
+      case 64: launch_reduce<64, 3>(g, a, partials, nblk, nvel, st); break;
+      case 128: launch_reduce<128, 3>(g, a, partials, nblk, nvel, st); break;
+      case 256: launch_reduce<256, 3>(g, a, partials, nblk, nvel, st); break;
+      case 512: launch_reduce<512, 3>(g, a, partials, nblk, nvel, st); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (g.n) {
+      case 8: launch_reduce<8, 2>(g, a, partials, nblk, nvel, st); break;
+      case 16: launch_reduce<16, 2>(g, a, partials, nblk, nvel, st); break;
+      case 32: launch_reduce<32, 2>(g, a, partials, nblk, nvel, st); break;
+      case 64: launch_reduce<64, 2>(g, a, partials, nblk, nvel, st); break;
+      case 128: launch_reduce<128, 2>(g, a, partials, nblk, nvel, st); break;
+      case 256: launch_reduce<256, 2>(g, a, partials, nblk, nvel, st); break;
+      case 512: launch_reduce<512, 2>(g, a, partials, nblk, nvel, st); break;
+      case 1024: launch_reduce<1024, 2>(g, a, partials, nblk, nvel, st); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
   hipLaunchKernelGGL(k_reduce_final, dim3(g.batch), dim3(RBS), 0, st, partials, nblk, out);
   return hipGetLastError();
 }
