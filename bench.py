@@ -55,23 +55,26 @@ def measured_traffic(kernel):
     return None
 
 
-def pass_bytes(n, fp64=False):
+def pass_bytes(n, fp64=False, stage32=False):
     """Algorithmic HBM bytes of each right-hand-side pass per evaluation (one
     member): reads + writes of the retained-mode pencil model.  cb = bytes per
-    complex value in the rhs precision, 16 bytes per FP64 state value.  The
-    y/x/y passes run in slabs of z planes; one launch covers its slab's share."""
+    complex value in the rhs precision; the state is read in FP64 (16 bytes),
+    or (stage32: a stage of an FP32 step, whose input is written in FP32) in
+    FP32, and f is written in FP64.  The y/x/y passes run in slabs of z
+    planes; one launch covers its slab's share."""
     K = (n - 1) // 3
     Kf, Kx = 2 * K + 1, K + 1
     mr = Kf * Kf * Kx
     c1 = Kx * Kf * n
     c2 = Kx * n * n
     cb = 16 if fp64 else 8
+    sb = 8 if stage32 else 16
     return {
-        "zinv": 3 * mr * 16 + 6 * c1 * cb,
+        "zinv": 3 * mr * sb + 6 * c1 * cb,
         "yinv": 6 * c1 * cb + 6 * c2 * cb,
         "xpass": 6 * c2 * cb + 3 * c2 * cb,
         "yfwd": 3 * c2 * cb + 3 * c1 * cb,
-        "zfwd": 3 * c1 * cb + 3 * mr * 16 + 3 * mr * 16,
+        "zfwd": 3 * c1 * cb + 3 * mr * sb + 3 * mr * 16,
     }
 
 
@@ -585,7 +588,8 @@ def bench_throughput(args):
 
     rhs_evals = 7 * args.steps * batch
     value = rhs_evals / elapsed
-    pb = pass_bytes(n, fp64) if dim == 3 else pass_bytes_2d(n, fp64)
+    # inside the BS5 steps the 3D FP32 right-hand side reads FP32 stage inputs
+    pb = pass_bytes(n, fp64, stage32=not fp64) if dim == 3 else pass_bytes_2d(n, fp64)
     pb = {k: v * batch for k, v in pb.items()}
     n_rhs = prof["zinv"][1]                       # one first-pass launch per evaluation
     per_kernel = {}

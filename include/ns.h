@@ -229,7 +229,7 @@ int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
 /* Autotuner of the 3D right-hand side.  Parameters 0-4 are launch variants of
  * the five passes (z-inverse, y-inverse, x-pass, y-forward, z-forward): radix
  * plan (wide = few passes, narrow = at most 8 values per thread) and column
- * tile (16 or 32 columns per block).  Parameter 5 is the slab schedule of
+ * tile (16, 32 or 64 columns per block).  Parameter 5 is the slab schedule of
  * the y/x/y passes: variant v < 5 runs them over slabs of n >> v planes of z
  * (at least 1) through slab buffers that are reused, so that small slabs stay
  * in the memory-side cache; v >= 5 uses slabs of n >> (v - 4) planes that

@@ -104,7 +104,7 @@ struct Layout {
   size_t tw32, tw64, nu, h, red_out, mask, alpha, red_part;
   size_t ctl_d[6], ctl_i[7], ctl_l[3];
   size_t mw, mmom, mvel, mgrad, mloss, mx, my, pend_x, pend_h, pend_ok, ring_x, ring_y, ring_n, rows, act;
-  size_t fields[10], a1, a2, total;
+  size_t fields[10], stage32, a1, a2, total;
 };
 
 Layout make_layout(const ns_config* c) {
@@ -140,6 +140,7 @@ Layout make_layout(const ns_config* c) {
   L.rows = take((size_t)TRAIN_MAX * 4);
   L.act = take(nsk::mlp_act_floats(TRAIN_MAX) * 4);
   for (int i = 0; i < 10; ++i) L.fields[i] = take((size_t)g.epm * B * 16);
+  L.stage32 = take((size_t)g.epm * B * 8);   // FP32 stage input of an FP32 3D right-hand side
   const int fp64 = c->rhs_precision == NS_FP64;
   const size_t scratch = c->dim == 3 ? nsk::rhs3d_scratch_bytes(g, fp64) : nsk::rhs2d_scratch_bytes(g, fp64);
   const size_t cb = fp64 ? 16 : 8;
@@ -168,6 +169,7 @@ struct ns_solver {
   void* tw;          // twiddles in the rhs precision
   double2* u;        // committed state u_n (compact)
   double2* U;        // stage / candidate state
+  float2* U32;       // stage state rounded to FP32: the input of an FP32 3D right-hand side
   double2* k[8];     // stage derivatives; k[0] = f(u_n) when k1_valid
   nsk::RhsBufs rb;
   nsk::CtlState ctl;
@@ -228,8 +230,32 @@ static int rhs(ns_solver* s, const double2* U, double2* K) {
   p.nu = s->nu_d;
   p.ri = s->cfg.ri;
   p.kappa = s->cfg.kappa;
-  hipError_t e = s->g.dim == 3 ? nsk::rhs3d_compact(s->g, s->fp64, U, K, p, s->rb, s->tw, s->st)
+  hipError_t e = s->g.dim == 3 ? nsk::rhs3d_compact(s->g, s->fp64, U, nullptr, K, p, s->rb, s->tw, s->st)
                                : nsk::rhs2d_compact(s->g, s->fp64, U, K, p, s->rb, s->tw, s->st);
+  return e == hipSuccess ? NS_OK : NS_ERR_HIP;
+}
+
+// Stage inputs: an FP32 3D right-hand side rounds its input to FP32 anyway
+// (after the curl), so its stages are written once in FP32 and read in FP32
+// by the z passes (half the stage traffic); the FP64 copy is written only
+// where it is needed (the last stage of an FSAL pair is u_{n+1}).
+static bool stage32(const ns_solver* s) { return s->g.dim == 3 && !s->fp64; }
+
+// U_i = u + h sum_j c_j k_j and k_i = f(U_i); keep64: also write U_i in FP64.
+static int stage(ns_solver* s, const Combo& c, const double* h, bool keep64, double2* K) {
+  prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
+  if (stage32(s)) {
+    NS_HIP(nsk::combine2(s->g, s->u, c, h, keep64 ? s->U : nullptr, s->U32, s->st));
+  } else {
+    NS_HIP(nsk::combine(s->g, s->u, c, h, s->U, s->st));
+  }
+  prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
+  if (!stage32(s)) return rhs(s, s->U, K);
+  nsk::RhsParams p;
+  p.nu = s->nu_d;
+  p.ri = s->cfg.ri;
+  p.kappa = s->cfg.kappa;
+  const hipError_t e = nsk::rhs3d_compact(s->g, 0, nullptr, s->U32, K, p, s->rb, s->tw, s->st);
   return e == hipSuccess ? NS_OK : NS_ERR_HIP;
 }
 
@@ -267,10 +293,7 @@ static int embedded_stages(ns_solver* s, const Pair& P, const double* h, double 
       c.coef[c.nterms] = a;
       ++c.nterms;
     }
-    prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
-    NS_HIP(nsk::combine(s->g, s->u, c, h, s->U, s->st));
-    prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
-    int rc = rhs(s, s->U, s->k[i]);
+    int rc = stage(s, c, h, i == S - 1, s->k[i]);
     if (rc) return rc;
   }
   nsk::ReduceArgs ra;
@@ -420,6 +443,7 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->tw = w + (s->fp64 ? L.tw64 : L.tw32);
   s->u = (double2*)(w + L.fields[0]);
   s->U = (double2*)(w + L.fields[1]);
+  s->U32 = (float2*)(w + L.stage32);
   for (int i = 0; i < 8; ++i) s->k[i] = (double2*)(w + L.fields[2 + i]);
   s->rb.a1 = w + L.a1;
   s->rb.a2 = w + L.a2;
@@ -555,10 +579,7 @@ int ns_step_rk4(ns_solver* s, double h) {
     c.nterms = 1;
     c.src[0] = s->k[i - 1];
     c.coef[0] = stage_a[i - 1];
-    prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
-    NS_HIP(nsk::combine(s->g, s->u, c, s->h_d, s->U, s->st));
-    prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
-    rc = rhs(s, s->U, s->k[i]);
+    rc = stage(s, c, s->h_d, false, s->k[i]);
     if (rc) return rc;
   }
   Combo c;

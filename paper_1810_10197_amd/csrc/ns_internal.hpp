@@ -42,7 +42,7 @@ struct RhsBufs {
   hipStream_t side;   // second stream of the two-stream slab schedule (default priority)
   hipEvent_t fork, join;   // order `side` after / before the solver's stream
 };
-constexpr int NVARIANT_COL = 4, NVARIANT_ROW = 2, NVARIANT_SLAB = 9;
+constexpr int NVARIANT_COL = 5, NVARIANT_ROW = 2, NVARIANT_SLAB = 9;
 // 3D slab schedule of the y/x/y passes, variant v: v < 5 one stream with
 // slabs of n >> v planes; v >= 5 slabs of n >> (v - 4) planes alternating
 // between two streams and two slab buffers, so that the passes of one slab
@@ -53,9 +53,11 @@ bool slab_two_streams(int v);
 int default_slab_variant(const Geom& g, int fp64);
 
 // k = f(U) on compact FP64 buffers for every member (3D: rhs3d.hip,
-// 2D: rhs2d.hip).  tw: table of TWN twiddles in the rhs precision.
+// 2D: rhs2d.hip).  tw: table of TWN twiddles in the rhs precision.  In 3D
+// with an FP32 right-hand side the input may instead be U32, the same state
+// rounded to FP32 (U is then ignored and may be null).
 size_t rhs3d_scratch_bytes(const Geom& g, int fp64);
-hipError_t rhs3d_compact(const Geom& g, int fp64, const double2* U, double2* k,
+hipError_t rhs3d_compact(const Geom& g, int fp64, const double2* U, const float2* U32, double2* k,
                          const RhsParams& p, const RhsBufs& b, const void* tw, hipStream_t st);
 size_t rhs2d_scratch_bytes(const Geom& g, int fp64);
 hipError_t rhs2d_compact(const Geom& g, int fp64, const double2* U, double2* k,
@@ -68,9 +70,12 @@ struct Combo {
   double coef[MAXTERMS];
   int nterms;
 };
-// out = base + h_m * sum_j coef_j src_j (per member m; base may be null = 0)
+// out = base + h_m * sum_j coef_j src_j (per member m; base may be null = 0);
+// combine2 writes it to out64 and/or, rounded, to out32 (either may be null).
 hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
                    double2* out, hipStream_t st);
+hipError_t combine2(const Geom& g, const double2* base, const Combo& c, const double* h, double2* out64,
+                    float2* out32, hipStream_t st);
 
 // Full <-> compact state conversions.
 hipError_t pack_state(const Geom& g, const double2* full, double2* compact, hipStream_t st);

@@ -12,13 +12,15 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int floor_pow2(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p; }
 
 // Column passes: C adjacent columns per block (CW: requested width, 0 = the
-// default of >= 16 columns and >= 256 threads), N/E threads per column.
+// default of >= 16 columns and >= 256 threads), N/E threads per column.  A
+// request of 64 columns may use up to 160 KB of LDS (one block per CU): the
+// longer contiguous runs per row can outweigh the lower block count.
 template <class PL, typename T, int CW = 0> struct ColCfg {
   using V = cplx<T>;
   static constexpr int N = PL::N;
   static constexpr int E = PL::E;
   static constexpr int TT = N / E;
-  static constexpr int LDS_BUDGET = 80 * 1024;
+  static constexpr int LDS_BUDGET = (CW >= 64 ? 160 : 80) * 1024;
   static constexpr int C = floor_pow2(cmin(CW > 0 ? CW : cmax(256 / TT, 16),
                                            cmin(1024 / TT, LDS_BUDGET / ((N + 1) * (int)sizeof(V)))));
   static constexpr int NT = C * TT;

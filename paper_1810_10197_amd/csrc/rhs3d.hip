@@ -26,7 +26,9 @@
 //   A1  [m][6][ky'][z][kx]   written by P1, read by P2 (columns (z, kx))
 //   A2s [m][6][zl][y][kx]    slab: written by P2, read by P3 (rows (zl, y))
 //   A3s [m][3][y][zl][kx]    slab: written by P3, read by P4 (columns (zl, kx))
-//   A4  [m][3][z][ky'][kx]   written by P4, read by P5 (columns (ky', kx))
+//   A4  [m][3][z][ky'][kx]   written by P4, read by P5 (columns (ky', kx)); the
+//                            z-row pitch is padded to a multiple of 32 values so
+//                            that P5's column tiles are whole cache lines
 #include <type_traits>
 
 #include "pass_common.hpp"
@@ -46,8 +48,11 @@ static_assert(TWN == TWN_TABLE, "twiddle table length");
 // the curl) at every kz' the thread's registers hold, zero in the gap, with
 // kz per register.  No branches on lanes (band tests fold or become
 // selects), so that all of a thread's loads are in flight together.
-template <class PL, bool PAIR>
-__device__ __forceinline__ void zinv_loads(const double2* pa, const double2* pb, unsigned lane, int colc, int t,
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
+template <class PL, bool PAIR, typename UT>
+__device__ __forceinline__ void zinv_loads(const UT* pa, const UT* pb, unsigned lane, int colc, int t,
                                            double2 (&a)[PL::E], double2 (&b)[PL::E], int (&kzs)[PL::E]) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX, TT = PL::TT;
   const double2 zero2 = make_double2(0.0, 0.0);
@@ -73,12 +78,12 @@ __device__ __forceinline__ void zinv_loads(const double2* pa, const double2* pb,
       use = (e <= K) || (e >= N - K);
       const int kz = e <= K ? e : e - N;
       kzs[i] = kz;
-      off = (unsigned)(colc + (use ? (kz >= 0 ? kz : kz + KF) : 0) * NCOL) * 16u;
+      off = (unsigned)(colc + (use ? (kz >= 0 ? kz : kz + KF) : 0) * NCOL) * (unsigned)sizeof(UT);
     }
-    const double2 x = *byte_at(pa + rowb * NCOL, off);
+    const double2 x = to_d2(*byte_at(pa + rowb * NCOL, off));
     a[i] = use ? x : zero2;
     if (PAIR) {
-      const double2 y = *byte_at(pb + rowb * NCOL, off);
+      const double2 y = to_d2(*byte_at(pb + rowb * NCOL, off));
       b[i] = use ? y : zero2;
     } else {
       b[i] = zero2;
@@ -89,8 +94,8 @@ __device__ __forceinline__ void zinv_loads(const double2* pa, const double2* pb,
 // Logical block id = (member, column tile, field) with the field fastest: the
 // six blocks of one tile run on one XCD back to back and read u_hat once from
 // HBM, the rest from L2.
-template <class PL, typename T, int CW>
-__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const double2* __restrict__ U,
+template <class PL, typename T, int CW, typename UT>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __restrict__ U,
                                                              cplx<T>* __restrict__ A1, long long nblocks,
                                                              const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
@@ -118,12 +123,12 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const double2*
   // components read by field f: u_f, or the pair (a, b) of omega_f = i (ka b - kb a)
   const int ca = f < 3 ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
   const int cb = f == 3 ? 1 : (f == 4 ? 2 : 0);
-  const double2* Um = U + (long long)m * 3 * MR;
-  const unsigned lane = (unsigned)(colc + t * NCOL) * 16u;
+  const UT* Um = U + (long long)m * 3 * MR;
+  const unsigned lane = (unsigned)(colc + t * NCOL) * (unsigned)sizeof(UT);
   double2 a[E], b[E];
   int kzs[E];
-  if (f < 3) zinv_loads<PL, false>(Um + ca * MR, Um, lane, colc, t, a, b, kzs);
-  else zinv_loads<PL, true>(Um + ca * MR, Um + cb * MR, lane, colc, t, a, b, kzs);
+  if (f < 3) zinv_loads<PL, false, UT>(Um + ca * MR, Um, lane, colc, t, a, b, kzs);
+  else zinv_loads<PL, true, UT>(Um + ca * MR, Um + cb * MR, lane, colc, t, a, b, kzs);
   V v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -349,9 +354,10 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>*
   for (int i = 0; i < E; ++i) v[i] = *byte_at(in + (long long)in_base<PL>(i) * nkxs, lane);
   fft_regs<PL, -1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
+    constexpr int NCOLP = (KF * KX + 31) / 32 * 32;  // line-aligned z-row pitch of A4
     const int zl = cz / KX, kx = cz - zl * KX;
-    V* out = A4 + (bc * N + z0) * KF * KX;
-    const unsigned lo = (unsigned)(zl * KF * KX + t * KX + kx) * (unsigned)sizeof(V);
+    V* out = A4 + (bc * N + z0) * NCOLP;
+    const unsigned lo = (unsigned)(zl * NCOLP + t * KX + kx) * (unsigned)sizeof(V);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int c = out_base<PL>(i);
@@ -371,13 +377,14 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>*
 }
 
 // ---------------------------------------------------------------- P5
-template <class PL, typename T, int CW>
+template <class PL, typename T, int CW, typename UT>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>* __restrict__ A4,
-                                                           const double2* __restrict__ U,
+                                                           const UT* __restrict__ U,
                                                            double2* __restrict__ Kout,
                                                            const double* __restrict__ nu,
                                                            const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
+  constexpr int NCOLP = (NCOL + 31) / 32 * 32;      // line-aligned z-row pitch of A4
   constexpr long long MR = (long long)NCOL * KF;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
@@ -390,14 +397,14 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
   const int colc = valid ? col : 0;
   Tw<PL, V> w;
   tw_load<PL>(w, t, tw);
-  const unsigned lane = (unsigned)(colc + t * NCOL) * (unsigned)sizeof(V);
+  const unsigned lane = (unsigned)(colc + t * NCOLP) * (unsigned)sizeof(V);
   V o[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();                // LDS reuse across fields
-    const V* in = A4 + (long long)(m * 3 + c) * N * NCOL;
+    const V* in = A4 + (long long)(m * 3 + c) * N * NCOLP;
 #pragma unroll
-    for (int i = 0; i < E; ++i) o[c][i] = *byte_at(in + (long long)in_base<PL>(i) * NCOL, lane);
+    for (int i = 0; i < E; ++i) o[c][i] = *byte_at(in + (long long)in_base<PL>(i) * NCOLP, lane);
     fft_regs<PL, -1>(o[c], t, lds + lc * CF::LD, w);
   }
   if (!valid) return;
@@ -406,9 +413,10 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
   const int ky = kyp <= K ? kyp : kyp - KF;
   const double scale = 1.0 / ((double)N * (double)N * (double)N);
   const double num = nu[m];
-  const double2* Um = U + (long long)m * 3 * MR;
+  const UT* Um = U + (long long)m * 3 * MR;
   double2* Km = Kout + (long long)m * 3 * MR;
   const unsigned lo = (unsigned)(col + t * NCOL) * 16u;
+  constexpr unsigned USZ = (unsigned)sizeof(UT);
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int c = out_base<PL>(i);
@@ -422,7 +430,8 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
     const unsigned off = (bd == BAND_LO || bd == BAND_HI)
                              ? lo
                              : (unsigned)(col + (kz >= 0 ? kz : kz + KF) * NCOL) * 16u;
-    const double2* up = Um + rowb * NCOL;
+    const unsigned offu = off / 16u * USZ;       // the same element in the input's precision
+    const UT* up = Um + rowb * NCOL;
     double2* kp = Km + rowb * NCOL;
     const double n0x = (double)o[0][i].x * scale, n0y = (double)o[0][i].y * scale;
     const double n1x = (double)o[1][i].x * scale, n1y = (double)o[1][i].y * scale;
@@ -432,7 +441,8 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
     if (k2 == 0.0) {
       f0 = make_double2(0.0, 0.0); f1 = f0; f2 = f0;
     } else {
-      const double2 u0 = *byte_at(up, off), u1 = *byte_at(up + MR, off), u2 = *byte_at(up + 2 * MR, off);
+      const double2 u0 = to_d2(*byte_at(up, offu)), u1 = to_d2(*byte_at(up + MR, offu)),
+                    u2 = to_d2(*byte_at(up + 2 * MR, offu));
       const double px = (kx * n0x + ky * n1x + kz * n2x) / k2;
       const double py = (kx * n0y + ky * n1y + kz * n2y) / k2;
       const double vk = num * k2;
@@ -449,25 +459,26 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
 // ---------------------------------------------------------------- host side
 // Launch variants of each pass, chosen at run time (the autotuner times them
 // on the live workspace): column passes 0 wide plan / 16 columns, 1 wide /
-// 32, 2 narrow plan / 16, 3 narrow / 32; x-pass 0 wide, 1 narrow.  Sizes
-// below 64 always use variant 0.
+// 32, 2 narrow plan / 16, 3 narrow / 32, 4 wide / 64 (as many as the LDS
+// and the 1024-thread limit allow); x-pass 0 wide, 1 narrow.  Sizes below 64
+// always use variant 0.
 template <int N, int V> struct ColVar {
-  using PL = typename std::conditional<(V >= 2 && N >= 64), PlanS<N>, Plan<N>>::type;
-  static constexpr int CW = (V & 1) && N >= 64 ? 32 : 16;
+  using PL = typename std::conditional<(V >= 2 && V <= 3 && N >= 64), PlanS<N>, Plan<N>>::type;
+  static constexpr int CW = N < 64 ? 16 : (V == 4 ? 64 : ((V & 1) ? 32 : 16));
 };
 
 #define NSK_MARK(id, ph, stream) \
   if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, stream)
 
-template <int N, typename T, int V>
-static void launch_zinv(const Geom& g, const double2* U, cplx<T>* A1, const cplx<T>* tw, hipStream_t st) {
+template <int N, typename T, int V, typename UT>
+static void launch_zinv(const Geom& g, const UT* U, cplx<T>* A1, const cplx<T>* tw, hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = g.Kf * g.Kx;
   const long long nb = (long long)g.batch * 6 * ((ncol + CF::C - 1) / CF::C);
   const long long nbp = (nb + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_zinv<typename CV::PL, T, CV::CW>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, U, A1, nb,
-                     tw);
+  hipLaunchKernelGGL((k_zinv<typename CV::PL, T, CV::CW, UT>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, U, A1,
+                     nb, tw);
 }
 template <int N, typename T, int V>
 static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2s, int z0, int zs, const cplx<T>* tw,
@@ -496,13 +507,15 @@ static void launch_yfwd(const Geom& g, const cplx<T>* A3s, cplx<T>* A4, int z0, 
   hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch * 3),
                      dim3(CF::NT), 0, st, A3s, A4, z0, zs, tw);
 }
-template <int N, typename T, int V>
-static void launch_zfwd(const Geom& g, const cplx<T>* A4, const double2* U, double2* K, const double* nu,
+template <int N, typename T, int V, typename UT>
+static void launch_zfwd(const Geom& g, const cplx<T>* A4, const UT* U, double2* K, const double* nu,
                         const cplx<T>* tw, hipStream_t st) {
-  using CV = ColVar<N, V>;
+  // P5 holds three transformed fields: a 64-column block would exceed the
+  // registers of 1024 threads, so its variant 4 is variant 1
+  using CV = ColVar<N, V == 4 ? 1 : V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = g.Kf * g.Kx;
-  hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch),
+  hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW, UT>), dim3((ncol + CF::C - 1) / CF::C, g.batch),
                      dim3(CF::NT), 0, st, A4, U, K, nu, tw);
 }
 
@@ -520,7 +533,8 @@ static Scratch3d scratch3d(const Geom& g, int fp64) {
   Scratch3d s;
   s.a1 = 0;
   s.a4 = al256(B * 6 * n * plane * cb);
-  s.a2s[0] = s.a4 + al256(B * 3 * n * plane * cb);
+  const size_t planep = (plane + 31) / 32 * 32;       // A4's padded z-row pitch
+  s.a2s[0] = s.a4 + al256(B * 3 * n * planep * cb);
   s.a3s[0] = s.a2s[0] + al256(p2 * n);
   s.a2s[1] = s.a3s[0] + al256(p3 * n);
   s.a3s[1] = s.a2s[1] + al256(p2 * (n / 2));
@@ -543,8 +557,8 @@ int default_slab_variant(const Geom& g, int fp64) {
   return v;
 }
 
-template <int N, typename T>
-static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
+template <int N, typename T, typename UT>
+static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams& p,
                         const RhsBufs& bufs, const void* twv, hipStream_t st) {
   using V = cplx<T>;
   const V* tw = (const V*)twv;
@@ -557,10 +571,11 @@ static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsPa
   const int zs = slab_planes(g, tv[5]);
   NSK_MARK(PROF_P1, 0, st);
   switch (tv[0]) {
-    case 1: launch_zinv<N, T, 1>(g, U, A1, tw, st); break;
-    case 2: launch_zinv<N, T, 2>(g, U, A1, tw, st); break;
-    case 3: launch_zinv<N, T, 3>(g, U, A1, tw, st); break;
-    default: launch_zinv<N, T, 0>(g, U, A1, tw, st);
+    case 1: launch_zinv<N, T, 1, UT>(g, U, A1, tw, st); break;
+    case 2: launch_zinv<N, T, 2, UT>(g, U, A1, tw, st); break;
+    case 3: launch_zinv<N, T, 3, UT>(g, U, A1, tw, st); break;
+      case 4: launch_zinv<N, T, 4, UT>(g, U, A1, tw, st); break;
+    default: launch_zinv<N, T, 0, UT>(g, U, A1, tw, st);
   }
   NSK_MARK(PROF_P1, 1, st);
   // the slab phase is timed as a whole: its launches may overlap on two
@@ -582,6 +597,7 @@ static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsPa
       case 1: launch_yinv<N, T, 1>(g, A1, A2s, z0, nz, tw, ss); break;
       case 2: launch_yinv<N, T, 2>(g, A1, A2s, z0, nz, tw, ss); break;
       case 3: launch_yinv<N, T, 3>(g, A1, A2s, z0, nz, tw, ss); break;
+      case 4: launch_yinv<N, T, 4>(g, A1, A2s, z0, nz, tw, ss); break;
       default: launch_yinv<N, T, 0>(g, A1, A2s, z0, nz, tw, ss);
     }
     if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2s, A3s, nz, tw, ss);
@@ -590,6 +606,7 @@ static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsPa
       case 1: launch_yfwd<N, T, 1>(g, A3s, A4, z0, nz, tw, ss); break;
       case 2: launch_yfwd<N, T, 2>(g, A3s, A4, z0, nz, tw, ss); break;
       case 3: launch_yfwd<N, T, 3>(g, A3s, A4, z0, nz, tw, ss); break;
+      case 4: launch_yfwd<N, T, 4>(g, A3s, A4, z0, nz, tw, ss); break;
       default: launch_yfwd<N, T, 0>(g, A3s, A4, z0, nz, tw, ss);
     }
   }
@@ -601,34 +618,37 @@ static hipError_t run3d(const Geom& g, const double2* U, double2* K, const RhsPa
   NSK_MARK(PROF_SLAB, 1, st);
   NSK_MARK(PROF_P5, 0, st);
   switch (tv[4]) {
-    case 1: launch_zfwd<N, T, 1>(g, A4, U, K, p.nu, tw, st); break;
-    case 2: launch_zfwd<N, T, 2>(g, A4, U, K, p.nu, tw, st); break;
-    case 3: launch_zfwd<N, T, 3>(g, A4, U, K, p.nu, tw, st); break;
-    default: launch_zfwd<N, T, 0>(g, A4, U, K, p.nu, tw, st);
+    case 1: launch_zfwd<N, T, 1, UT>(g, A4, U, K, p.nu, tw, st); break;
+    case 2: launch_zfwd<N, T, 2, UT>(g, A4, U, K, p.nu, tw, st); break;
+    case 3: launch_zfwd<N, T, 3, UT>(g, A4, U, K, p.nu, tw, st); break;
+      case 4: launch_zfwd<N, T, 4, UT>(g, A4, U, K, p.nu, tw, st); break;
+    default: launch_zfwd<N, T, 0, UT>(g, A4, U, K, p.nu, tw, st);
   }
   NSK_MARK(PROF_P5, 1, st);
   return hipGetLastError();
 }
 #undef NSK_MARK
 
-template <typename T>
-static hipError_t dispatch3d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
+template <typename T, typename UT>
+static hipError_t dispatch3d(const Geom& g, const UT* U, double2* K, const RhsParams& p,
                              const RhsBufs& b, const void* tw, hipStream_t st) {
   switch (g.n) {
-    case 8: return run3d<8, T>(g, U, K, p, b, tw, st);
-    case 16: return run3d<16, T>(g, U, K, p, b, tw, st);
-    case 32: return run3d<32, T>(g, U, K, p, b, tw, st);
-    case 64: return run3d<64, T>(g, U, K, p, b, tw, st);
-    case 128: return run3d<128, T>(g, U, K, p, b, tw, st);
-    case 256: return run3d<256, T>(g, U, K, p, b, tw, st);
-    case 512: return run3d<512, T>(g, U, K, p, b, tw, st);
+    case 8: return run3d<8, T, UT>(g, U, K, p, b, tw, st);
+    case 16: return run3d<16, T, UT>(g, U, K, p, b, tw, st);
+    case 32: return run3d<32, T, UT>(g, U, K, p, b, tw, st);
+    case 64: return run3d<64, T, UT>(g, U, K, p, b, tw, st);
+    case 128: return run3d<128, T, UT>(g, U, K, p, b, tw, st);
+    case 256: return run3d<256, T, UT>(g, U, K, p, b, tw, st);
+    case 512: return run3d<512, T, UT>(g, U, K, p, b, tw, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t rhs3d_compact(const Geom& g, int fp64, const double2* U, double2* K, const RhsParams& p,
-                         const RhsBufs& b, const void* tw, hipStream_t st) {
-  return fp64 ? dispatch3d<double>(g, U, K, p, b, tw, st) : dispatch3d<float>(g, U, K, p, b, tw, st);
+hipError_t rhs3d_compact(const Geom& g, int fp64, const double2* U, const float2* U32, double2* K,
+                         const RhsParams& p, const RhsBufs& b, const void* tw, hipStream_t st) {
+  if (fp64) return dispatch3d<double, double2>(g, U, K, p, b, tw, st);
+  if (U32) return dispatch3d<float, float2>(g, U32, K, p, b, tw, st);
+  return dispatch3d<float, double2>(g, U, K, p, b, tw, st);
 }
 
 size_t rhs3d_scratch_bytes(const Geom& g, int fp64) { return scratch3d(g, fp64).total; }

@@ -52,11 +52,12 @@ static dim3 member_grid(long long per_member, int batch) {
 }
 
 // out = base + h_m sum_j coef_j src_j with NT terms known at compile time, so
-// that every term's load is in flight at once.
-template <int NT>
+// that every term's load is in flight at once; written in FP64 (out64)
+// and/or rounded to FP32 (out32, the stage input of an FP32 right-hand side).
+template <int NT, bool W64, bool W32>
 __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ base, Combo c,
-                                                 const double* __restrict__ h, double2* __restrict__ out,
-                                                 long long epm) {
+                                                 const double* __restrict__ h, double2* __restrict__ out64,
+                                                 float2* __restrict__ out32, long long epm) {
   const long long off = (long long)blockIdx.y * epm;
   const double hm = h[blockIdx.y];
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -73,7 +74,8 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ bas
     }
     r.x += hm * sx;
     r.y += hm * sy;
-    out[off + i] = r;
+    if (W64) out64[off + i] = r;
+    if (W32) out32[off + i] = make_float2((float)r.x, (float)r.y);
   }
 }
 
@@ -84,18 +86,34 @@ static unsigned grid_for(long long total, int bs) {
   return (unsigned)b;
 }
 
-hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
-                   double2* out, hipStream_t st) {
+template <bool W64, bool W32>
+static hipError_t combine_to(const Geom& g, const double2* base, const Combo& c, const double* h,
+                             double2* out64, float2* out32, hipStream_t st) {
   const dim3 grid = member_grid(g.epm, g.batch);
   switch (c.nterms) {
-#define NSK_COMBINE(k) \
-    case k: hipLaunchKernelGGL(k_combine<k>, grid, dim3(256), 0, st, base, c, h, out, g.epm); break;
+#define NSK_COMBINE(k)                                                                               \
+    case k:                                                                                          \
+      hipLaunchKernelGGL((k_combine<k, W64, W32>), grid, dim3(256), 0, st, base, c, h, out64, out32, \
+                         g.epm);                                                                     \
+      break;
     NSK_COMBINE(0) NSK_COMBINE(1) NSK_COMBINE(2) NSK_COMBINE(3) NSK_COMBINE(4)
     NSK_COMBINE(5) NSK_COMBINE(6) NSK_COMBINE(7) NSK_COMBINE(8) NSK_COMBINE(9)
 #undef NSK_COMBINE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
+                   double2* out, hipStream_t st) {
+  return combine_to<true, false>(g, base, c, h, out, nullptr, st);
+}
+
+hipError_t combine2(const Geom& g, const double2* base, const Combo& c, const double* h, double2* out64,
+                    float2* out32, hipStream_t st) {
+  if (out64 && out32) return combine_to<true, true>(g, base, c, h, out64, out32, st);
+  if (out32) return combine_to<false, true>(g, base, c, h, nullptr, out32, st);
+  return combine_to<true, false>(g, base, c, h, out64, nullptr, st);
 }
 
 __global__ void k_pack(const double2* __restrict__ full, double2* __restrict__ compact, Geom g,
