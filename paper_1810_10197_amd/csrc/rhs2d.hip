@@ -21,14 +21,18 @@
 namespace nsk {
 
 // ---------------------------------------------------------------- Q1
+// Column tile of Q1: the default width (narrower tiles give more blocks but
+// shorter runs per row, measured slower at 1024^2).
+template <class PL> constexpr int q1_cw() { return 0; }
+
 template <class PL, typename T>
-__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k2_yinv(const double2* __restrict__ U,
+__global__ __launch_bounds__((ColCfg<PL, T, q1_cw<PL>()>::NT)) void k2_yinv(const double2* __restrict__ U,
                                                               cplx<T>* __restrict__ B1, Geom g,
                                                               int nfield, long long nblocks,
                                                               const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<PL, T>;
+  using CF = ColCfg<PL, T, q1_cw<PL>()>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
   const long long L = xcd_logical(blockIdx.x, gridDim.x);
@@ -193,45 +197,66 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k2_xpass(const cplx<T>* _
 }
 
 // ---------------------------------------------------------------- Q3
+// One block per tile of C columns kx; the NF transformed fields of a column
+// are transformed side by side by NF thread groups (so that a 1024-point
+// column still gives enough blocks), their outputs meet in LDS, and the
+// epilogue's modes are shared out over all groups.
+template <class PL, typename T, int NF> struct Q3Cfg {
+  static constexpr int N = PL::N;
+  static constexpr int TT = N / PL::E;
+  static constexpr int LD = N + 1;
+  static constexpr int LDS_BUDGET = 160 * 1024;
+  static constexpr int C =
+      cmax(1, cmin(cmin(1024 / (TT * NF), 8), floor_pow2(LDS_BUDGET / (NF * LD * (int)sizeof(cplx<T>)))));
+  static constexpr int NT = C * TT * NF;
+};
+
 template <class PL, typename T, bool SCALAR>
-__global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k2_yfwd(const cplx<T>* __restrict__ B2,
-                                                              const double2* __restrict__ U,
-                                                              double2* __restrict__ Kout, Geom g,
-                                                              const double* __restrict__ nu,
-                                                              double ri, double kappa,
-                                                              const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2>::NT)) void k2_yfwd(const cplx<T>* __restrict__ B2,
+                                                                          const double2* __restrict__ U,
+                                                                          double2* __restrict__ Kout, Geom g,
+                                                                          const double* __restrict__ nu,
+                                                                          double ri, double kappa,
+                                                                          const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
-  using V = cplx<T>;
-  using CF = ColCfg<PL, T>;
-  constexpr int E = CF::E, C = CF::C;
   constexpr int NF = SCALAR ? 4 : 2;
-  __shared__ V lds[C * CF::LD];
-  const int lc = threadIdx.x % C, t = threadIdx.x / C;
+  using V = cplx<T>;
+  using QC = Q3Cfg<PL, T, NF>;
+  constexpr int E = PL::E, C = QC::C, TT = QC::TT, LD = QC::LD;
+  __shared__ V lds[NF * C * LD];
+  const int f = threadIdx.x / (C * TT);
+  const int rem = threadIdx.x - f * (C * TT);
+  const int lc = rem % C, t = rem / C;
   const int kx = blockIdx.x * C + lc;
   const int m = blockIdx.y;
   const bool valid = kx < g.Kx;
-  V o[NF][E];
+  V* buf = lds + (f * C + lc) * LD;
+  V o[E];
+  {
+    const V* in = B2 + ((long long)(m * 4 + f) * N) * g.Kx + (valid ? kx : 0);
 #pragma unroll
-  for (int c = 0; c < NF; ++c) {
-    if (c > 0) __syncthreads();
-    const V* in = B2 + ((long long)(m * 4 + c) * N) * g.Kx + (valid ? kx : 0);
-#pragma unroll
-    for (int i = 0; i < E; ++i) o[c][i] = in[(long long)in_pos<PL>(t, i) * g.Kx];
-    fft_regs<PL, -1>(o[c], t, lds + lc * CF::LD, tw);
+    for (int i = 0; i < E; ++i) o[i] = in[(long long)in_pos<PL>(t, i) * g.Kx];
   }
+  fft_regs<PL, -1>(o, t, buf, tw);
+  __syncthreads();                               // every group done with its exchanges
+#pragma unroll
+  for (int i = 0; i < E; ++i) buf[out_pos<PL>(t, i)] = o[i];
+  __syncthreads();
   if (!valid) return;
   const double scale = 1.0 / ((double)N * (double)N);
   const double num = nu[m];
   const long long cs = g.mr;
+  const V* col0 = lds + lc * LD;                 // field c of this column: col0 + c * C * LD
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
+  for (int i = f; i < E; i += NF) {
     const int e = out_pos<PL>(t, i);
     if (!((e <= g.K) || (e >= N - g.K))) continue;
     const int ky = e <= g.K ? e : e - N;
     const long long idx = (long long)m * g.ncomp * cs + (long long)(ky >= 0 ? ky : ky + g.Kf) * g.Kx + kx;
     const double k2 = (double)(kx * kx + ky * ky);
-    double nx = (double)o[0][i].x * scale, nxi = (double)o[0][i].y * scale;
-    double ny = (double)o[1][i].x * scale, nyi = (double)o[1][i].y * scale;
+    const V v0 = col0[e], v1 = col0[C * LD + e];
+    double nx = (double)v0.x * scale, nxi = (double)v0.y * scale;
+    double ny = (double)v1.x * scale, nyi = (double)v1.y * scale;
     if (k2 == 0.0) {
       Kout[idx] = make_double2(0.0, 0.0);
       Kout[idx + cs] = make_double2(0.0, 0.0);
@@ -251,8 +276,9 @@ __global__ __launch_bounds__((ColCfg<PL, T>::NT)) void k2_yfwd(const cplx<T>* __
     Kout[idx + cs] = make_double2(ny - ky * px - vk * u1.x, nyi - ky * py - vk * u1.y);
     if constexpr (SCALAR) {
       // -i k . q_hat - kappa |k|^2 rho_hat
-      const double sx = kx * ((double)o[2][i].x * scale) + ky * ((double)o[3][i].x * scale);
-      const double sy = kx * ((double)o[2][i].y * scale) + ky * ((double)o[3][i].y * scale);
+      const V v2 = col0[2 * C * LD + e], v3 = col0[3 * C * LD + e];
+      const double sx = kx * ((double)v2.x * scale) + ky * ((double)v3.x * scale);
+      const double sy = kx * ((double)v2.y * scale) + ky * ((double)v3.y * scale);
       const double kk2 = kappa * k2;
       Kout[idx + 2 * cs] = make_double2(sy - kk2 * rh.x, -sx - kk2 * rh.y);
     }
@@ -265,7 +291,7 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
                         const RhsBufs& bufs, const void* twv, hipStream_t st) {
   using V = cplx<T>;
   using PL = Plan<N>;
-  using CF = ColCfg<PL, T>;
+  using CF = ColCfg<PL, T, q1_cw<PL>()>;
   using RC = RowCfg<PL, T>;
   const V* tw = (const V*)twv;
   V* B1 = (V*)bufs.a1;
@@ -285,7 +311,8 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
                      dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
   NSK_MARK(PROF_P3, 1);
   NSK_MARK(PROF_P5, 0);
-  hipLaunchKernelGGL((k2_yfwd<PL, T, SCALAR>), dim3((g.Kx + CF::C - 1) / CF::C, g.batch), dim3(CF::NT), 0,
+  using QC = Q3Cfg<PL, T, SCALAR ? 4 : 2>;
+  hipLaunchKernelGGL((k2_yfwd<PL, T, SCALAR>), dim3((g.Kx + QC::C - 1) / QC::C, g.batch), dim3(QC::NT), 0,
                      st, B2, U, K, g, p.nu, p.ri, p.kappa, tw);
   NSK_MARK(PROF_P5, 1);
 #undef NSK_MARK
