@@ -104,7 +104,7 @@ struct Layout {
   size_t tw32, tw64, nu, h, red_out, mask, alpha, red_part;
   size_t ctl_d[6], ctl_i[7], ctl_l[3];
   size_t mw, mmom, mvel, mgrad, mloss, mx, my, pend_x, pend_h, pend_ok, ring_x, ring_y, ring_n, rows, act;
-  size_t fields[10], stage32, a1, a2, total;
+  size_t fields[10], stage32, dpart, a1, a2, total;
 };
 
 Layout make_layout(const ns_config* c) {
@@ -141,6 +141,7 @@ Layout make_layout(const ns_config* c) {
   L.act = take(nsk::mlp_act_floats(TRAIN_MAX) * 4);
   for (int i = 0; i < 10; ++i) L.fields[i] = take((size_t)g.epm * B * 16);
   L.stage32 = take((size_t)g.epm * B * 8);   // FP32 stage input of an FP32 3D right-hand side
+  L.dpart = take((size_t)g.epm * B * 16);    // sum_{j<S} (b_j - bh_j) k_j, from the last combination
   const int fp64 = c->rhs_precision == NS_FP64;
   const size_t scratch = c->dim == 3 ? nsk::rhs3d_scratch_bytes(g, fp64) : nsk::rhs2d_scratch_bytes(g, fp64);
   const size_t cb = fp64 ? 16 : 8;
@@ -170,6 +171,7 @@ struct ns_solver {
   double2* u;        // committed state u_n (compact)
   double2* U;        // stage / candidate state
   float2* U32;       // stage state rounded to FP32: the input of an FP32 3D right-hand side
+  double2* dpart;    // embedded difference over all stages but the last (written with u_{n+1})
   double2* k[8];     // stage derivatives; k[0] = f(u_n) when k1_valid
   nsk::RhsBufs rb;
   nsk::CtlState ctl;
@@ -241,11 +243,15 @@ static int rhs(ns_solver* s, const double2* U, double2* K) {
 // where it is needed (the last stage of an FSAL pair is u_{n+1}).
 static bool stage32(const ns_solver* s) { return s->g.dim == 3 && !s->fp64; }
 
-// U_i = u + h sum_j c_j k_j and k_i = f(U_i); keep64: also write U_i in FP64.
-static int stage(ns_solver* s, const Combo& c, const double* h, bool keep64, double2* K) {
+// U_i = u + h sum_j c_j k_j and k_i = f(U_i); keep64: also write U_i in FP64;
+// dpart (not null): also sum_j coef2_j k_j from the same loads.
+static int stage(ns_solver* s, const Combo& c, const double* h, bool keep64, double2* K,
+                 double2* dpart = nullptr) {
   prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
   if (stage32(s)) {
-    NS_HIP(nsk::combine2(s->g, s->u, c, h, keep64 ? s->U : nullptr, s->U32, s->st));
+    NS_HIP(nsk::combine2(s->g, s->u, c, h, keep64 ? s->U : nullptr, s->U32, dpart, s->st));
+  } else if (dpart) {
+    NS_HIP(nsk::combine2(s->g, s->u, c, h, s->U, nullptr, dpart, s->st));
   } else {
     NS_HIP(nsk::combine(s->g, s->u, c, h, s->U, s->st));
   }
@@ -283,6 +289,12 @@ static double forcing_kf2(const ns_solver* s) {
 // a valid k[0].
 static int embedded_stages(ns_solver* s, const Pair& P, const double* h, double atol, double rtol) {
   const int S = P.stages;
+  // The last combination (U_S = u_{n+1}, FSAL) loads every k_j the embedded
+  // difference needs except k_S, so it also writes their part of it; the
+  // reduction then reads that part and k_S instead of all stages.
+  bool fused = true;
+  for (int j = 0; j < S - 1; ++j)
+    if (rq(P.b[j]) - rq(P.bh[j]) != 0.0 && P.a(S - 1, j) == 0.0) fused = false;
   for (int i = 1; i < S; ++i) {
     Combo c;
     c.nterms = 0;
@@ -291,9 +303,11 @@ static int embedded_stages(ns_solver* s, const Pair& P, const double* h, double 
       if (a == 0.0) continue;
       c.src[c.nterms] = s->k[j];
       c.coef[c.nterms] = a;
+      c.coef2[c.nterms] = rq(P.b[j]) - rq(P.bh[j]);
       ++c.nterms;
     }
-    int rc = stage(s, c, h, i == S - 1, s->k[i]);
+    const bool last = i == S - 1;
+    int rc = stage(s, c, h, last, s->k[i], last && fused ? s->dpart : nullptr);
     if (rc) return rc;
   }
   nsk::ReduceArgs ra;
@@ -301,12 +315,20 @@ static int embedded_stages(ns_solver* s, const Pair& P, const double* h, double 
   ra.un = s->U;
   ra.fk = s->k[S - 1];
   ra.delta.nterms = 0;
-  for (int j = 0; j < S; ++j) {
-    const double e = rq(P.b[j]) - rq(P.bh[j]);
-    if (e == 0.0) continue;
-    ra.delta.src[ra.delta.nterms] = s->k[j];
-    ra.delta.coef[ra.delta.nterms] = e;
-    ++ra.delta.nterms;
+  if (fused) {
+    ra.delta.src[0] = s->dpart;
+    ra.delta.coef[0] = 1.0;
+    ra.delta.src[1] = s->k[S - 1];
+    ra.delta.coef[1] = rq(P.b[S - 1]) - rq(P.bh[S - 1]);
+    ra.delta.nterms = 2;
+  } else {
+    for (int j = 0; j < S; ++j) {
+      const double e = rq(P.b[j]) - rq(P.bh[j]);
+      if (e == 0.0) continue;
+      ra.delta.src[ra.delta.nterms] = s->k[j];
+      ra.delta.coef[ra.delta.nterms] = e;
+      ++ra.delta.nterms;
+    }
   }
   ra.h = h;
   ra.atol = atol;
@@ -444,6 +466,7 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->u = (double2*)(w + L.fields[0]);
   s->U = (double2*)(w + L.fields[1]);
   s->U32 = (float2*)(w + L.stage32);
+  s->dpart = (double2*)(w + L.dpart);
   for (int i = 0; i < 8; ++i) s->k[i] = (double2*)(w + L.fields[2 + i]);
   s->rb.a1 = w + L.a1;
   s->rb.a2 = w + L.a2;

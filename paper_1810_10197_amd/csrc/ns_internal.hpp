@@ -69,13 +69,15 @@ struct Combo {
   const double2* src[MAXTERMS];
   double coef[MAXTERMS];
   int nterms;
+  double coef2[MAXTERMS];   // second combination of the same sources (combine2's out2)
 };
 // out = base + h_m * sum_j coef_j src_j (per member m; base may be null = 0);
-// combine2 writes it to out64 and/or, rounded, to out32 (either may be null).
+// combine2 writes it to out64 and/or, rounded, to out32 (either may be null),
+// and, if out2 is not null, sum_j coef2_j src_j to out2 from the same loads.
 hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
                    double2* out, hipStream_t st);
 hipError_t combine2(const Geom& g, const double2* base, const Combo& c, const double* h, double2* out64,
-                    float2* out32, hipStream_t st);
+                    float2* out32, double2* out2, hipStream_t st);
 
 // Full <-> compact state conversions.
 hipError_t pack_state(const Geom& g, const double2* full, double2* compact, hipStream_t st);

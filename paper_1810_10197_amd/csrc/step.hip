@@ -53,11 +53,13 @@ static dim3 member_grid(long long per_member, int batch) {
 
 // out = base + h_m sum_j coef_j src_j with NT terms known at compile time, so
 // that every term's load is in flight at once; written in FP64 (out64)
-// and/or rounded to FP32 (out32, the stage input of an FP32 right-hand side).
-template <int NT, bool W64, bool W32>
+// and/or rounded to FP32 (out32, the stage input of an FP32 right-hand side);
+// with D2 also out2 = sum_j coef2_j src_j from the same loads.
+template <int NT, bool W64, bool W32, bool D2>
 __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ base, Combo c,
                                                  const double* __restrict__ h, double2* __restrict__ out64,
-                                                 float2* __restrict__ out32, long long epm) {
+                                                 float2* __restrict__ out32, double2* __restrict__ out2,
+                                                 long long epm) {
   const long long off = (long long)blockIdx.y * epm;
   const double hm = h[blockIdx.y];
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -66,16 +68,21 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ bas
 #pragma unroll
     for (int j = 0; j < NT; ++j) v[j] = c.src[j][off + i];
     double2 r = base ? base[off + i] : make_double2(0.0, 0.0);
-    double sx = 0.0, sy = 0.0;
+    double sx = 0.0, sy = 0.0, dx = 0.0, dy = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       sx += c.coef[j] * v[j].x;
       sy += c.coef[j] * v[j].y;
+      if (D2) {
+        dx += c.coef2[j] * v[j].x;
+        dy += c.coef2[j] * v[j].y;
+      }
     }
     r.x += hm * sx;
     r.y += hm * sy;
     if (W64) out64[off + i] = r;
     if (W32) out32[off + i] = make_float2((float)r.x, (float)r.y);
+    if (D2) out2[off + i] = make_double2(dx, dy);
   }
 }
 
@@ -86,15 +93,15 @@ static unsigned grid_for(long long total, int bs) {
   return (unsigned)b;
 }
 
-template <bool W64, bool W32>
+template <bool W64, bool W32, bool D2>
 static hipError_t combine_to(const Geom& g, const double2* base, const Combo& c, const double* h,
-                             double2* out64, float2* out32, hipStream_t st) {
+                             double2* out64, float2* out32, double2* out2, hipStream_t st) {
   const dim3 grid = member_grid(g.epm, g.batch);
   switch (c.nterms) {
-#define NSK_COMBINE(k)                                                                               \
-    case k:                                                                                          \
-      hipLaunchKernelGGL((k_combine<k, W64, W32>), grid, dim3(256), 0, st, base, c, h, out64, out32, \
-                         g.epm);                                                                     \
+#define NSK_COMBINE(k)                                                                                 \
+    case k:                                                                                            \
+      hipLaunchKernelGGL((k_combine<k, W64, W32, D2>), grid, dim3(256), 0, st, base, c, h, out64, out32, \
+                         out2, g.epm);                                                                 \
       break;
     NSK_COMBINE(0) NSK_COMBINE(1) NSK_COMBINE(2) NSK_COMBINE(3) NSK_COMBINE(4)
     NSK_COMBINE(5) NSK_COMBINE(6) NSK_COMBINE(7) NSK_COMBINE(8) NSK_COMBINE(9)
@@ -106,14 +113,19 @@ static hipError_t combine_to(const Geom& g, const double2* base, const Combo& c,
 
 hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
                    double2* out, hipStream_t st) {
-  return combine_to<true, false>(g, base, c, h, out, nullptr, st);
+  return combine_to<true, false, false>(g, base, c, h, out, nullptr, nullptr, st);
 }
 
 hipError_t combine2(const Geom& g, const double2* base, const Combo& c, const double* h, double2* out64,
-                    float2* out32, hipStream_t st) {
-  if (out64 && out32) return combine_to<true, true>(g, base, c, h, out64, out32, st);
-  if (out32) return combine_to<false, true>(g, base, c, h, nullptr, out32, st);
-  return combine_to<true, false>(g, base, c, h, out64, nullptr, st);
+                    float2* out32, double2* out2, hipStream_t st) {
+  if (out2) {
+    if (out64 && out32) return combine_to<true, true, true>(g, base, c, h, out64, out32, out2, st);
+    if (out64) return combine_to<true, false, true>(g, base, c, h, out64, nullptr, out2, st);
+    return hipErrorInvalidValue;               // the delta part comes with the last stage only
+  }
+  if (out64 && out32) return combine_to<true, true, false>(g, base, c, h, out64, out32, nullptr, st);
+  if (out32) return combine_to<false, true, false>(g, base, c, h, nullptr, out32, nullptr, st);
+  return combine_to<true, false, false>(g, base, c, h, out64, nullptr, nullptr, st);
 }
 
 __global__ void k_pack(const double2* __restrict__ full, double2* __restrict__ compact, Geom g,
@@ -302,6 +314,7 @@ static void launch_reduce(const Geom& g, const ReduceArgs& a, double* partials, 
   const int epm = (int)g.epm;
   switch (a.delta.nterms) {
     case 0: hipLaunchKernelGGL((k_reduce<N, DIM, 0>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm); break;
+    case 2: hipLaunchKernelGGL((k_reduce<N, DIM, 2>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm); break;
     case 6: hipLaunchKernelGGL((k_reduce<N, DIM, 6>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm); break;
     case 7: hipLaunchKernelGGL((k_reduce<N, DIM, 7>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm); break;
     default: hipLaunchKernelGGL((k_reduce<N, DIM, -1>), grid, dim3(RBS), 0, st, a, partials, nblk, nvel, epm);
