@@ -368,6 +368,151 @@ def study_e1(args):
     print(json.dumps(out))
 
 
+def study_problem(args):
+    """Time to solution on the other workloads, FP32 right-hand side, FP64
+    state.  rt2d: the 2D Boussinesq Rayleigh-Taylor problem at 1024^2 to
+    T = 4 (Ri = 0.5, nu = kappa = 1e-4): fixed-step RK4 against BS5 with the
+    Sec. 2.2.1 controller and with the proposer.  hit512: forced isotropic
+    turbulence at 512^3 (nu = 0.005, energy held at 0.125 by the rescale of
+    0 < |k| <= 2) to T = 5: BS5 with the controller against BS5 with the
+    proposer.  The error is the relative L2 of the final state against an
+    FP64 reference (RK4 at dt = 1e-4 for rt2d, BS5 at tol 1e-10 for hit512),
+    and the relative error of the kinetic energy.  An FP64-RHS BS5 arm shows
+    the method's own error: the Rayleigh-Taylor flow is unstable, so FP32
+    rounding in the right-hand side grows with the instability.  The proposer
+    is trained on the ensemble rows plus the problem itself at reduced
+    resolution (weighted ten times)."""
+    import numpy as np
+    import torch
+    from paper_1810_10197_amd import inputs, ns
+    pr = args.problem
+    if pr == "rt2d":
+        n, T, nu, dim = 1024, 4.0, 1e-4, 2
+        kw = dict(dim=2, scalar=1, ri=0.5, kappa=1e-4)
+        state = lambda nn: inputs.rayleigh_taylor2d(nn)[None]
+        train_ns, train_T, h0 = (256, 512), 4.0, 1e-3
+    else:
+        n, T, nu, dim = 512, 5.0, 0.005, 3
+        kw = dict(dim=3, force_kf=2.0, force_e0=0.125)
+        state = lambda nn: inputs.random_isotropic(nn, 1810)[None]
+        train_ns, train_T, h0 = (64, 128), 5.0, 1e-3
+    out = {"study": "time_to_solution", "problem": pr, "n": n, "T": T, "nu": nu}
+
+    def solver(prec, nn=n):
+        s = ns.Solver(n=nn, nu=nu, rhs_precision=prec, **kw)
+        s.set_state(state(nn))
+        return s
+
+    def rel_l2(a, b):
+        return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+    def energy(u):
+        # kinetic energy of the velocity components (half-spectrum weights)
+        w = np.full(u.shape[1:], 2.0)
+        w[..., 0] = 1.0
+        return 0.5 * float(np.sum(w * np.abs(u[:dim]) ** 2))
+
+    def errs(u, uref):
+        return {"rel_l2_err": rel_l2(u, uref), "rel_energy_err": abs(energy(u) - energy(uref)) / energy(uref)}
+
+    def rk4_run(dt, prec):
+        s = solver(prec)
+        steps = max(1, int(math.ceil(T / dt - 1e-9)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s.step_rk4(dt if i < steps - 1 else T - (steps - 1) * dt)
+            if (i + 1) % 5000 == 0:
+                log("rk4 %s dt=%g step %d/%d" % (prec, dt, i + 1, steps))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        u = s.get_state().cpu().numpy()[0]
+        s.close()
+        return u, wall, 4 * steps
+
+    def bs5_run(tol, prec, ctl, w=None, budget_s=150.0):
+        # quarter-unit chunks (progress lines between them); a run that
+        # exceeds its wall budget stops early and is reported as such
+        s = solver(prec)
+        if w is not None:
+            s.mlp_set_weights(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, tot = h0, {"n_rhs": 0, "n_accept": 0, "n_reject": 0}
+        nch = int(math.ceil(4 * T - 1e-9))
+        for c in range(nch):
+            st = s.integrate(min(T, 0.25 * (c + 1)), h, tol, tol, controller=ctl)[0]
+            h = st["h_next"]
+            for k in tot:
+                tot[k] += st[k]
+            log("%s %s tol=%g t=%g rhs %d rej %d" % (ctl, prec, tol, st["t"], tot["n_rhs"], tot["n_reject"]))
+            if time.perf_counter() - t0 > budget_s and c < nch - 1:
+                tot["stopped_at_t"] = st["t"]
+                break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        u = s.get_state().cpu().numpy()[0]
+        s.close()
+        return u, wall, tot
+
+    t0 = time.perf_counter()
+    if pr == "rt2d":
+        uref, _, _ = rk4_run(1e-4, "fp64")
+    else:
+        uref, _, _ = bs5_run(1e-10, "fp64", "pi")
+    out["ref_wall_s"] = time.perf_counter() - t0
+    log("reference done (%.1f s)" % out["ref_wall_s"])
+    if pr == "rt2d":
+        out["rk4_fp64"] = []
+        for dt in args.rk4_dts:
+            u, wall, nr = rk4_run(dt, "fp64")
+            out["rk4_fp64"].append({"dt": dt, "wall_s": wall, "n_rhs": nr, **errs(u, uref)})
+            log("rk4 fp64 dt=%g err %.3e / energy %.3e wall %.2f s" % (dt, out["rk4_fp64"][-1]["rel_l2_err"],
+                                                                     out["rk4_fp64"][-1]["rel_energy_err"], wall))
+    # proposer: ensemble rows plus the problem at reduced resolution
+    fields, nus = inputs.ensemble_members(args.members, 64)
+    xs, ys, _, _ = collect_rows(ns, fields, nus, 64, 2.0, (1e-5, 1e-7, 1e-9))
+    X, Y = [xs], [ys]
+    for nn in train_ns:
+        s = solver("fp32", nn)
+        s.mlp_set_weights(np.zeros(ns.NS_MLP_NWEIGHTS, dtype=np.float32))
+        s.mlp_collect(True)
+        for tol in (1e-6, 1e-7, 1e-8):
+            s.set_state(state(nn))
+            s.set_time(np.zeros(1))
+            h = h0
+            for c in range(int(math.ceil(train_T - 1e-12))):
+                st = s.integrate(min(train_T, c + 1.0), h, tol, tol)[0]
+                h = st["h_next"]
+        x2, y2, _ = s.mlp_rows()
+        s.close()
+        # the problem's own rows are few next to the ensemble's: weight them
+        X += [x2] * 10
+        Y += [y2] * 10
+        log("collect %s n=%d: %d rows" % (pr, nn, len(y2)))
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    s = ns.Solver(dim=3, n=8, nu=0.01, rhs_precision="fp32")
+    s.mlp_set_weights(_initial_weights(ns, 1810))
+    s.mlp_push_rows(X, Y)
+    s.mlp_fit_stats()
+    loss = s.mlp_train(1, 256, 1e-3, 1810)
+    for k in range(args.iters // 500):
+        loss = s.mlp_train(500, 256, 1e-3, 1811 + k)
+    w = s.mlp_get_weights()
+    s.close()
+    out["proposer_training"] = {"rows": int(len(Y)), "loss_last": loss}
+    for ctl, prec in (("pi", "fp32"), ("mlp", "fp32"), ("pi", "fp64")):
+        key = "bs5_%s_%s" % (ctl, prec)
+        out[key] = []
+        for tol in args.tols:
+            u, wall, tot = bs5_run(tol, prec, ctl, w if ctl == "mlp" else None)
+            out[key].append({"tol": tol, "wall_s": wall, **tot, **errs(u, uref)})
+            r = out[key][-1]
+            log("%s tol=%g err %.3e / energy %.3e wall %.2f s rhs %d rej %d" % (
+                key, tol, r["rel_l2_err"], r["rel_energy_err"], wall, tot["n_rhs"], tot["n_reject"]))
+    print(json.dumps(out))
+
+
 def study_tts(args):
     """Wall time to a fixed relative energy error at T on the Taylor-Green
     vortex (nu = 1/1600): plain FP64 RK4 at fixed steps (the last one clipped
@@ -467,10 +612,11 @@ def main():
                     help="comma-separated launch variants of the 5 passes and the slab (skips the autotuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter scale)")
-    ap.add_argument("--study", choices=["tts", "mlp", "e1"], default=None,
+    ap.add_argument("--study", choices=["tts", "mlp", "e1", "problem"], default=None,
                     help="tts: wall time to a fixed energy error, BS5 (+proposer) vs FP64 RK4; "
                          "mlp: what the trained proposer gains on held-out ensemble members; "
-                         "e1: Taylor-Green at Re=280, 64^3, RHS counts at equal dissipation error")
+                         "e1: Taylor-Green at Re=280, 64^3, RHS counts at equal dissipation error; "
+                         "problem: time to solution on --problem (rt2d or hit512)")
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--rk4-dts", type=float, nargs="*", default=[0.02, 0.01, 0.005, 0.0025])
@@ -481,6 +627,8 @@ def main():
     ap.add_argument("--e1-tols", type=float, nargs="*",
                     default=[1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10])
     ap.add_argument("--members", type=int, default=128)
+    ap.add_argument("--problem", choices=["rt2d", "hit512"], default="rt2d",
+                    help="--study problem: which workload")
     ap.add_argument("--workload", choices=["tgv", "ensemble", "rt2d"], default="tgv",
                     help="tgv: 3D Taylor-Green at --n; ensemble: --members x 64^3; rt2d: 2D "
                          "Boussinesq at 1024^2")
@@ -498,6 +646,8 @@ def main():
         return study_mlp(args)
     if args.study == "e1":
         return study_e1(args)
+    if args.study == "problem":
+        return study_problem(args)
     if args.calibrate_copy:
         nbytes = args.calibrate_copy * 1024 * 1024
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

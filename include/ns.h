@@ -148,9 +148,9 @@ int ns_step_dp5(ns_solver* s, double h, double atol, double rtol, int flags,
  * is captured once as a HIP graph and replayed until every member is done.
  * controller: NS_CTRL_PI or NS_CTRL_MLP (needs weights, see
  * ns_mlp_set_weights: after an accepted step the network's proposal exp(y)
- * replaces the Sec. 2.2.1 factor fac, clamped to [fac/2, min(2 fac, dmax)]
- * with dmax = 2 (1 right after a rejection), so the controller stays the
- * fallback; after a rejection, or if the proposal is not finite, fac is used),
+ * replaces the Sec. 2.2.1 factor fac, clamped to [0.7 fac, fac]: it can only
+ * shorten a step, by at most 30%, so the controller stays the fallback; after
+ * a rejection, or if the proposal is not finite, fac is used),
  * optionally or-ed with NS_INTEGRATE_HOST and with NS_METHOD_DP5 (the DP5 pair
  * of ns_step_dp5 instead of BS5).  stats_host[batch] (host, may be NULL)
  * receives the counters.  Returns NS_ERR_STEPFAIL after 50 consecutive

@@ -19,8 +19,9 @@ the run; the final step is clipped to land on t_end.  An optional PI term
 err_prev^beta (beta = 0 reproduces the paper exactly) and an optional
 proposer callable (the MLP of the step-size proposer) are supported; after an
 accepted step the proposer's factor exp(y) replaces the controller's factor
-fac, clamped to [fac / 2, min(2 fac, dmax)], so a proposer that is wrong can
-neither stall the run nor grow the step faster than dmax allows.
+fac, clamped to [0.7 fac, fac]: the proposer can only shorten a step (to avoid
+a rejection), and since 0.7 dmax > 1 a proposer that is wrong cannot hold the
+step down (at worst about 1.4 times the controller's steps).
 """
 import math
 
@@ -106,12 +107,9 @@ def integrate(rhs, u0, t_end, h0, atol, rtol, tab=tableaux.BS5,
             if proposer is not None:
                 y = proposer(u, hc, list(acc_errs))
                 if y is not None and math.isfinite(y):
-                    # the controller's factor fac bounds the proposal to
-                    # [fac / 2, min(2 fac, dmax)]: the controller stays the
-                    # fallback when the proposer is wrong
-                    dmax = 1.0 if prev_rejected else 2.0
-                    lo, hi = 0.5 * fac, min(2.0 * fac, dmax)
-                    h_new = hc * min(hi, max(lo, math.exp(y)))
+                    # the proposer may only shorten the controller's step,
+                    # by at most 30%: exp(y) is clamped to [0.7 fac, fac]
+                    h_new = hc * min(fac, max(0.7 * fac, math.exp(y)))
             err_prev = err
             prev_rejected = False
             consec = 0

@@ -7,8 +7,9 @@
 //   fac = 0.8 err^(-1/5) clamped to [0.01, dmax], dmax = 1 if the attempt
 //         is accepted right after a rejection, 2 otherwise; err = 0 gives dmax
 //   accept iff err <= 1; the next step is hc * fac, or with the learned
-//   proposer (after an accepted step) hc * clamp(exp(y), fac/2, min(2 fac, dmax)),
-//   so the controller stays the fallback when the proposer is wrong
+//   proposer (after an accepted step) hc * clamp(exp(y), 0.7 fac, fac): the
+//   proposer can only shorten a step, and 0.7 dmax > 1 keeps a wrong proposer
+//   from holding the step down
 //   the next attempt is clipped to land on t_end; 50 consecutive
 //   rejections, or a step too small to advance t, stop the member.
 #include "ns_internal.hpp"
@@ -58,10 +59,9 @@ __global__ void k_control(CtlState c, const double* __restrict__ red, double M, 
     if (use_mlp) {
       const float y = mlp_y[m];
       if (isfinite(y)) {
-        // the controller's own factor bounds the proposal: [fac/2, min(2 fac, dmax)]
+        // the proposer may only shorten the controller's step, by at most 30%
         const double fac = step_factor_dev(err, prev_rej);
-        const double dmax = prev_rej ? 1.0 : 2.0;
-        const double lo = 0.5 * fac, hi = 2.0 * fac < dmax ? 2.0 * fac : dmax;
+        const double lo = 0.7 * fac, hi = fac;
         double g = exp((double)y);
         g = g < lo ? lo : (g > hi ? hi : g);
         hnew = hc * g;

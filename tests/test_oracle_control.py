@@ -71,22 +71,22 @@ def test_clipping_lands_on_t_end(monkeypatch):
 
 def test_proposer_is_bounded_by_controller_factor(monkeypatch):
     """After an accepted step the proposal exp(y) is clamped to
-    [fac / 2, min(2 fac, dmax)] around the controller's factor fac."""
+    [0.7 fac, fac] around the controller's factor fac."""
     # err 0.5 -> fac 0.918959; err 40 rejects (fac 0.382541); err 0.9 after
-    # the rejection -> fac 0.817036 with dmax = 1; err 1e-12 -> fac 2
+    # the rejection -> fac 0.817036 (dmax = 1); err 1e-12 -> fac 2
     script = Scripted([0.5, 0.5, 40.0, 0.9, 1e-12, 1e-12] + [1e-12] * 200)
     monkeypatch.setattr(stepping, "embedded_attempt", script)
-    ys = iter([-5.0, 5.0, 5.0, -5.0, 0.1] + [0.0] * 200)
+    ys = iter([-5.0, 5.0, 5.0, -5.0, 0.5] + [0.0] * 200)
     control.integrate(None, np.zeros(2), t_end=1.0, h0=0.1, atol=1, rtol=1,
                       proposer=lambda u, h, e: next(ys))
     f05, f40, f09 = 0.918959, 0.382541, 0.817036
     expect = [0.1]
-    expect.append(expect[-1] * 0.5 * f05)          # y = -5 -> lower bound fac/2
-    expect.append(expect[-1] * 2.0 * f05)          # y = +5 -> upper bound 2 fac
+    expect.append(expect[-1] * 0.7 * f05)          # y = -5 -> lower bound 0.7 fac
+    expect.append(expect[-1] * f05)                # y = +5 -> upper bound fac
     expect.append(expect[-1] * f40)                # rejection: controller only
-    expect.append(expect[-1] * 1.0)                # y = +5 after rejection: dmax = 1
-    expect.append(expect[-1] * 1.0)                # y = -5, fac 2: fac/2 = 1
-    expect.append(expect[-1] * math.exp(0.1))      # inside the bounds: exp(y)
+    expect.append(expect[-1] * f09)                # y = +5 after rejection: fac (dmax 1)
+    expect.append(expect[-1] * 1.4)                # y = -5, fac 2: 0.7 fac = 1.4 (can grow)
+    expect.append(expect[-1] * math.exp(0.5))      # inside the bounds: exp(y)
     assert script.calls[:7] == pytest.approx(expect, rel=2e-5)
 
 
