@@ -7,7 +7,8 @@ Navier--Stokes"): the rotational form of Eq. (1b) with the modified pressure,
 the spectral ODE system of Eq. (2) whose nonlinear term u x omega is evaluated
 pointwise in physical space and transformed back (Sec. 2.1), and the
 Boussinesq system of Eqs. (3a-c), (4a-b) (Sec. 3.2).  Dealiasing uses the
-2/3 rule (see the design doc for why this replaces the 3/2 padding of Sec. 2.1.1).
+2/3 rule (rhs_ns3d, rhs_ns2d) or the 3/2-rule zero padding of Sec. 2.1.1
+(rhs_ns3d_padded).
 
 Every function works on the full half-spectrum layout; shapes are
 (C, N, N, N//2+1) in 3D and (C, N, N//2+1) in 2D, complex128.
@@ -189,6 +190,94 @@ def rhs_ns3d(uh, nu):
     # k = 0: the projection is undefined there; the mean of u x omega over a
     # periodic box vanishes for a solenoidal field, so the mean velocity is
     # held fixed (f(0) = 0) rather than fed with rounding noise.
+    f[:, 0, 0, 0] = 0.0
+    return f
+
+
+# ---------------------------------------------------------------------------
+# 3/2-rule dealiasing (Sec. 2.1.1): the velocity and vorticity spectra are
+# padded with zeros to 3N/2 frequencies per direction, the product is formed
+# on the (3N/2)^3 grid, and the result is truncated back to N frequencies.
+# ---------------------------------------------------------------------------
+
+def cutoff_padded(n):
+    """Largest retained |k_j| of the 3/2 rule on an N grid: N/2 - 1.
+
+    Of the N frequencies -N/2..N/2-1 kept per direction, the Nyquist one
+    (-N/2, which has no +N/2 partner) is held at zero: the retained set is
+    then symmetric and a real field stays real.
+    """
+    return n // 2 - 1
+
+
+def padded_size(n):
+    """Points per direction of the padded grid, 3N/2."""
+    return 3 * n // 2
+
+
+def mask_padded(n):
+    """Boolean mask of the retained modes (every |k_j| <= N/2 - 1), 3D."""
+    K = cutoff_padded(n)
+    kx, ky, kz = wavenumbers(n, 3)
+    return (np.abs(kx) <= K) & (np.abs(ky) <= K) & (np.abs(kz) <= K)
+
+
+def _band_index(n, K):
+    """Positions of the wavenumbers -K..K along a full axis of length n."""
+    return np.arange(-K, K + 1) % n
+
+
+def pad_spectrum(uh, n, m):
+    """N-grid half spectra (C, N, N, N//2+1) -> M-grid ones (M > N), zeros
+    outside the retained set of the 3/2 rule.  Coefficients are copied
+    unscaled: with the normalised convention a mode's value does not depend
+    on the grid it is sampled on."""
+    K = cutoff_padded(n)
+    out = np.zeros(uh.shape[:-3] + (m, m, m // 2 + 1), dtype=np.complex128)
+    src = np.ix_(_band_index(n, K), _band_index(n, K), np.arange(K + 1))
+    dst = np.ix_(_band_index(m, K), _band_index(m, K), np.arange(K + 1))
+    for c in range(uh.shape[0]):
+        out[c][dst] = uh[c][src]
+    return out
+
+
+def truncate_spectrum(vh, m, n):
+    """M-grid half spectra -> N-grid ones, keeping the retained set of the
+    3/2 rule on N and zeros elsewhere (the inverse of pad_spectrum on it)."""
+    K = cutoff_padded(n)
+    out = np.zeros(vh.shape[:-3] + (n, n, n // 2 + 1), dtype=np.complex128)
+    src = np.ix_(_band_index(m, K), _band_index(m, K), np.arange(K + 1))
+    dst = np.ix_(_band_index(n, K), _band_index(n, K), np.arange(K + 1))
+    for c in range(vh.shape[0]):
+        out[c][dst] = vh[c][src]
+    return out
+
+
+def rhs_ns3d_padded(uh, nu):
+    """f(u_hat) of Eq. (2) with the nonlinear term dealiased by the 3/2 rule.
+
+    1. u_hat restricted to the retained set; omega_hat = i k x u_hat;
+    2. both padded with zeros to M = 3N/2 frequencies per direction;
+    3. u and omega on the M^3 grid (inverse real DFT); u x omega pointwise;
+    4. forward DFT on the M^3 grid (normalised by M^3), truncated to the
+       retained set of the N grid;
+    5. projection and viscous term as in rhs_ns3d, with f(0) = 0.
+    """
+    n = uh.shape[1]
+    m = padded_size(n)
+    keep = mask_padded(n)
+    u0 = uh * keep
+    up = pad_spectrum(u0, n, m)
+    wp = pad_spectrum(curl3(u0, n), n, m)
+    u = inverse(up, m, 3)
+    w = inverse(wp, m, 3)
+    nl = truncate_spectrum(forward(cross3(u, w), 3), m, n)
+    kx, ky, kz = wavenumbers(n, 3)
+    k2 = kx * kx + ky * ky + kz * kz
+    k2safe = np.where(k2 == 0, 1.0, k2)
+    p = (kx * nl[0] + ky * nl[1] + kz * nl[2]) / k2safe
+    p = np.where(k2 == 0, 0.0, p)
+    f = np.stack([nl[0] - kx * p, nl[1] - ky * p, nl[2] - kz * p]) - nu * k2 * u0
     f[:, 0, 0, 0] = 0.0
     return f
 

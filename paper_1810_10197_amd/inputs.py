@@ -6,7 +6,8 @@ side: it only builds initial states in the half-spectrum layout of the C ABI,
 complex128 arrays of shape (3, N, N, N//2+1) in 3D ([kz][ky][kx], kx = 0..N/2)
 and (C, N, N//2+1) in 2D ([ky][kx]), normalised so that physical values are
 sum_k u_hat_k exp(i k.x).  Only modes with every |k_j| <= (N-1)//3 are
-populated.
+populated (random fields take a wider band on request: |k_j| <= N/2 - 1 is
+the retained set of the 3/2 rule).
 
 * Taylor--Green vortex (Sec. 3.1): u = sin x cos y cos z,
   v = -cos x sin y cos z, w = 0 -- written from its eight Fourier
@@ -30,9 +31,9 @@ def cutoff(n):
     return (n - 1) // 3
 
 
-def _kidx(n):
+def _kidx(n, K=None):
     """Signed retained wavenumbers and their storage index on a full axis."""
-    K = cutoff(n)
+    K = cutoff(n) if K is None else K
     ks = np.arange(-K, K + 1)
     return ks, ks % n
 
@@ -69,11 +70,11 @@ def tgv2d(n, with_density=False):
     return u
 
 
-def _hermitian_kx0(a, n):
+def _hermitian_kx0(a, n, K=None):
     """Make the kx = 0 plane of a (C, N, N, h) field Hermitian:
     a(0, -ky, -kz) = conj(a(0, ky, kz)), a(0,0,0) = 0.  The canonical half is
     ky > 0, or ky = 0 and kz > 0."""
-    ks, idx = _kidx(n)
+    ks, idx = _kidx(n, K)
     for ky, iy in zip(ks, idx):
         for kz, iz in zip(ks, idx):
             if ky > 0 or (ky == 0 and kz > 0):
@@ -89,11 +90,14 @@ def _energy_scale(u, e0):
     return u * np.sqrt(e0 / e)
 
 
-def random_isotropic(n, seed, k0=3.0, e0=0.125):
-    """Random-phase solenoidal field with shell energy ~ k^4 exp(-2 (k/k0)^2)."""
-    K = cutoff(n)
+def random_isotropic(n, seed, k0=3.0, e0=0.125, band=None):
+    """Random-phase solenoidal field with shell energy ~ k^4 exp(-2 (k/k0)^2)
+    on the modes |k_j| <= band (default (N-1)//3)."""
+    K = cutoff(n) if band is None else band
+    if not 0 <= K <= n // 2 - 1:
+        raise ValueError("band must lie in 0..n/2-1")
     rng = np.random.Generator(np.random.PCG64(seed))
-    ks, idx = _kidx(n)
+    ks, idx = _kidx(n, K)
     kx = np.arange(0, K + 1)
     KZ, KY, KX = np.meshgrid(ks, ks, kx, indexing="ij")
     kmag = np.sqrt(KX * KX + KY * KY + KZ * KZ)
@@ -109,7 +113,7 @@ def random_isotropic(n, seed, k0=3.0, e0=0.125):
     sel = np.ix_(idx, idx, np.arange(K + 1))
     for c, comp in enumerate((ux, uy, uz)):
         u[c][sel] = comp
-    u = _hermitian_kx0(u, n)
+    u = _hermitian_kx0(u, n, K)
     return _energy_scale(u, e0)
 
 

@@ -68,3 +68,15 @@ def test_mistyped_tableau_entry_is_caught(monkeypatch):
     A[5][3] = F(58653, 366081)
     bad = dict(tableaux.BS5, A=A)
     assert _fails(tt.test_main_weights_order, bad, 5) or _fails(tt.test_row_sums_equal_c, bad, "x")
+
+
+def test_unpadded_product_is_caught(monkeypatch):
+    # forming the product on the N grid itself lets aliases reach retained modes
+    monkeypatch.setattr(spectral, "padded_size", lambda n: n)
+    assert _fails(ts.test_padded_rhs_against_direct_convolution, 8, 21)
+
+
+def test_padding_that_keeps_the_nyquist_mode_is_caught(monkeypatch):
+    # a truncation that keeps |k_j| <= N/2 (Nyquist included) breaks the zero pattern
+    monkeypatch.setattr(spectral, "cutoff_padded", lambda n: n // 2)
+    assert _fails(ts.test_padded_rhs_against_direct_convolution, 8, 21)

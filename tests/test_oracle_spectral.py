@@ -219,3 +219,104 @@ def test_dealiased_product_is_exact_truncation(n, seed):
     expect = exact - np.stack([kx * p, ky * p, kz * p])
     expect[:, 0, 0, 0] = 0.0          # mean mode held fixed
     assert np.abs(spectral.rhs_ns3d(uh, 0.0) - expect).max() < 1e-13 * np.abs(expect).max()
+
+
+# ---------------------------------------------------------------- 3/2 rule
+def _real_band_limited(n, K, seed):
+    """A random real solenoidal velocity with every |k_j| <= K (half spectrum)."""
+    rng = np.random.default_rng(seed)
+    kx, ky, kz = spectral.wavenumbers(n, 3)
+    keep = (np.abs(kx) <= K) & (np.abs(ky) <= K) & (np.abs(kz) <= K)
+    shape = (3,) + keep.shape
+    uh = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * keep
+    uh = spectral.forward(spectral.inverse(uh, n, 3), 3) * keep     # a real field
+    k2 = kx * kx + ky * ky + kz * kz
+    div = (kx * uh[0] + ky * uh[1] + kz * uh[2]) / np.where(k2 == 0, 1, k2)
+    return uh - np.stack([kx * div, ky * div, kz * div])
+
+
+def _full_cube(uh, n, K):
+    """Coefficients c[:, kz+K, ky+K, kx+K] of every mode with |k_j| <= K,
+    the kx < 0 half from conj(u_hat(-k)) of a real field."""
+    ks = range(-K, K + 1)
+    L = 2 * K + 1
+    out = np.zeros((uh.shape[0], L, L, L), dtype=complex)
+    for a, kz in enumerate(ks):
+        for b, ky in enumerate(ks):
+            for c, kx in enumerate(ks):
+                if kx >= 0:
+                    out[:, a, b, c] = uh[:, kz % n, ky % n, kx]
+                else:
+                    out[:, a, b, c] = np.conj(uh[:, (-kz) % n, (-ky) % n, -kx])
+    return out
+
+
+@pytest.mark.parametrize("n,seed", [(8, 21), (10, 22)])
+def test_padded_rhs_against_direct_convolution(n, seed):
+    """The 3/2 rule forms the product of the two truncated Fourier series
+    exactly: on every retained mode the nonlinear term equals the direct
+    convolution sum_{p+q=k} u_hat(p) x omega_hat(q) over the retained set
+    (no transform involved), followed by the projection and the viscous
+    term of Eq. (2)."""
+    K = n // 2 - 1
+    L = 2 * K + 1
+    uh = _real_band_limited(n, K, seed)
+    U = _full_cube(uh, n, K)
+    k = np.arange(-K, K + 1)
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    W = 1j * np.stack([KY * U[2] - KZ * U[1], KZ * U[0] - KX * U[2], KX * U[1] - KY * U[0]])
+    conv = np.zeros_like(U)
+    for a in range(L):
+        za, zb = max(0, a - K), min(L, a + K + 1)
+        for b in range(L):
+            ya, yb = max(0, b - K), min(L, b + K + 1)
+            for c in range(L):
+                xa, xb = max(0, c - K), min(L, c + K + 1)
+                p = U[:, a, b, c]
+                q = W[:, za - a + K:zb - a + K, ya - b + K:yb - b + K, xa - c + K:xb - c + K]
+                conv[:, za:zb, ya:yb, xa:xb] += np.stack([p[1] * q[2] - p[2] * q[1],
+                                                          p[2] * q[0] - p[0] * q[2],
+                                                          p[0] * q[1] - p[1] * q[0]])
+    nu = 0.03
+    expect = np.zeros_like(uh)
+    for a, kz in enumerate(k):
+        for b, ky in enumerate(k):
+            for c in range(K, L):
+                kx = c - K
+                nl = conv[:, a, b, c]
+                kk = kx * kx + ky * ky + kz * kz
+                if kk == 0:
+                    continue                      # mean mode held fixed
+                kv = np.array([kx, ky, kz], dtype=float)
+                expect[:, kz % n, ky % n, kx] = nl - kv * (kv @ nl) / kk - nu * kk * uh[:, kz % n, ky % n, kx]
+    got = spectral.rhs_ns3d_padded(uh, nu)
+    assert np.abs(got - expect).max() < 1e-13 * np.abs(expect).max()
+    # the Nyquist planes and everything past K stay zero
+    assert np.all(got[:, ~spectral.mask_padded(n)] == 0.0)
+
+
+def test_padded_rhs_equals_two_thirds_rule_on_the_padded_grid():
+    """(3N/2 - 1)/3 rounds down to N/2 - 1, so the 2/3 rule on the 3N/2 grid
+    keeps the same modes and forms the same product: both right-hand sides
+    agree once moved onto a common grid."""
+    n = 16
+    m = spectral.padded_size(n)
+    uh = _real_band_limited(n, n // 2 - 1, 31)
+    assert spectral.cutoff(m) == spectral.cutoff_padded(n)
+    big = spectral.rhs_ns3d(spectral.pad_spectrum(uh, n, m), 0.02)
+    got = spectral.rhs_ns3d_padded(uh, 0.02)
+    assert np.abs(spectral.truncate_spectrum(big, m, n) - got).max() < 1e-13 * np.abs(got).max()
+
+
+def test_padded_rhs_inviscid_invariants():
+    """The 3/2-rule system is a Galerkin truncation: with nu = 0 it conserves
+    energy and helicity exactly."""
+    n = 16
+    u = _real_band_limited(n, n // 2 - 1, 41) * 0.1
+    f = spectral.rhs_ns3d_padded(u, 0.0)
+    w = diagnostics.weights(n, 3)
+    om = spectral.curl3(u, n)
+    scale = np.sqrt(np.sum(w * np.abs(u) ** 2)) * np.sqrt(np.sum(w * np.abs(f) ** 2))
+    scale_h = np.sqrt(np.sum(w * np.abs(om) ** 2)) * np.sqrt(np.sum(w * np.abs(f) ** 2))
+    assert abs(np.sum(w * np.real(np.conj(u) * f).sum(0))) < 1e-14 * scale
+    assert abs(np.sum(w * np.real(np.conj(om) * f).sum(0))) < 1e-14 * scale_h
