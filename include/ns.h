@@ -7,7 +7,8 @@
  * (Sec. 2.1, Eq. (2)):  d u_hat / dt = f(u_hat), with
  *
  *   f(u_hat) = N_hat - k (k . N_hat) / |k|^2 - nu |k|^2 u_hat,
- *   N_hat    = 2/3-dealiased DFT of u x omega evaluated in physical space,
+ *   N_hat    = dealiased DFT of u x omega evaluated in physical space
+ *              (2/3 rule, or the 3/2-rule padding of Sec. 2.1.1),
  *
  * and, in two dimensions, the Boussinesq system of Sec. 3.2, Eqs. (3a-c),
  * (4a-b).  Steppers: classical RK4 with a fixed step and the Bogacki--Shampine
@@ -22,9 +23,11 @@
  * i.e. numpy.fft.rfftn of the physical field over its spatial axes divided by
  * n^dim (the normalised transform; physical values are sum_k u_hat e^{ik.x}).
  * Full axes hold wavenumbers 0..n/2-1, -n/2..-1; the last axis 0..n/2.  Only
- * modes with every |k_j| <= K = (n-1)/3 (2/3 rule) are read; the library
- * writes zeros everywhere else.  The kx = 0 plane must be Hermitian (a real
- * field).  Internally the solver keeps only the retained modes.
+ * modes with every |k_j| <= K are read; the library writes zeros everywhere
+ * else.  K = (n-1)/3 under the 2/3 rule (NS_DEALIAS_23); K = n/2 - 1 under
+ * the 3/2 rule (NS_DEALIAS_32), whose products are formed on the zero-padded
+ * (3n/2)^dim grid.  The kx = 0 plane must be Hermitian (a real field).
+ * Internally the solver keeps only the retained modes.
  *
  * Memory ownership: the caller owns every device buffer (state, f, the
  * workspace); the solver keeps non-owning pointers and never frees caller
@@ -59,6 +62,10 @@ extern "C" {
 #define NS_ERR_UNSUPPORTED (-6) /* size or mode not built */
 #define NS_ERR_STATE (-7)       /* call out of order (e.g. no state set) */
 
+#define NS_DEALIAS_23 0         /* 2/3 rule: |k_j| <= (n-1)/3, products on the n grid */
+#define NS_DEALIAS_32 1         /* 3/2 rule (Sec. 2.1.1): |k_j| <= n/2-1, products on
+                                   the zero-padded 3n/2 grid, truncated back */
+
 #define NS_FP32 0               /* FFTs and nonlinear term in float */
 #define NS_FP64 1               /* FFTs and nonlinear term in double */
 
@@ -83,6 +90,7 @@ typedef struct ns_config {
   double kappa;         /* Boussinesq scalar diffusivity */
   double force_kf;      /* 3D: forcing band 0 < |k| <= kf after each accepted step; <= 0 off */
   double force_e0;      /* energy the forcing restores */
+  int dealias;          /* NS_DEALIAS_23, or NS_DEALIAS_32 (3D, n = 16..512) */
 } ns_config;
 
 typedef struct ns_solver ns_solver;

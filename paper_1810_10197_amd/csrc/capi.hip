@@ -75,6 +75,8 @@ bool valid_config(const ns_config* c) {
   if (c->dim != 2 && c->dim != 3) return false;
   const int maxn = c->dim == 3 ? 512 : 1024;
   if (c->n < 8 || c->n > maxn || (c->n & (c->n - 1))) return false;
+  if (c->dealias != NS_DEALIAS_23 && c->dealias != NS_DEALIAS_32) return false;
+  if (c->dealias == NS_DEALIAS_32 && (c->dim != 3 || c->n < 16)) return false;
   if (c->batch < 1 || c->batch > 65535) return false;
   if (c->rhs_precision != NS_FP32 && c->rhs_precision != NS_FP64) return false;
   if (c->scalar != 0 && !(c->dim == 2 && c->scalar == 1)) return false;
@@ -88,14 +90,18 @@ bool valid_config(const ns_config* c) {
 Geom make_geom(const ns_config* c) {
   Geom g;
   g.dim = c->dim;
-  g.n = c->n;
-  g.K = (c->n - 1) / 3;
+  g.nf = c->n;
+  // The 3/2 rule on n: products on the padded 3n/2 grid, modes |k_j| <= n/2 - 1
+  // kept -- the same computation as the 2/3 rule on 3n/2, whose (3n/2 - 1)/3
+  // rounds down to n/2 - 1.
+  g.n = c->dealias == NS_DEALIAS_32 ? 3 * c->n / 2 : c->n;
+  g.K = (g.n - 1) / 3;
   g.Kf = 2 * g.K + 1;
   g.Kx = g.K + 1;
   g.ncomp = c->dim == 3 ? 3 : (c->scalar ? 3 : 2);
   g.mr = (long long)g.Kx * g.Kf * (c->dim == 3 ? g.Kf : 1);
   g.epm = g.mr * g.ncomp;
-  g.full = (long long)(c->n / 2 + 1) * c->n * (c->dim == 3 ? c->n : 1);
+  g.full = (long long)(g.nf / 2 + 1) * g.nf * (c->dim == 3 ? g.nf : 1);
   g.batch = c->batch;
   return g;
 }

@@ -10,8 +10,9 @@
 // j + r*N/R of butterfly j and writes element (j/NS)*NS*R + j%NS + r*NS; the
 // output comes out in natural order.
 //
-// Twiddles come from a table of exp(-2 pi i m / TWN), m < TWN, computed on
-// the host in double precision (std::cos/std::sin) and rounded once; a pass
+// Lengths are 2^k, or 3 * 2^k with a radix-24 (3 x 8) first pass.  Twiddles
+// come from a table of exp(-2 pi i m / TWN), m < TWN, computed on the host in
+// double precision (std::cos/std::sin) and rounded once; a pass
 // with radix R loads log2(R) entries per butterfly and multiplies them
 // together for the rest (see Tw below).  The
 // radix-8/16 butterfly constants are cos/sin of multiples of pi/8, written
@@ -22,7 +23,7 @@
 
 namespace nsk {
 
-constexpr int TWN = 1024;   // twiddle table length; every N divides it
+constexpr int TWN = 3072;   // twiddle table length; every N (2^k and 3 * 2^k) divides it
 
 template <typename T> struct cx;
 template <> struct cx<float> { using type = float2; };
@@ -116,6 +117,70 @@ template <int R, int DIR, typename V> struct DftSplit {
 template <int DIR, typename V> struct Dft<8, DIR, V> : DftSplit<8, DIR, V> {};
 template <int DIR, typename V> struct Dft<16, DIR, V> : DftSplit<16, DIR, V> {};
 
+// sqrt(3)/2 = sin(pi/3); cos and sin of multiples of 2 pi / 24 (15 degrees)
+// from the closed forms cos(pi/12) = (sqrt 6 + sqrt 2)/4, sin(pi/12) =
+// (sqrt 6 - sqrt 2)/4, cos(pi/6) = sqrt(3)/2, cos(pi/4) = sqrt(2)/2.
+#define NSK_S3 0.86602540378443864676
+#define NSK_C15 0.96592582628906828675
+#define NSK_S15 0.25881904510252076235
+__device__ __forceinline__ double cos24(int k) {
+  switch (((k % 24) + 24) % 24) {
+    case 0: return 1.0; case 1: return NSK_C15; case 2: return NSK_S3; case 3: return NSK_C2;
+    case 4: return 0.5; case 5: return NSK_S15; case 6: return 0.0; case 7: return -NSK_S15;
+    case 8: return -0.5; case 9: return -NSK_C2; case 10: return -NSK_S3; case 11: return -NSK_C15;
+    case 12: return -1.0; case 13: return -NSK_C15; case 14: return -NSK_S3; case 15: return -NSK_C2;
+    case 16: return -0.5; case 17: return -NSK_S15; case 18: return 0.0; case 19: return NSK_S15;
+    case 20: return 0.5; case 21: return NSK_C2; case 22: return NSK_S3; default: return NSK_C15;
+  }
+}
+__device__ __forceinline__ double sin24(int k) { return cos24(k - 6); }
+
+// 3-point DFT: X1,2 = a - (b + c)/2 +- DIR i (sqrt(3)/2) (b - c).
+template <int DIR, typename V> struct Dft<3, DIR, V> {
+  static __device__ __forceinline__ void run(V* v) {
+    using T = decltype(V::x);
+    const T h = (T)0.5, r3 = (T)NSK_S3;
+    const V a = v[0], t1 = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    const V t2 = mk<V>(a.x - h * t1.x, a.y - h * t1.y);
+    const V t3 = mul_si<DIR>(mk<V>(r3 * d.x, r3 * d.y));
+    v[0] = cadd(a, t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  }
+};
+
+// 24-point DFT as 3 x 8: with n = n1 + 3 n2 and k = 8 k1 + k2, eight-point
+// transforms over n2 for each n1, the twiddles w_24^(n1 k2), then
+// three-point transforms over n1 for each k2.
+template <int DIR, typename V> struct Dft<24, DIR, V> {
+  static __device__ __forceinline__ void run(V* v) {
+    using T = decltype(V::x);
+    V y[3][8];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+#pragma unroll
+      for (int n2 = 0; n2 < 8; ++n2) y[n1][n2] = v[n1 + 3 * n2];
+      Dft<8, DIR, V>::run(y[n1]);
+    }
+#pragma unroll
+    for (int n1 = 1; n1 < 3; ++n1) {
+#pragma unroll
+      for (int k2 = 1; k2 < 8; ++k2) {
+        const int m = n1 * k2;
+        const V w = mk<V>((T)cos24(m), (T)(DIR * sin24(m)));
+        y[n1][k2] = cmul(y[n1][k2], w);
+      }
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+      V z[3] = {y[0][k2], y[1][k2], y[2][k2]};
+      Dft<3, DIR, V>::run(z);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) v[8 * k1 + k2] = z[k1];
+    }
+  }
+};
+
 // Radix plans: a transform of length N in P passes of radices R0, R1, R2
 // (R0 = E, the values each thread holds; N/E threads per transform).
 template <int N_, int E_, int P_, int R0_, int R1_, int R2_> struct PlanT {
@@ -123,6 +188,7 @@ template <int N_, int E_, int P_, int R0_, int R1_, int R2_> struct PlanT {
   static constexpr int TT = N / E;
   static constexpr int RL = P == 1 ? R0 : (P == 2 ? R1 : R2);   // last radix
   static_assert(R0 * R1 * R2 == N && R0 == E, "radix plan");
+  static_assert((R1 & (R1 - 1)) == 0 && (R2 & (R2 - 1)) == 0, "later passes have power-of-two radices");
 };
 // Wide plans: few passes, up to 16 values per thread.
 template <int N> struct Plan;
@@ -134,6 +200,13 @@ template <> struct Plan<128>  : PlanT<128, 16, 2, 16, 8, 1> {};
 template <> struct Plan<256>  : PlanT<256, 16, 2, 16, 16, 1> {};
 template <> struct Plan<512>  : PlanT<512, 8, 3, 8, 8, 8> {};
 template <> struct Plan<1024> : PlanT<1024, 16, 3, 16, 16, 4> {};
+// 3 * 2^k (the 3/2-padded grids of n = 2^(k+1)): a radix-24 first pass.
+template <> struct Plan<24>   : PlanT<24, 24, 1, 24, 1, 1> {};
+template <> struct Plan<48>   : PlanT<48, 24, 2, 24, 2, 1> {};
+template <> struct Plan<96>   : PlanT<96, 24, 2, 24, 4, 1> {};
+template <> struct Plan<192>  : PlanT<192, 24, 2, 24, 8, 1> {};
+template <> struct Plan<384>  : PlanT<384, 24, 3, 24, 8, 2> {};
+template <> struct Plan<768>  : PlanT<768, 24, 3, 24, 8, 4> {};
 // Narrow plans: at most 8 values per thread (fewer registers, one more pass).
 template <int N> struct PlanS;
 template <> struct PlanS<8>    : PlanT<8, 8, 1, 8, 1, 1> {};
@@ -144,6 +217,12 @@ template <> struct PlanS<128>  : PlanT<128, 8, 3, 8, 8, 2> {};
 template <> struct PlanS<256>  : PlanT<256, 8, 3, 8, 8, 4> {};
 template <> struct PlanS<512>  : PlanT<512, 8, 3, 8, 8, 8> {};
 template <> struct PlanS<1024> : PlanT<1024, 16, 3, 16, 16, 4> {};
+template <> struct PlanS<24>   : Plan<24> {};
+template <> struct PlanS<48>   : Plan<48> {};
+template <> struct PlanS<96>   : Plan<96> {};
+template <> struct PlanS<192>  : Plan<192> {};
+template <> struct PlanS<384>  : Plan<384> {};
+template <> struct PlanS<768>  : Plan<768> {};
 
 // log2 and highest set bit for 1 <= x < 32, written without recursion so that
 // they fold to constants inside unrolled loops.
@@ -174,7 +253,7 @@ __device__ __forceinline__ void tw_load(Tw<P, V>& w, int t, const V* __restrict_
     constexpr int R = P::R1, NS = P::R0;
 #pragma unroll
     for (int s = 0; s < Tw<P, V>::S1; ++s) {
-      const int e = ((t + TT * s) & (NS - 1)) * (N / (NS * R));
+      const int e = ((t + TT * s) % NS) * (N / (NS * R));
 #pragma unroll
       for (int q = 0; q < Tw<P, V>::L1; ++q) w.b1[s][q] = tab[(e << q) * (TWN / N)];
     }
@@ -183,7 +262,7 @@ __device__ __forceinline__ void tw_load(Tw<P, V>& w, int t, const V* __restrict_
     constexpr int R = P::R2, NS = P::R0 * P::R1;
 #pragma unroll
     for (int s = 0; s < Tw<P, V>::S2; ++s) {
-      const int e = ((t + TT * s) & (NS - 1)) * (N / (NS * R));
+      const int e = ((t + TT * s) % NS) * (N / (NS * R));
 #pragma unroll
       for (int q = 0; q < Tw<P, V>::L2; ++q) w.b2[s][q] = tab[(e << q) * (TWN / N)];
     }
@@ -234,7 +313,7 @@ __device__ __forceinline__ void pass_write(const V (&v)[E], int t, V* buf) {
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int j = t + TT * s;
-    const int base = (j / NS) * NS * R + (j & (NS - 1));
+    const int base = (j / NS) * NS * R + j % NS;
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[lslot<PAD>(base + r * NS)] = v[s * R + r];
   }

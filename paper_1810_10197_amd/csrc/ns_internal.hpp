@@ -5,18 +5,19 @@
 
 namespace nsk {
 
-constexpr int TWN_TABLE = 1024;   // twiddle table length (exp(-2 pi i m / 1024))
+constexpr int TWN_TABLE = 3072;   // twiddle table length (exp(-2 pi i m / 3072))
 
 // Grid geometry of one member.  Retained modes (2/3 rule): |k_j| <= K on every
 // axis.  Compact spectral layout per component: [kz'][ky'][kx] (3D) or
 // [ky'][kx] (2D) with kz', ky' in 0..2K (k = k' for k' <= K, k' - (2K+1)
 // otherwise) and kx in 0..K.
 struct Geom {
-  int dim, n, K, Kf, Kx;
+  int dim, n, K, Kf, Kx;   // n: grid of the physical-space products (the FFT length)
+  int nf;                  // grid of the caller's half-spectrum layout (n, or 2n/3 when padded)
   int ncomp;          // state components: 3 (3D), 2 or 3 (2D)
   long long mr;       // retained modes per component
   long long epm;      // compact elements per member = ncomp * mr
-  long long full;     // half-spectrum entries per component (n^(d-1) (n/2+1))
+  long long full;     // half-spectrum entries per component (nf^(d-1) (nf/2+1))
   int batch;
 };
 

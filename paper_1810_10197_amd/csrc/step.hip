@@ -33,11 +33,11 @@ __device__ __forceinline__ Modes decode(const Geom& g, long long i) {
 
 // Offset of a retained mode in the full half-spectrum layout of one component.
 __device__ __forceinline__ long long full_offset(const Geom& g, const Modes& md) {
-  const long long nh = g.n / 2 + 1;
-  const int iy = md.ky < 0 ? md.ky + g.n : md.ky;
+  const long long nh = g.nf / 2 + 1;
+  const int iy = md.ky < 0 ? md.ky + g.nf : md.ky;
   if (g.dim == 3) {
-    const int iz = md.kz < 0 ? md.kz + g.n : md.kz;
-    return ((long long)iz * g.n + iy) * nh + md.kx;
+    const int iz = md.kz < 0 ? md.kz + g.nf : md.kz;
+    return ((long long)iz * g.nf + iy) * nh + md.kx;
   }
   return (long long)iy * nh + md.kx;
 }
@@ -147,15 +147,15 @@ hipError_t pack_state(const Geom& g, const double2* full, double2* compact, hipS
 __global__ void k_unpack(const double2* __restrict__ compact, double2* __restrict__ full, Geom g,
                          long long total) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  const long long nh = g.n / 2 + 1;
+  const long long nh = g.nf / 2 + 1;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     const long long mc = i / g.full, q = i - mc * g.full;       // member*ncomp + c
     const int kx = (int)(q % nh);
     const long long r = q / nh;
-    const int iy = (int)(r % g.n);
-    const int iz = (int)(r / g.n);                             // 0 in 2D
-    const int ky = iy < g.n / 2 ? iy : iy - g.n;
-    const int kz = iz < g.n / 2 ? iz : iz - g.n;
+    const int iy = (int)(r % g.nf);
+    const int iz = (int)(r / g.nf);                            // 0 in 2D
+    const int ky = iy < g.nf / 2 ? iy : iy - g.nf;
+    const int kz = iz < g.nf / 2 ? iz : iz - g.nf;
     const bool keep = kx <= g.K && ky <= g.K && -ky <= g.K && (g.dim == 2 || (kz <= g.K && -kz <= g.K));
     double2 v = make_double2(0.0, 0.0);
     if (keep) {
@@ -335,6 +335,12 @@ hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, do
       case 128: launch_reduce<128, 3>(g, a, partials, nblk, nvel, st); break;
       case 256: launch_reduce<256, 3>(g, a, partials, nblk, nvel, st); break;
       case 512: launch_reduce<512, 3>(g, a, partials, nblk, nvel, st); break;
+      case 24: launch_reduce<24, 3>(g, a, partials, nblk, nvel, st); break;
+      case 48: launch_reduce<48, 3>(g, a, partials, nblk, nvel, st); break;
+      case 96: launch_reduce<96, 3>(g, a, partials, nblk, nvel, st); break;
+      case 192: launch_reduce<192, 3>(g, a, partials, nblk, nvel, st); break;
+      case 384: launch_reduce<384, 3>(g, a, partials, nblk, nvel, st); break;
+      case 768: launch_reduce<768, 3>(g, a, partials, nblk, nvel, st); break;
       default: return hipErrorInvalidValue;
     }
   } else {

@@ -46,6 +46,7 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_profile_stop", "ns_strerror", "ns_free"]
 NS_NTUNE = 6
 NS_TUNE_MAXV = 9
+NS_DEALIAS = {"2/3": 0, "3/2": 1}
 PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other", "slab"]
 
 
@@ -53,7 +54,8 @@ class NsConfig(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("batch", ctypes.c_int),
                 ("rhs_precision", ctypes.c_int), ("scalar", ctypes.c_int),
                 ("ri", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("force_kf", ctypes.c_double), ("force_e0", ctypes.c_double)]
+                ("force_kf", ctypes.c_double), ("force_e0", ctypes.c_double),
+                ("dealias", ctypes.c_int)]
 
 
 class NsStats(ctypes.Structure):
@@ -301,12 +303,13 @@ class Solver:
     """One solver instance on a CUDA/HIP device, memory owned by torch."""
 
     def __init__(self, dim=3, n=32, batch=1, nu=0.0, rhs_precision="fp32", scalar=0,
-                 ri=0.0, kappa=0.0, force_kf=0.0, force_e0=0.0, device="cuda"):
+                 ri=0.0, kappa=0.0, force_kf=0.0, force_e0=0.0, device="cuda", dealias="2/3"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         prec = {"fp32": NS_FP32, "fp64": NS_FP64}[rhs_precision]
-        self.cfg = NsConfig(dim, n, batch, prec, scalar, ri, kappa, force_kf, force_e0)
+        self.cfg = NsConfig(dim, n, batch, prec, scalar, ri, kappa, force_kf, force_e0,
+                            NS_DEALIAS[dealias])
         nbytes = ns_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise ValueError("unsupported configuration")

@@ -48,7 +48,10 @@ def test_host_only_entry_points(lib):
                 ns.NsConfig(3, 32, 0, 0, 0, 0, 0, 0, 0),
                 ns.NsConfig(3, 32, 1, 2, 0, 0, 0, 0, 0),
                 ns.NsConfig(3, 32, 1, 0, 1, 0, 0, 0, 0),     # scalar needs 2D
-                ns.NsConfig(2, 2048, 1, 0, 1, 0, 0, 0, 0)]:  # 2D limited to 1024
+                ns.NsConfig(2, 2048, 1, 0, 1, 0, 0, 0, 0),   # 2D limited to 1024
+                ns.NsConfig(3, 32, 1, 0, 0, 0, 0, 0, 0, 2),  # no such dealiasing rule
+                ns.NsConfig(2, 64, 1, 0, 0, 0, 0, 0, 0, 1),  # 3/2 rule: 3D only
+                ns.NsConfig(3, 8, 1, 0, 0, 0, 0, 0, 0, 1)]:  # 3/2 rule: n >= 16
         assert ns.ns_workspace_bytes(bad) == 0
     assert ns.ns_strerror(ns.NS_ERR_STEPFAIL).startswith("too many")
     # argument errors are caught before any device call
@@ -66,3 +69,7 @@ def test_workspace_scales_with_problem():
     c = ns.ns_workspace_bytes(ns.NsConfig(3, 128, 1, 1, 0, 0, 0, 0, 0))
     assert 3.5 * a < b < 4.5 * a
     assert c > a
+    # the 3/2 rule keeps (n-1)^2 n/2 modes (not ~(2n/3)^2 n/3) and forms the
+    # products on the (3n/2)^3 grid: its workspace is several times larger
+    d = ns.ns_workspace_bytes(ns.NsConfig(3, 128, 1, 0, 0, 0, 0, 0, 0, 1))
+    assert d > 3 * a
