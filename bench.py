@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rhs256_fp32_hbm_traffic.txt")
-TRAFFIC_SOURCES = ["fft_core.hpp", "pass_common.hpp", "rhs3d.hip"]
+TRAFFIC_SOURCES = ["fft_core.hpp", "pass_common.hpp", "rhs3d_kernels.hpp", "rhs3d.hip"]
 
 
 def measured_traffic(kernel):
@@ -89,24 +89,27 @@ def pass_bytes_2d(n, fp64=False):
     return {"zinv": 3 * mr * 16 + col, "xpass": 2 * col, "zfwd": col + 2 * 3 * mr * 16}
 
 
-def cpu_baseline(n, nu, budget_s):
-    """Oracle RHS/s on the host: repeat the FP64 NumPy right-hand side until
-    the time budget is used (at least one evaluation)."""
+def cpu_baseline(n, nu, budget_s, padded=False):
+    """Oracle RHS/s on the host: repeat the FP64 NumPy right-hand side (2/3
+    rule, or padded: 3/2 rule) until the time budget is used (at least one
+    evaluation)."""
     import numpy as np
     from oracle import spectral
     from paper_1810_10197_amd import inputs
     u = inputs.tgv3d(n)
+    rhs = spectral.rhs_ns3d_padded if padded else spectral.rhs_ns3d
     t0 = time.perf_counter()
     count = 0
     while True:
-        spectral.rhs_ns3d(u, nu)
+        rhs(u, nu)
         count += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
     return {"value": count / dt, "unit": "RHS evals/s", "cores": 1, "kind": "oracle",
-            "sample": "%d FP64 NumPy right-hand sides of the %d^3 Taylor-Green field "
-                      "(%.1f s; numpy.fft is single-threaded)" % (count, n, dt)}
+            "sample": "%d FP64 NumPy right-hand sides (%s rule) of the %d^3 Taylor-Green field "
+                      "(%.1f s; numpy.fft is single-threaded)"
+                      % (count, "3/2" if padded else "2/3", n, dt)}
 
 
 def log(msg):
@@ -629,6 +632,8 @@ def main():
     ap.add_argument("--members", type=int, default=128)
     ap.add_argument("--problem", choices=["rt2d", "hit512"], default="rt2d",
                     help="--study problem: which workload")
+    ap.add_argument("--dealias", choices=["2/3", "3/2"], default="2/3",
+                    help="3/2: products on the zero-padded 3n/2 grid (Sec. 2.1.1)")
     ap.add_argument("--workload", choices=["tgv", "ensemble", "rt2d"], default="tgv",
                     help="tgv: 3D Taylor-Green at --n; ensemble: --members x 64^3; rt2d: 2D "
                          "Boussinesq at 1024^2")
@@ -668,14 +673,20 @@ def bench_throughput(args):
 
     wl = args.workload
     fp64 = args.prec == "fp64"
+    padded = args.dealias == "3/2"
+    if padded and wl != "tgv":
+        raise SystemExit("--dealias 3/2 applies to the 3D Taylor-Green workload")
     if wl == "tgv":
         n, batch, dim = args.n, 1, 3
         nu = 1.0 / 1600
-        s = ns.Solver(dim=3, n=n, batch=1, nu=nu, rhs_precision=args.prec)
+        s = ns.Solver(dim=3, n=n, batch=1, nu=nu, rhs_precision=args.prec, dealias=args.dealias)
         s.set_state(inputs.tgv3d(n)[None])
         cfg = {"workload": "3D Taylor-Green vortex %d^3, nu=1/1600, BS5 attempts at h=%g, "
-                           "atol=rtol=1e-6, %s FFTs, FP64 state" % (n, args.dt, args.prec),
-               "n": n, "batch": 1}
+                           "atol=rtol=1e-6, %s FFTs, FP64 state, %s" %
+                           (n, args.dt, args.prec,
+                            "3/2-rule dealiasing (products on %d^3)" % (3 * n // 2) if padded
+                            else "2/3-rule dealiasing"),
+               "n": n, "batch": 1, "dealias": args.dealias}
         h = args.dt
     elif wl == "ensemble":
         n, batch, dim = 64, args.members, 3
@@ -739,7 +750,9 @@ def bench_throughput(args):
     rhs_evals = 7 * args.steps * batch
     value = rhs_evals / elapsed
     # inside the BS5 steps the 3D FP32 right-hand side reads FP32 stage inputs
-    pb = pass_bytes(n, fp64, stage32=not fp64) if dim == 3 else pass_bytes_2d(n, fp64)
+    # the 3/2 rule runs the same passes on the padded grid 3n/2
+    pb = (pass_bytes(3 * n // 2 if padded else n, fp64, stage32=not fp64) if dim == 3
+          else pass_bytes_2d(n, fp64))
     pb = {k: v * batch for k, v in pb.items()}
     n_rhs = prof["zinv"][1]                       # one first-pass launch per evaluation
     per_kernel = {}
@@ -772,8 +785,10 @@ def bench_throughput(args):
     model_bytes = sum(pb.values())
     unit = "RHS evals/s" if batch == 1 else "member RHS evals/s"
     out = {
-        "metric": "RHS evals/s at 256^3 (BS5 step, FP32 RHS / FP64 state)" if wl == "tgv" and n == 256
-        else "RHS evals/s (BS5 step, %s RHS / FP64 state)" % args.prec.upper(),
+        "metric": "RHS evals/s at 256^3 (BS5 step, FP32 RHS / FP64 state)"
+        if wl == "tgv" and n == 256 and not padded
+        else "RHS evals/s (BS5 step, %s RHS / FP64 state%s)" % (args.prec.upper(),
+                                                              ", 3/2 rule" if padded else ""),
         "value": value,
         "unit": unit,
         "n_gpus": 1,
@@ -788,7 +803,8 @@ def bench_throughput(args):
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom) if (wl == "tgv" and n == 256 and not fp64) else None,
+                     "traffic": measured_traffic(dom) if (wl == "tgv" and n == 256 and not fp64
+                                                          and not padded) else None,
                      "kernel": dom},
         "rhs_model_gb": model_bytes / 1e9,
         "rhs_passes_ms": rhs_ms,
@@ -802,7 +818,7 @@ def bench_throughput(args):
         "kernels": per_kernel,
     }
     if not args.no_cpu and wl == "tgv":
-        out["cpu_baseline"] = cpu_baseline(n, nu, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(n, nu, args.cpu_budget, padded)
     print(json.dumps(out))
 
 
