@@ -10,7 +10,8 @@
 // j + r*N/R of butterfly j and writes element (j/NS)*NS*R + j%NS + r*NS; the
 // output comes out in natural order.
 //
-// Lengths are 2^k, or 3 * 2^k with a radix-24 (3 x 8) first pass.  Twiddles
+// Lengths are 2^k, or 3 * 2^k with a radix-24 (3 x 8) or radix-12 (3 x 4)
+// first pass.  Twiddles
 // come from a table of exp(-2 pi i m / TWN), m < TWN, computed on the host in
 // double precision (std::cos/std::sin) and rounded once; a pass
 // with radix R loads log2(R) entries per butterfly and multiplies them
@@ -149,46 +150,51 @@ template <int DIR, typename V> struct Dft<3, DIR, V> {
   }
 };
 
-// 24-point DFT as 3 x 8: with n = n1 + 3 n2 and k = 8 k1 + k2, eight-point
-// transforms over n2 for each n1, the twiddles w_24^(n1 k2), then
+// 3M-point DFT (M = 4 or 8) as 3 x M: with n = n1 + 3 n2 and k = M k1 + k2,
+// M-point transforms over n2 for each n1, the twiddles w_3M^(n1 k2), then
 // three-point transforms over n1 for each k2.
-template <int DIR, typename V> struct Dft<24, DIR, V> {
+template <int M, int DIR, typename V> struct Dft3xM {
   static __device__ __forceinline__ void run(V* v) {
     using T = decltype(V::x);
-    V y[3][8];
+    constexpr int U = 8 / M;                    // w_3M = w_24^U
+    V y[3][M];
 #pragma unroll
     for (int n1 = 0; n1 < 3; ++n1) {
 #pragma unroll
-      for (int n2 = 0; n2 < 8; ++n2) y[n1][n2] = v[n1 + 3 * n2];
-      Dft<8, DIR, V>::run(y[n1]);
+      for (int n2 = 0; n2 < M; ++n2) y[n1][n2] = v[n1 + 3 * n2];
+      Dft<M, DIR, V>::run(y[n1]);
     }
 #pragma unroll
     for (int n1 = 1; n1 < 3; ++n1) {
 #pragma unroll
-      for (int k2 = 1; k2 < 8; ++k2) {
-        const int m = n1 * k2;
+      for (int k2 = 1; k2 < M; ++k2) {
+        const int m = n1 * k2 * U;
         const V w = mk<V>((T)cos24(m), (T)(DIR * sin24(m)));
         y[n1][k2] = cmul(y[n1][k2], w);
       }
     }
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
+    for (int k2 = 0; k2 < M; ++k2) {
       V z[3] = {y[0][k2], y[1][k2], y[2][k2]};
       Dft<3, DIR, V>::run(z);
 #pragma unroll
-      for (int k1 = 0; k1 < 3; ++k1) v[8 * k1 + k2] = z[k1];
+      for (int k1 = 0; k1 < 3; ++k1) v[M * k1 + k2] = z[k1];
     }
   }
 };
+template <int DIR, typename V> struct Dft<12, DIR, V> : Dft3xM<4, DIR, V> {};
+template <int DIR, typename V> struct Dft<24, DIR, V> : Dft3xM<8, DIR, V> {};
 
-// Radix plans: a transform of length N in P passes of radices R0, R1, R2
+// Radix plans: a transform of length N in P passes of radices R0, R1, R2, R3
 // (R0 = E, the values each thread holds; N/E threads per transform).
-template <int N_, int E_, int P_, int R0_, int R1_, int R2_> struct PlanT {
-  static constexpr int N = N_, E = E_, P = P_, R0 = R0_, R1 = R1_, R2 = R2_;
+template <int N_, int E_, int P_, int R0_, int R1_, int R2_, int R3_ = 1> struct PlanT {
+  static constexpr int N = N_, E = E_, P = P_, R0 = R0_, R1 = R1_, R2 = R2_, R3 = R3_;
   static constexpr int TT = N / E;
-  static constexpr int RL = P == 1 ? R0 : (P == 2 ? R1 : R2);   // last radix
-  static_assert(R0 * R1 * R2 == N && R0 == E, "radix plan");
-  static_assert((R1 & (R1 - 1)) == 0 && (R2 & (R2 - 1)) == 0, "later passes have power-of-two radices");
+  static constexpr int RL = P == 1 ? R0 : (P == 2 ? R1 : (P == 3 ? R2 : R3));   // last radix
+  static_assert(R0 * R1 * R2 * R3 == N && R0 == E, "radix plan");
+  static_assert((R1 & (R1 - 1)) == 0 && (R2 & (R2 - 1)) == 0 && (R3 & (R3 - 1)) == 0,
+                "later passes have power-of-two radices");
+  static_assert(E % R1 == 0 && E % R2 == 0 && E % R3 == 0, "whole butterflies per thread");
 };
 // Wide plans: few passes, up to 16 values per thread.
 template <int N> struct Plan;
@@ -217,12 +223,13 @@ template <> struct PlanS<128>  : PlanT<128, 8, 3, 8, 8, 2> {};
 template <> struct PlanS<256>  : PlanT<256, 8, 3, 8, 8, 4> {};
 template <> struct PlanS<512>  : PlanT<512, 8, 3, 8, 8, 8> {};
 template <> struct PlanS<1024> : PlanT<1024, 16, 3, 16, 16, 4> {};
-template <> struct PlanS<24>   : Plan<24> {};
-template <> struct PlanS<48>   : Plan<48> {};
-template <> struct PlanS<96>   : Plan<96> {};
-template <> struct PlanS<192>  : Plan<192> {};
-template <> struct PlanS<384>  : Plan<384> {};
-template <> struct PlanS<768>  : Plan<768> {};
+// 3 * 2^k: a radix-12 (3 x 4) first pass, 12 values per thread.
+template <> struct PlanS<24>   : PlanT<24, 12, 2, 12, 2, 1> {};
+template <> struct PlanS<48>   : PlanT<48, 12, 2, 12, 4, 1> {};
+template <> struct PlanS<96>   : PlanT<96, 12, 3, 12, 4, 2> {};
+template <> struct PlanS<192>  : PlanT<192, 12, 3, 12, 4, 4> {};
+template <> struct PlanS<384>  : PlanT<384, 12, 4, 12, 4, 4, 2> {};
+template <> struct PlanS<768>  : PlanT<768, 12, 4, 12, 4, 4, 4> {};
 
 // log2 and highest set bit for 1 <= x < 32, written without recursion so that
 // they fold to constants inside unrolled loops.
@@ -242,8 +249,10 @@ __host__ __device__ constexpr int highbit(int x) {
 template <class P, typename V> struct Tw {
   static constexpr int S1 = P::P >= 2 ? P::E / P::R1 : 1, L1 = P::P >= 2 ? ilog2(P::R1) : 1;
   static constexpr int S2 = P::P >= 3 ? P::E / P::R2 : 1, L2 = P::P >= 3 ? ilog2(P::R2) : 1;
+  static constexpr int S3 = P::P >= 4 ? P::E / P::R3 : 1, L3 = P::P >= 4 ? ilog2(P::R3) : 1;
   V b1[S1][L1];
   V b2[S2][L2];
+  V b3[S3][L3];
 };
 
 template <class P, typename V>
@@ -265,6 +274,15 @@ __device__ __forceinline__ void tw_load(Tw<P, V>& w, int t, const V* __restrict_
       const int e = ((t + TT * s) % NS) * (N / (NS * R));
 #pragma unroll
       for (int q = 0; q < Tw<P, V>::L2; ++q) w.b2[s][q] = tab[(e << q) * (TWN / N)];
+    }
+  }
+  if constexpr (P::P >= 4) {
+    constexpr int R = P::R3, NS = P::R0 * P::R1 * P::R2;
+#pragma unroll
+    for (int s = 0; s < Tw<P, V>::S3; ++s) {
+      const int e = ((t + TT * s) % NS) * (N / (NS * R));
+#pragma unroll
+      for (int q = 0; q < Tw<P, V>::L3; ++q) w.b3[s][q] = tab[(e << q) * (TWN / N)];
     }
   }
 }
@@ -376,6 +394,13 @@ __device__ __forceinline__ void fft_regs(V (&v)[P::E], int t, V* buf, const Tw<P
     group_sync<WAVE>();
     pass_read<N, E, P::R2, V, PAD>(v, t, buf);
     pass_tw<E, P::R2, DIR>(v, w.b2);
+  }
+  if constexpr (P::P >= 4) {
+    group_sync<WAVE>();
+    pass_write<N, E, P::R2, P::R0 * P::R1, V, PAD>(v, t, buf);
+    group_sync<WAVE>();
+    pass_read<N, E, P::R3, V, PAD>(v, t, buf);
+    pass_tw<E, P::R3, DIR>(v, w.b3);
   }
 }
 template <class P, int DIR, typename V, bool PAD = false, bool WAVE = false>

@@ -79,11 +79,16 @@ def test_padded_rhs_256_full_size(ns):
     for prec in ("fp64", "fp32"):
         s = solver(ns, n, prec, nu=nu)
         got[prec] = s.rhs(u[None]).cpu().numpy()[0]
+        if prec == "fp32":
+            # the narrow plans (radix-12 first pass, four passes at 384) everywhere
+            s.tune([2, 3, 1, 2, 3, 8])
+            got["fp32_narrow"] = s.rhs(u[None]).cpu().numpy()[0]
         s.close()
     ref = spectral.rhs_ns3d_padded(u, nu)
     assert np.abs(got["fp64"] - ref).max() <= 1e-11 * np.abs(ref).max()
-    errs = per_field_rel_l2(got["fp32"], ref)
-    assert max(errs) <= 5e-6, errs
+    for key in ("fp32", "fp32_narrow"):
+        errs = per_field_rel_l2(got[key], ref)
+        assert max(errs) <= 5e-6, (key, errs)
 
 
 def test_padded_and_two_thirds_agree_inside_the_two_thirds_band(ns):
@@ -137,3 +142,27 @@ def test_padded_integrate_matches_oracle_controller(ns):
     s.close()
     assert (st["n_accept"], st["n_reject"], st["n_rhs"]) == (ref["n_accept"], ref["n_reject"], ref["n_rhs"])
     assert np.abs(got - ref["u"]).max() <= 1e-12 * np.abs(ref["u"]).max()
+
+
+def test_padded_inviscid_invariants_512(ns):
+    """N = 512 (products on 768^3, beyond the oracle's quick range), wide and
+    narrow plans: the inviscid 3/2-rule right-hand side conserves energy and
+    is solenoidal."""
+    n = 512
+    announce("padded inviscid invariants n=512 fp32 (768^3 grid)")
+    u = inputs.random_isotropic(n, 3, k0=n / 6.0, band=n // 2 - 1)
+    s = solver(ns, n, "fp32", nu=0.0)
+    fs = [s.rhs(u[None]).cpu().numpy()[0]]
+    s.tune([2, 3, 1, 2, 3, 8])
+    fs.append(s.rhs(u[None]).cpu().numpy()[0])
+    s.close()
+    from oracle import diagnostics
+    w = diagnostics.weights(n, 3)
+    kx, ky, kz = spectral.wavenumbers(n, 3)
+    for f in fs:
+        rate = np.sum(w * np.real(np.conj(u) * f).sum(0))
+        scale = np.sqrt(np.sum(w * np.abs(u) ** 2) * np.sum(w * np.abs(f) ** 2))
+        assert abs(rate) < 1e-6 * scale
+        div = np.abs(kx * f[0] + ky * f[1] + kz * f[2]).max()
+        assert div < 1e-5 * np.abs(f).max() * n
+    assert max(per_field_rel_l2(fs[1], fs[0])) < 5e-6      # the two plans agree
