@@ -234,9 +234,9 @@ typedef struct ns_kernel_times {
 int ns_profile_start(ns_solver* s);
 int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
 
-/* Autotuner of the 3D right-hand side.  Parameters 0-4 are launch variants of
+/* Autotuner of the right-hand side.  3D: parameters 0-4 are launch variants of
  * the five passes (z-inverse, y-inverse, x-pass, y-forward, z-forward): radix
- * plan (wide = few passes, narrow = at most 8 values per thread) and column
+ * plan (wide = few passes, narrow = fewer values per thread) and column
  * tile (16, 32 or 64 columns per block).  Parameter 5 is the slab schedule of
  * the y/x/y passes: variant v < 5 runs them over slabs of n >> v planes of z
  * (at least 1) through slab buffers that are reused, so that small slabs stay
@@ -248,8 +248,10 @@ int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
  * of the y/x/y phase per evaluation) and keeps the fastest; ms_host
  * (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL) receives the average
  * milliseconds (0 for variants a parameter lacks).  tune_get /
- * tune_set read or restore the choice (e.g. from a cache).  2D solvers accept
- * the calls and ignore the choice. */
+ * tune_set read or restore the choice (e.g. from a cache).  2D (n >= 256):
+ * parameter 0 is the y-inverse's and parameter 4 the y-forward's variant
+ * (radix plan and column tile, 0-4), timed per launch; the other parameters
+ * are accepted and ignored, as are all of them below 256 points. */
 #define NS_NTUNE 6
 #define NS_TUNE_MAXV 9
 int ns_autotune(ns_solver* s, int reps, double* ms_host);

@@ -995,13 +995,16 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
   if (!s->have_state) return NS_ERR_STATE;
   if (ms_host)
     for (int i = 0; i < NS_NTUNE * NS_TUNE_MAXV; ++i) ms_host[i] = 0.0;
-  if (s->g.dim != 3) return NS_OK;
   const bool was_on = s->prof_on;
   int rc = NS_OK;
-  // the slab first (it changes what the passes read from), then every pass
-  const int order[NS_NTUNE] = {5, 0, 1, 2, 3, 4};
-  for (int q = 0; q < NS_NTUNE && !rc; ++q) {
-    const int p = order[q];
+  // 3D: the slab first (it changes what the passes read from), then every
+  // pass; 2D: the two column passes (Q1 in slot 0, Q3 in slot 4)
+  const bool d3 = s->g.dim == 3;
+  const int order3[NS_NTUNE] = {5, 0, 1, 2, 3, 4};
+  const int order2[2] = {0, 4};
+  const int nq = d3 ? NS_NTUNE : (s->g.n >= 256 ? 2 : 0);
+  for (int q = 0; q < nq && !rc; ++q) {
+    const int p = d3 ? order3[q] : order2[q];
     const int nv = tune_nvariants(p);
     double best = 1e300;
     int best_v = s->rb.variant[p];
@@ -1020,7 +1023,7 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
       // z passes: per launch; the y/x/y passes and the slab schedule: wall
       // time of the y/x/y phase per evaluation
       double ms = 1e300;
-      if (p == 1 || p == 2 || p == 3 || p == 5) {
+      if (d3 && (p == 1 || p == 2 || p == 3 || p == 5)) {
         if (kt.count[nsk::PROF_SLAB]) ms = kt.ms[nsk::PROF_SLAB] / (double)kt.count[nsk::PROF_SLAB];
       } else if (kt.count[p]) {
         ms = kt.ms[p] / (double)kt.count[p];

@@ -222,7 +222,7 @@ template <> struct PlanS<64>   : PlanT<64, 8, 2, 8, 8, 1> {};
 template <> struct PlanS<128>  : PlanT<128, 8, 3, 8, 8, 2> {};
 template <> struct PlanS<256>  : PlanT<256, 8, 3, 8, 8, 4> {};
 template <> struct PlanS<512>  : PlanT<512, 8, 3, 8, 8, 8> {};
-template <> struct PlanS<1024> : PlanT<1024, 16, 3, 16, 16, 4> {};
+template <> struct PlanS<1024> : PlanT<1024, 8, 4, 8, 8, 8, 2> {};
 // 3 * 2^k: a radix-12 (3 x 4) first pass, 12 values per thread.
 template <> struct PlanS<24>   : PlanT<24, 12, 2, 12, 2, 1> {};
 template <> struct PlanS<48>   : PlanT<48, 12, 2, 12, 4, 1> {};

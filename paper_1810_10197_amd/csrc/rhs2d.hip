@@ -21,18 +21,16 @@
 namespace nsk {
 
 // ---------------------------------------------------------------- Q1
-// Column tile of Q1: the default width (narrower tiles give more blocks but
-// shorter runs per row, measured slower at 1024^2).
-template <class PL> constexpr int q1_cw() { return 0; }
-
-template <class PL, typename T>
-__global__ __launch_bounds__((ColCfg<PL, T, q1_cw<PL>()>::NT)) void k2_yinv(const double2* __restrict__ U,
+// CW: column tile width (0 = the default); narrower tiles give more blocks
+// but shorter runs per row.
+template <class PL, typename T, int CW>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k2_yinv(const double2* __restrict__ U,
                                                               cplx<T>* __restrict__ B1, Geom g,
                                                               int nfield, long long nblocks,
                                                               const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
   using V = cplx<T>;
-  using CF = ColCfg<PL, T, q1_cw<PL>()>;
+  using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C;
   __shared__ V lds[C * CF::LD];
   const long long L = xcd_logical(blockIdx.x, gridDim.x);
@@ -200,19 +198,20 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k2_xpass(const cplx<T>* _
 // One block per tile of C columns kx; the NF transformed fields of a column
 // are transformed side by side by NF thread groups (so that a 1024-point
 // column still gives enough blocks), their outputs meet in LDS, and the
-// epilogue's modes are shared out over all groups.
-template <class PL, typename T, int NF> struct Q3Cfg {
+// epilogue's modes are shared out over all groups.  CMAX caps the tile
+// width (fewer columns per block, more blocks).
+template <class PL, typename T, int NF, int CMAX = 8> struct Q3Cfg {
   static constexpr int N = PL::N;
   static constexpr int TT = N / PL::E;
   static constexpr int LD = N + 1;
   static constexpr int LDS_BUDGET = 160 * 1024;
   static constexpr int C =
-      cmax(1, cmin(cmin(1024 / (TT * NF), 8), floor_pow2(LDS_BUDGET / (NF * LD * (int)sizeof(cplx<T>)))));
+      cmax(1, cmin(cmin(1024 / (TT * NF), CMAX), floor_pow2(LDS_BUDGET / (NF * LD * (int)sizeof(cplx<T>)))));
   static constexpr int NT = C * TT * NF;
 };
 
-template <class PL, typename T, bool SCALAR>
-__global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2>::NT)) void k2_yfwd(const cplx<T>* __restrict__ B2,
+template <class PL, typename T, bool SCALAR, int CMAX>
+__global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_yfwd(const cplx<T>* __restrict__ B2,
                                                                           const double2* __restrict__ U,
                                                                           double2* __restrict__ Kout, Geom g,
                                                                           const double* __restrict__ nu,
@@ -221,7 +220,7 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2>::NT)) void k2_yfwd(co
   constexpr int N = PL::N;
   constexpr int NF = SCALAR ? 4 : 2;
   using V = cplx<T>;
-  using QC = Q3Cfg<PL, T, NF>;
+  using QC = Q3Cfg<PL, T, NF, CMAX>;
   constexpr int E = PL::E, C = QC::C, TT = QC::TT, LD = QC::LD;
   __shared__ V lds[NF * C * LD];
   const int f = threadIdx.x / (C * TT);
@@ -286,24 +285,61 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2>::NT)) void k2_yfwd(co
 }
 
 // ---------------------------------------------------------------- host side
+// Launch variants (the autotuner's choice; grids below 256 points use 0):
+// Q1 (tuning slot 0) 0 default tile, 1 four columns, 2 two columns, 3 narrow
+// plan default tile, 4 narrow plan two columns; Q3 (slot 4) 0 up to eight
+// columns, 1 two, 2 one, 3 narrow plan up to eight, 4 narrow plan one.  The
+// x-pass keeps the wide plan (a row stays inside one wavefront).
+template <int N, int V> struct Q1Var {
+  using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
+  static constexpr int CW = N < 256 ? 0 : (V == 1 ? 4 : (V == 2 || V == 4 ? 2 : 0));
+};
+template <int N, int V> struct Q3Var {
+  using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
+  static constexpr int CMAX = N < 256 ? 8 : (V == 1 ? 2 : (V == 2 || V == 4 ? 1 : 8));
+};
+
+template <int N, typename T, int VAR>
+static void launch_q1(const Geom& g, const double2* U, cplx<T>* B1, int nfield, const cplx<T>* tw,
+                      hipStream_t st) {
+  using QV = Q1Var<N, VAR>;
+  using CF = ColCfg<typename QV::PL, T, QV::CW>;
+  const long long nb1 = (long long)g.batch * nfield * ((g.Kx + CF::C - 1) / CF::C);
+  const long long nb1p = (nb1 + 7) / 8 * 8;
+  hipLaunchKernelGGL((k2_yinv<typename QV::PL, T, QV::CW>), dim3((unsigned)nb1p), dim3(CF::NT), 0, st, U, B1, g,
+                     nfield, nb1, tw);
+}
+template <int N, typename T, bool SCALAR, int VAR>
+static void launch_q3(const Geom& g, const cplx<T>* B2, const double2* U, double2* K, const RhsParams& p,
+                      const cplx<T>* tw, hipStream_t st) {
+  using QV = Q3Var<N, VAR>;
+  using QC = Q3Cfg<typename QV::PL, T, SCALAR ? 4 : 2, QV::CMAX>;
+  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX>), dim3((g.Kx + QC::C - 1) / QC::C, g.batch),
+                     dim3(QC::NT), 0, st, B2, U, K, g, p.nu, p.ri, p.kappa, tw);
+}
+
 template <int N, typename T, bool SCALAR>
 static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
                         const RhsBufs& bufs, const void* twv, hipStream_t st) {
   using V = cplx<T>;
   using PL = Plan<N>;
-  using CF = ColCfg<PL, T, q1_cw<PL>()>;
   using RC = RowCfg<PL, T>;
   const V* tw = (const V*)twv;
   V* B1 = (V*)bufs.a1;
   V* B2 = (V*)bufs.a2;
   const int nfield = SCALAR ? 4 : 3;
-  const long long nb1 = (long long)g.batch * nfield * ((g.Kx + CF::C - 1) / CF::C);
-  const long long nb1p = (nb1 + 7) / 8 * 8;
+  // variants only matter (and are only built) from 256 points on
+  const int v1 = N >= 256 ? bufs.variant[0] : 0, v3 = N >= 256 ? bufs.variant[4] : 0;
 #define NSK_MARK(id, ph) \
   if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, st)
   NSK_MARK(PROF_P1, 0);
-  hipLaunchKernelGGL((k2_yinv<PL, T>), dim3((unsigned)nb1p), dim3(CF::NT), 0, st, U, B1, g, nfield, nb1,
-                     tw);
+  switch (v1) {
+    case 1: launch_q1<N, T, N >= 256 ? 1 : 0>(g, U, B1, nfield, tw, st); break;
+    case 2: launch_q1<N, T, N >= 256 ? 2 : 0>(g, U, B1, nfield, tw, st); break;
+    case 3: launch_q1<N, T, N >= 256 ? 3 : 0>(g, U, B1, nfield, tw, st); break;
+    case 4: launch_q1<N, T, N >= 256 ? 4 : 0>(g, U, B1, nfield, tw, st); break;
+    default: launch_q1<N, T, 0>(g, U, B1, nfield, tw, st);
+  }
   NSK_MARK(PROF_P1, 1);
   const long long rows = (long long)g.batch * N;
   NSK_MARK(PROF_P3, 0);
@@ -311,9 +347,13 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
                      dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
   NSK_MARK(PROF_P3, 1);
   NSK_MARK(PROF_P5, 0);
-  using QC = Q3Cfg<PL, T, SCALAR ? 4 : 2>;
-  hipLaunchKernelGGL((k2_yfwd<PL, T, SCALAR>), dim3((g.Kx + QC::C - 1) / QC::C, g.batch), dim3(QC::NT), 0,
-                     st, B2, U, K, g, p.nu, p.ri, p.kappa, tw);
+  switch (v3) {
+    case 1: launch_q3<N, T, SCALAR, N >= 256 ? 1 : 0>(g, B2, U, K, p, tw, st); break;
+    case 2: launch_q3<N, T, SCALAR, N >= 256 ? 2 : 0>(g, B2, U, K, p, tw, st); break;
+    case 3: launch_q3<N, T, SCALAR, N >= 256 ? 3 : 0>(g, B2, U, K, p, tw, st); break;
+    case 4: launch_q3<N, T, SCALAR, N >= 256 ? 4 : 0>(g, B2, U, K, p, tw, st); break;
+    default: launch_q3<N, T, SCALAR, 0>(g, B2, U, K, p, tw, st);
+  }
   NSK_MARK(PROF_P5, 1);
 #undef NSK_MARK
   return hipGetLastError();

@@ -107,3 +107,28 @@ def test_boussinesq_bs5_steps_and_diagnostics(ns):
     assert eps[0] == pytest.approx(diagnostics.dissipation(ref, f, 2), rel=1e-9)
     assert sh[0] == pytest.approx(diagnostics.shells(ref, 2), rel=1e-12, abs=1e-300)
     s.close()
+
+
+@pytest.mark.parametrize("n,scalar", [(1024, 1), (256, 0)])
+def test_rhs2d_every_launch_variant(ns, n, scalar):
+    """Each variant of the two column passes (radix plan and tile width; the
+    narrow 1024-point plan has four passes) is a correct right-hand side, and
+    the autotuner keeps one of them."""
+    announce("rhs2d variants n=%d scalar=%d" % (n, scalar))
+    nu, kappa, ri = 1e-3, 2e-3, 0.5
+    u = random2d(n, 5 * n + scalar, 3 if scalar else 2)
+    ref = spectral.rhs_ns2d(u, nu, kappa, ri) if scalar else spectral.rhs_ns2d(u, nu)
+    s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision="fp32", scalar=scalar, ri=ri if scalar else 0.0,
+                  kappa=kappa if scalar else 0.0)
+    for v in range(5):
+        s.tune([v, 0, 0, 0, 4 - v, 0])
+        got = s.rhs(u[None]).cpu().numpy()[0]
+        err = max(per_field_rel_l2(got, ref))
+        assert err <= 3e-6, (v, err)
+    s.set_state(u[None])
+    variants, ms = s.autotune(reps=2)
+    assert ms[0][variants[0]] == min(x for x in ms[0][:5] if x > 0)
+    assert ms[4][variants[4]] == min(x for x in ms[4][:5] if x > 0)
+    got = s.rhs(u[None]).cpu().numpy()[0]
+    assert max(per_field_rel_l2(got, ref)) <= 3e-6
+    s.close()
