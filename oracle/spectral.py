@@ -8,7 +8,7 @@ the spectral ODE system of Eq. (2) whose nonlinear term u x omega is evaluated
 pointwise in physical space and transformed back (Sec. 2.1), and the
 Boussinesq system of Eqs. (3a-c), (4a-b) (Sec. 3.2).  Dealiasing uses the
 2/3 rule (rhs_ns3d, rhs_ns2d) or the 3/2-rule zero padding of Sec. 2.1.1
-(rhs_ns3d_padded).
+(rhs_ns3d_padded, rhs_ns2d_padded).
 
 Every function works on the full half-spectrum layout; shapes are
 (C, N, N, N//2+1) in 3D and (C, N, N//2+1) in 2D, complex128.
@@ -215,11 +215,13 @@ def padded_size(n):
     return 3 * n // 2
 
 
-def mask_padded(n):
-    """Boolean mask of the retained modes (every |k_j| <= N/2 - 1), 3D."""
+def mask_padded(n, dim=3):
+    """Boolean mask of the retained modes (every |k_j| <= N/2 - 1)."""
     K = cutoff_padded(n)
-    kx, ky, kz = wavenumbers(n, 3)
-    return (np.abs(kx) <= K) & (np.abs(ky) <= K) & (np.abs(kz) <= K)
+    m = True
+    for k in wavenumbers(n, dim):
+        m = m & (np.abs(k) <= K)
+    return m
 
 
 def _band_index(n, K):
@@ -227,30 +229,31 @@ def _band_index(n, K):
     return np.arange(-K, K + 1) % n
 
 
+def _moved(a, src_n, dst_n, K):
+    """Copy the modes |k_j| <= K of half spectra a (C, src_n, ..., src_n//2+1)
+    into zero half spectra on the dst_n grid; 2D or 3D from a's rank."""
+    dim = a.ndim - 1
+    out = np.zeros((a.shape[0],) + (dst_n,) * (dim - 1) + (dst_n // 2 + 1,), dtype=np.complex128)
+    full_s = [_band_index(src_n, K)] * (dim - 1) + [np.arange(K + 1)]
+    full_d = [_band_index(dst_n, K)] * (dim - 1) + [np.arange(K + 1)]
+    src, dst = np.ix_(*full_s), np.ix_(*full_d)
+    for c in range(a.shape[0]):
+        out[c][dst] = a[c][src]
+    return out
+
+
 def pad_spectrum(uh, n, m):
-    """N-grid half spectra (C, N, N, N//2+1) -> M-grid ones (M > N), zeros
+    """N-grid half spectra (C, N, [N,] N//2+1) -> M-grid ones (M > N), zeros
     outside the retained set of the 3/2 rule.  Coefficients are copied
     unscaled: with the normalised convention a mode's value does not depend
     on the grid it is sampled on."""
-    K = cutoff_padded(n)
-    out = np.zeros(uh.shape[:-3] + (m, m, m // 2 + 1), dtype=np.complex128)
-    src = np.ix_(_band_index(n, K), _band_index(n, K), np.arange(K + 1))
-    dst = np.ix_(_band_index(m, K), _band_index(m, K), np.arange(K + 1))
-    for c in range(uh.shape[0]):
-        out[c][dst] = uh[c][src]
-    return out
+    return _moved(uh, n, m, cutoff_padded(n))
 
 
 def truncate_spectrum(vh, m, n):
     """M-grid half spectra -> N-grid ones, keeping the retained set of the
     3/2 rule on N and zeros elsewhere (the inverse of pad_spectrum on it)."""
-    K = cutoff_padded(n)
-    out = np.zeros(vh.shape[:-3] + (n, n, n // 2 + 1), dtype=np.complex128)
-    src = np.ix_(_band_index(m, K), _band_index(m, K), np.arange(K + 1))
-    dst = np.ix_(_band_index(n, K), _band_index(n, K), np.arange(K + 1))
-    for c in range(vh.shape[0]):
-        out[c][dst] = vh[c][src]
-    return out
+    return _moved(vh, m, n, cutoff_padded(n))
 
 
 def rhs_ns3d_padded(uh, nu):
@@ -280,6 +283,46 @@ def rhs_ns3d_padded(uh, nu):
     f = np.stack([nl[0] - kx * p, nl[1] - ky * p, nl[2] - kz * p]) - nu * k2 * u0
     f[:, 0, 0, 0] = 0.0
     return f
+
+
+def rhs_ns2d_padded(uh, nu, kappa=0.0, ri=0.0):
+    """The 2D right-hand side of rhs_ns2d (plain or Boussinesq) with every
+    product -- v omega, -u omega and, with the scalar, rho u, rho v -- formed
+    by the 3/2 rule: the factors padded with zeros to M = 3N/2 frequencies
+    per direction, multiplied on the M^2 grid, transformed back (normalised
+    by M^2) and truncated to |k_j| <= N/2 - 1.  The linear terms (projection,
+    buoyancy, diffusion) then act on the N grid as in rhs_ns2d."""
+    n = uh.shape[1]
+    m = padded_size(n)
+    keep = mask_padded(n, 2)
+    u0 = uh * keep
+    kx, ky = wavenumbers(n, 2)
+    k2 = kx * kx + ky * ky
+    k2safe = np.where(k2 == 0, 1.0, k2)
+
+    def phys(a):
+        return inverse(pad_spectrum(a[None], n, m)[0], m, 2)
+
+    def spec(a):
+        return truncate_spectrum(forward(a, 2)[None], m, n)[0]
+
+    u, v = phys(u0[0]), phys(u0[1])
+    om = phys(1j * (kx * u0[1] - ky * u0[0]))
+    nx = spec(v * om)
+    ny = spec(-u * om)
+    if uh.shape[0] == 3:
+        rho = phys(u0[2])
+        qx = spec(rho * u)
+        qy = spec(rho * v)
+        ny = ny - ri * u0[2]
+    p = (kx * nx + ky * ny) / k2safe
+    fu = np.where(k2 == 0, 0.0, nx - kx * p) - nu * k2 * u0[0]
+    fv = np.where(k2 == 0, 0.0, ny - ky * p) - nu * k2 * u0[1]
+    if uh.shape[0] == 2:
+        return np.stack([fu, fv])
+    frho = -1j * (kx * qx + ky * qy) - kappa * k2 * u0[2]
+    frho[0, 0] = 0.0
+    return np.stack([fu, fv, frho])
 
 
 def rhs_ns2d(uh, nu, kappa=0.0, ri=0.0):

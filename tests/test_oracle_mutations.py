@@ -80,3 +80,8 @@ def test_padding_that_keeps_the_nyquist_mode_is_caught(monkeypatch):
     # a truncation that keeps |k_j| <= N/2 (Nyquist included) breaks the zero pattern
     monkeypatch.setattr(spectral, "cutoff_padded", lambda n: n // 2)
     assert _fails(ts.test_padded_rhs_against_direct_convolution, 8, 21)
+
+
+def test_unpadded_2d_product_is_caught(monkeypatch):
+    monkeypatch.setattr(spectral, "padded_size", lambda n: n)
+    assert _fails(ts.test_padded_rhs2d_against_direct_convolution, 10, 3, 52)

@@ -320,3 +320,103 @@ def test_padded_rhs_inviscid_invariants():
     scale_h = np.sqrt(np.sum(w * np.abs(om) ** 2)) * np.sqrt(np.sum(w * np.abs(f) ** 2))
     assert abs(np.sum(w * np.real(np.conj(u) * f).sum(0))) < 1e-14 * scale
     assert abs(np.sum(w * np.real(np.conj(om) * f).sum(0))) < 1e-14 * scale_h
+
+
+def _real_band_limited_2d(n, K, seed, ncomp):
+    """Random real 2D state with every |k_j| <= K: a solenoidal velocity from a
+    stream function, and (ncomp = 3) a scalar."""
+    rng = np.random.default_rng(seed)
+    kx, ky = spectral.wavenumbers(n, 2)
+    keep = (np.abs(kx) <= K) & (np.abs(ky) <= K)
+    psi = spectral.forward(rng.standard_normal((n, n)), 2) * keep
+    st = np.zeros((ncomp, n, n // 2 + 1), dtype=complex)
+    st[0] = 1j * ky * psi
+    st[1] = -1j * kx * psi
+    if ncomp == 3:
+        st[2] = spectral.forward(rng.standard_normal((n, n)), 2) * keep
+    return st
+
+
+def _full_square(a, n, K):
+    """Coefficients c[ky+K, kx+K] of a real 2D field's modes |k_j| <= K."""
+    L = 2 * K + 1
+    out = np.zeros((L, L), dtype=complex)
+    for b, ky in enumerate(range(-K, K + 1)):
+        for c, kx in enumerate(range(-K, K + 1)):
+            out[b, c] = a[ky % n, kx] if kx >= 0 else np.conj(a[(-ky) % n, -kx])
+    return out
+
+
+def _conv2(A, B, K):
+    """Direct convolution sum_{p+q=k} A(p) B(q) over the retained square."""
+    L = 2 * K + 1
+    out = np.zeros((L, L), dtype=complex)
+    for b in range(L):
+        ya, yb = max(0, b - K), min(L, b + K + 1)
+        for c in range(L):
+            xa, xb = max(0, c - K), min(L, c + K + 1)
+            out[ya:yb, xa:xb] += A[b, c] * B[ya - b + K:yb - b + K, xa - c + K:xb - c + K]
+    return out
+
+
+@pytest.mark.parametrize("n,ncomp,seed", [(8, 2, 51), (10, 3, 52), (8, 3, 53)])
+def test_padded_rhs2d_against_direct_convolution(n, ncomp, seed):
+    """2D 3/2 rule (plain and Boussinesq): every product is the exact
+    truncated convolution of the retained modes; the projection, buoyancy
+    and diffusion then follow Eqs. (4a-b)."""
+    K = n // 2 - 1
+    L = 2 * K + 1
+    st = _real_band_limited_2d(n, K, seed, ncomp)
+    nu, kappa, ri = 0.02, 0.03, 0.7
+    k = np.arange(-K, K + 1)
+    KY, KX = np.meshgrid(k, k, indexing="ij")
+    U, V = _full_square(st[0], n, K), _full_square(st[1], n, K)
+    W = 1j * (KX * V - KY * U)
+    nx, ny = _conv2(V, W, K), -_conv2(U, W, K)
+    if ncomp == 3:
+        R = _full_square(st[2], n, K)
+        qx, qy = _conv2(R, U, K), _conv2(R, V, K)
+    expect = np.zeros_like(st)
+    for b, ky in enumerate(k):
+        for c in range(K, L):
+            kx = c - K
+            kk = kx * kx + ky * ky
+            idx = (ky % n, kx)
+            if kk == 0:
+                continue
+            bx, by = nx[b, c], ny[b, c] - (ri * st[2][idx] if ncomp == 3 else 0.0)
+            p = (kx * bx + ky * by) / kk
+            expect[0][idx] = bx - kx * p - nu * kk * st[0][idx]
+            expect[1][idx] = by - ky * p - nu * kk * st[1][idx]
+            if ncomp == 3:
+                expect[2][idx] = -1j * (kx * qx[b, c] + ky * qy[b, c]) - kappa * kk * st[2][idx]
+    got = (spectral.rhs_ns2d_padded(st, nu, kappa, ri) if ncomp == 3
+           else spectral.rhs_ns2d_padded(st, nu))
+    assert np.abs(got - expect).max() < 1e-13 * np.abs(expect).max()
+    assert np.all(got[:, ~spectral.mask_padded(n, 2)] == 0.0)
+
+
+@pytest.mark.parametrize("ncomp", [2, 3])
+def test_padded_rhs2d_equals_two_thirds_rule_on_the_padded_grid(ncomp):
+    n = 32
+    m = spectral.padded_size(n)
+    st = _real_band_limited_2d(n, n // 2 - 1, 61 + ncomp, ncomp)
+    args = (1e-3, 2e-3, 0.5) if ncomp == 3 else (1e-3,)
+    big = spectral.rhs_ns2d(spectral.pad_spectrum(st, n, m), *args)
+    got = spectral.rhs_ns2d_padded(st, *args)
+    assert np.abs(spectral.truncate_spectrum(big, m, n) - got).max() < 1e-13 * np.abs(got).max()
+
+
+def test_padded_rhs2d_inviscid_budgets():
+    """nu = kappa = 0: the scalar variance is conserved and the kinetic energy
+    changes only by the buoyancy work -Ri <v, rho>."""
+    n, ri = 16, 0.8
+    st = _real_band_limited_2d(n, n // 2 - 1, 71, 3)
+    f = spectral.rhs_ns2d_padded(st, 0.0, 0.0, ri)
+    w = diagnostics.weights(n, 2)
+    rho_rate = np.sum(w * np.real(np.conj(st[2]) * f[2]))
+    e_rate = np.sum(w * np.real(np.conj(st[0]) * f[0] + np.conj(st[1]) * f[1]))
+    work = -ri * np.sum(w * np.real(np.conj(st[1]) * st[2]))
+    scale = np.sqrt(np.sum(w * np.abs(st) ** 2) * np.sum(w * np.abs(f) ** 2))
+    assert abs(rho_rate) < 1e-13 * scale
+    assert abs(e_rate - work) < 1e-13 * scale
