@@ -90,7 +90,7 @@ typedef struct ns_config {
   double kappa;         /* Boussinesq scalar diffusivity */
   double force_kf;      /* 3D: forcing band 0 < |k| <= kf after each accepted step; <= 0 off */
   double force_e0;      /* energy the forcing restores */
-  int dealias;          /* NS_DEALIAS_23, or NS_DEALIAS_32 (3D, n = 16..512) */
+  int dealias;          /* NS_DEALIAS_23, or NS_DEALIAS_32 (n >= 16) */
 } ns_config;
 
 typedef struct ns_solver ns_solver;

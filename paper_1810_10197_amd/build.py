@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libns.so")
-SOURCES = ["capi.hip", "rhs3d.hip", "rhs3d_pad.hip", "rhs2d.hip", "step.hip", "mlp.hip", "control.hip"]
+SOURCES = ["capi.hip", "rhs3d.hip", "rhs3d_pad.hip", "rhs2d.hip", "rhs2d_pad.hip", "step.hip", "mlp.hip", "control.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions

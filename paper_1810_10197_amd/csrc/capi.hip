@@ -76,7 +76,7 @@ bool valid_config(const ns_config* c) {
   const int maxn = c->dim == 3 ? 512 : 1024;
   if (c->n < 8 || c->n > maxn || (c->n & (c->n - 1))) return false;
   if (c->dealias != NS_DEALIAS_23 && c->dealias != NS_DEALIAS_32) return false;
-  if (c->dealias == NS_DEALIAS_32 && (c->dim != 3 || c->n < 16)) return false;
+  if (c->dealias == NS_DEALIAS_32 && c->n < 16) return false;
   if (c->batch < 1 || c->batch > 65535) return false;
   if (c->rhs_precision != NS_FP32 && c->rhs_precision != NS_FP64) return false;
   if (c->scalar != 0 && !(c->dim == 2 && c->scalar == 1)) return false;

@@ -213,6 +213,7 @@ template <> struct Plan<96>   : PlanT<96, 24, 2, 24, 4, 1> {};
 template <> struct Plan<192>  : PlanT<192, 24, 2, 24, 8, 1> {};
 template <> struct Plan<384>  : PlanT<384, 24, 3, 24, 8, 2> {};
 template <> struct Plan<768>  : PlanT<768, 24, 3, 24, 8, 4> {};
+template <> struct Plan<1536> : PlanT<1536, 24, 3, 24, 8, 8> {};
 // Narrow plans: at most 8 values per thread (fewer registers, one more pass).
 template <int N> struct PlanS;
 template <> struct PlanS<8>    : PlanT<8, 8, 1, 8, 1, 1> {};
@@ -230,6 +231,7 @@ template <> struct PlanS<96>   : PlanT<96, 12, 3, 12, 4, 2> {};
 template <> struct PlanS<192>  : PlanT<192, 12, 3, 12, 4, 4> {};
 template <> struct PlanS<384>  : PlanT<384, 12, 4, 12, 4, 4, 2> {};
 template <> struct PlanS<768>  : PlanT<768, 12, 4, 12, 4, 4, 4> {};
+template <> struct PlanS<1536> : Plan<1536> {};      // 12 x 128 would need five passes
 
 // log2 and highest set bit for 1 <= x < 32, written without recursion so that
 // they fold to constants inside unrolled loops.

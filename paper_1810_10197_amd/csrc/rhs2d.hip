@@ -1,363 +1,13 @@
-// Fused pass kernels of the 2D right-hand sides: plain Navier--Stokes
-// (components u, v) and the Boussinesq system of Sec. 3.2, Eqs. (4a-b)
-// (components u, v, rho), in two dimensions with gravity along -y:
-//
-//   f_u   = P(N_hat - Ri rho_hat e_y) - nu |k|^2 u_hat,   P = I - k k^T/|k|^2,
-//   f_rho = -i k . (rho u)^ - kappa |k|^2 rho_hat,
-//   N_hat = DFT(u x omega)/n^2 = DFT(v omega, -u omega)/n^2, omega = dv/dx - du/dy,
-//
-// both products 2/3-dealiased; f = 0 at k = 0.  Three passes:
-//
-//   Q1 y-inverse  compact FP64 state -> u, v, omega = i(kx v - ky u), rho cast
-//                 to T, 2K+1 non-zero ky -> n values of y        B1 [m][4][y][kx]
-//   Q2 x-pass     per (member, y) row: C2R transforms of (u + iv), omega and
-//                 rho, the products at every point, R2C of
-//                 (v omega - i u omega) and (rho u + i rho v), keep kx <= K
-//                                                                 B2 [m][4][y][kx]
-//   Q3 y-forward  n values of y -> 2K+1 retained ky, then projection,
-//                 buoyancy, diffusion and the cast to FP64, fused.
-#include "pass_common.hpp"
+// Host side of the 2D right-hand side: dispatch over grid sizes.  The
+// kernels are in rhs2d_kernels.hpp; the zero-padded grids of the 3/2 rule
+// (n = 3 * 2^k) are instantiated in rhs2d_pad.hip.
+#include "rhs2d_kernels.hpp"
 
 namespace nsk {
 
-// ---------------------------------------------------------------- Q1
-// CW: column tile width (0 = the default); narrower tiles give more blocks
-// but shorter runs per row.
-template <class PL, typename T, int CW>
-__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k2_yinv(const double2* __restrict__ U,
-                                                              cplx<T>* __restrict__ B1, Geom g,
-                                                              int nfield, long long nblocks,
-                                                              const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
-  using V = cplx<T>;
-  using CF = ColCfg<PL, T, CW>;
-  constexpr int E = CF::E, C = CF::C;
-  __shared__ V lds[C * CF::LD];
-  const long long L = xcd_logical(blockIdx.x, gridDim.x);
-  if (L >= nblocks) return;                    // uniform per block
-  const int ntiles = (g.Kx + C - 1) / C;
-  const int f = (int)(L % nfield);
-  const long long q = L / nfield;
-  const int tile = (int)(q % ntiles);
-  const int m = (int)(q / ntiles);
-  const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = tile * C + lc;
-  const bool valid = kx < g.Kx;
-  const long long cs = g.mr;
-  const double2* Um = U + (long long)m * g.ncomp * cs + (valid ? kx : 0);
-  // field f: 0 u, 1 v, 2 omega = i (kx v - ky u), 3 rho
-  const int ca = f == 2 ? 1 : (f == 3 ? 2 : f);
-  double2 a[E], b[E];
-  bool use[E];
-  int kys[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = in_pos<PL>(t, i);
-    const bool ret = (e <= g.K) || (e >= N - g.K);
-    use[i] = valid && ret;
-    const int ky = e <= g.K ? e : e - N;
-    kys[i] = ky;
-    const int kyp = ret ? (ky >= 0 ? ky : ky + g.Kf) : 0;
-    const double2* pp = Um + (long long)kyp * g.Kx;
-    a[i] = pp[ca * cs];
-    if (f == 2) b[i] = pp[0];
-  }
-  V v[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    double vx = a[i].x, vy = a[i].y;
-    if (f == 2) {
-      const double ky = kys[i];
-      const double wr = kx * a[i].x - ky * b[i].x, wi = kx * a[i].y - ky * b[i].y;
-      vx = -wi;
-      vy = wr;
-    }
-    v[i] = use[i] ? mk<V>((T)vx, (T)vy) : mk<V>((T)0, (T)0);
-  }
-  fft_regs<PL, +1>(v, t, lds + lc * CF::LD, tw);
-  if (valid) {
-    V* out = B1 + ((long long)(m * 4 + f) * N) * g.Kx + kx;
-#pragma unroll
-    for (int i = 0; i < E; ++i) out[(long long)out_pos<PL>(t, i) * g.Kx] = v[i];
-  }
-}
-
-// ---------------------------------------------------------------- Q2
-// Split a forward transform of (a + ib) held at out_pos registers into the
-// half spectra of a and b at position pos, the mirror value from the partner.
-template <class PL, typename V, typename T>
-__device__ __forceinline__ void split_pair(const V (&z)[PL::E], int i, int t, int partner, V& ah, V& bh) {
-  constexpr int TT = PL::TT;
-  V pv = z[mirror_reg<PL>(i, true)];
-  if constexpr (TT > 1) {
-    const V sh = shfl_c(z[mirror_reg<PL>(i, false)], partner, TT);
-    if (t != 0) pv = sh;
-  }
-  const T half = (T)0.5;
-  const V zk = z[i];
-  ah = mk<V>(half * (zk.x + pv.x), half * (zk.y - pv.y));
-  bh = mk<V>(half * (zk.y + pv.y), half * (pv.x - zk.x));
-}
-
-template <class PL, typename T, bool SCALAR>
-__global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k2_xpass(const cplx<T>* __restrict__ B1,
-                                                               cplx<T>* __restrict__ B2, Geom g,
-                                                               long long nrows,
-                                                               const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
-  using V = cplx<T>;
-  using RC = RowCfg<PL, T>;
-  constexpr int E = RC::E, TT = RC::TT;
-  static_assert(64 % TT == 0, "a row's threads must lie in one wavefront");
-  __shared__ V lds[RC::RPB * RC::LD];
-  const int grp = threadIdx.x / TT, t = threadIdx.x - grp * TT;
-  const long long row = (long long)blockIdx.x * RC::RPB + grp;
-  const bool valid = row < nrows;
-  const long long m = valid ? row / N : 0, y = valid ? row - m * N : 0;
-  const int K = g.K, Kx = g.Kx;
-  const T zero = (T)0;
-  V* buf = lds + grp * RC::LD;
-  const long long fs = (long long)N * Kx;          // field stride
-  const V* base = B1 + (m * 4 * N + y) * Kx;
-
-  int kk[E];
-  T sg[E];
-  bool use[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int pos = in_pos<PL>(t, i);
-    const bool lo = pos <= K, hi = pos >= N - K;
-    use[i] = valid && (lo || hi);
-    const int k0 = lo ? pos : N - pos;
-    kk[i] = k0 <= K ? k0 : K;
-    sg[i] = lo ? (T)1 : (T)-1;
-  }
-  // Z = A + iB at k <= K, conj(A) + i conj(B) at N - k.  Transforms:
-  // (u + iv), (omega + 0i) and, with the scalar, (rho + 0i): rho is not
-  // packed with omega, whose magnitude (~|k||u|) would swamp its rounding.
-  constexpr int NZ = SCALAR ? 3 : 2;
-  V z[NZ][E];
-#pragma unroll
-  for (int p = 0; p < NZ; ++p) {
-    V a[E], b[E];
-    const V* pa = base + (p == 0 ? 0 : p + 1) * fs;      // fields u | omega | rho
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      a[i] = pa[kk[i]];
-      b[i] = p == 0 ? pa[fs + kk[i]] : mk<V>(zero, zero);
-    }
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const T ay = kk[i] == 0 ? zero : a[i].y, by = kk[i] == 0 ? zero : b[i].y;
-      const V r = mk<V>(a[i].x - sg[i] * by, sg[i] * ay + b[i].x);
-      z[p][i] = use[i] ? r : mk<V>(zero, zero);
-    }
-  }
-  fft_regs<PL, +1, V, true, true>(z[0], t, buf, tw);
-  group_sync<true>();
-  fft_regs<PL, +1, V, true, true>(z[1], t, buf, tw);
-  if constexpr (SCALAR) {
-    group_sync<true>();
-    fft_regs<PL, +1, V, true, true>(z[NZ - 1], t, buf, tw);
-  }
-
-  // products at every point: n = (v w, -u w), q = (rho u, rho v)
-  V nn[E], qq[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const T u = z[0][i].x, v = z[0][i].y, w = z[1][i].x, r = SCALAR ? z[NZ - 1][i].x : zero;
-    nn[out_to_in<PL>(i)] = mk<V>(v * w, -(u * w));
-    qq[out_to_in<PL>(i)] = mk<V>(r * u, r * v);
-  }
-  group_sync<true>();
-  fft_regs<PL, -1, V, true, true>(nn, t, buf, tw);
-  if constexpr (SCALAR) {
-    group_sync<true>();
-    fft_regs<PL, -1, V, true, true>(qq, t, buf, tw);
-  }
-  const int partner = (TT - t) & (TT - 1);
-  V* out = B2 + (m * 4 * N + y) * Kx;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    V nx, ny, qx, qy;
-    split_pair<PL, V, T>(nn, i, t, partner, nx, ny);
-    if constexpr (SCALAR) split_pair<PL, V, T>(qq, i, t, partner, qx, qy);
-    const int pos = out_pos<PL>(t, i);
-    if (valid && pos <= K) {
-      out[pos] = nx;
-      out[fs + pos] = ny;
-      if constexpr (SCALAR) {
-        out[2 * fs + pos] = qx;
-        out[3 * fs + pos] = qy;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------- Q3
-// One block per tile of C columns kx; the NF transformed fields of a column
-// are transformed side by side by NF thread groups (so that a 1024-point
-// column still gives enough blocks), their outputs meet in LDS, and the
-// epilogue's modes are shared out over all groups.  CMAX caps the tile
-// width (fewer columns per block, more blocks).
-template <class PL, typename T, int NF, int CMAX = 8> struct Q3Cfg {
-  static constexpr int N = PL::N;
-  static constexpr int TT = N / PL::E;
-  static constexpr int LD = N + 1;
-  static constexpr int LDS_BUDGET = 160 * 1024;
-  static constexpr int C =
-      cmax(1, cmin(cmin(1024 / (TT * NF), CMAX), floor_pow2(LDS_BUDGET / (NF * LD * (int)sizeof(cplx<T>)))));
-  static constexpr int NT = C * TT * NF;
-};
-
-template <class PL, typename T, bool SCALAR, int CMAX>
-__global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_yfwd(const cplx<T>* __restrict__ B2,
-                                                                          const double2* __restrict__ U,
-                                                                          double2* __restrict__ Kout, Geom g,
-                                                                          const double* __restrict__ nu,
-                                                                          double ri, double kappa,
-                                                                          const cplx<T>* __restrict__ tw) {
-  constexpr int N = PL::N;
-  constexpr int NF = SCALAR ? 4 : 2;
-  using V = cplx<T>;
-  using QC = Q3Cfg<PL, T, NF, CMAX>;
-  constexpr int E = PL::E, C = QC::C, TT = QC::TT, LD = QC::LD;
-  __shared__ V lds[NF * C * LD];
-  const int f = threadIdx.x / (C * TT);
-  const int rem = threadIdx.x - f * (C * TT);
-  const int lc = rem % C, t = rem / C;
-  const int kx = blockIdx.x * C + lc;
-  const int m = blockIdx.y;
-  const bool valid = kx < g.Kx;
-  V* buf = lds + (f * C + lc) * LD;
-  V o[E];
-  {
-    const V* in = B2 + ((long long)(m * 4 + f) * N) * g.Kx + (valid ? kx : 0);
-#pragma unroll
-    for (int i = 0; i < E; ++i) o[i] = in[(long long)in_pos<PL>(t, i) * g.Kx];
-  }
-  fft_regs<PL, -1>(o, t, buf, tw);
-  __syncthreads();                               // every group done with its exchanges
-#pragma unroll
-  for (int i = 0; i < E; ++i) buf[out_pos<PL>(t, i)] = o[i];
-  __syncthreads();
-  if (!valid) return;
-  const double scale = 1.0 / ((double)N * (double)N);
-  const double num = nu[m];
-  const long long cs = g.mr;
-  const V* col0 = lds + lc * LD;                 // field c of this column: col0 + c * C * LD
-#pragma unroll
-  for (int i = f; i < E; i += NF) {
-    const int e = out_pos<PL>(t, i);
-    if (!((e <= g.K) || (e >= N - g.K))) continue;
-    const int ky = e <= g.K ? e : e - N;
-    const long long idx = (long long)m * g.ncomp * cs + (long long)(ky >= 0 ? ky : ky + g.Kf) * g.Kx + kx;
-    const double k2 = (double)(kx * kx + ky * ky);
-    const V v0 = col0[e], v1 = col0[C * LD + e];
-    double nx = (double)v0.x * scale, nxi = (double)v0.y * scale;
-    double ny = (double)v1.x * scale, nyi = (double)v1.y * scale;
-    if (k2 == 0.0) {
-      Kout[idx] = make_double2(0.0, 0.0);
-      Kout[idx + cs] = make_double2(0.0, 0.0);
-      if constexpr (SCALAR) Kout[idx + 2 * cs] = make_double2(0.0, 0.0);
-      continue;
-    }
-    const double2 u0 = U[idx], u1 = U[idx + cs];
-    double2 rh = make_double2(0.0, 0.0);
-    if constexpr (SCALAR) {
-      rh = U[idx + 2 * cs];
-      ny -= ri * rh.x;               // buoyancy -Ri rho e_y, before the projection
-      nyi -= ri * rh.y;
-    }
-    const double px = (kx * nx + ky * ny) / k2, py = (kx * nxi + ky * nyi) / k2;
-    const double vk = num * k2;
-    Kout[idx] = make_double2(nx - kx * px - vk * u0.x, nxi - kx * py - vk * u0.y);
-    Kout[idx + cs] = make_double2(ny - ky * px - vk * u1.x, nyi - ky * py - vk * u1.y);
-    if constexpr (SCALAR) {
-      // -i k . q_hat - kappa |k|^2 rho_hat
-      const V v2 = col0[2 * C * LD + e], v3 = col0[3 * C * LD + e];
-      const double sx = kx * ((double)v2.x * scale) + ky * ((double)v3.x * scale);
-      const double sy = kx * ((double)v2.y * scale) + ky * ((double)v3.y * scale);
-      const double kk2 = kappa * k2;
-      Kout[idx + 2 * cs] = make_double2(sy - kk2 * rh.x, -sx - kk2 * rh.y);
-    }
-  }
-}
-
-// ---------------------------------------------------------------- host side
-// Launch variants (the autotuner's choice; grids below 256 points use 0):
-// Q1 (tuning slot 0) 0 default tile, 1 four columns, 2 two columns, 3 narrow
-// plan default tile, 4 narrow plan two columns; Q3 (slot 4) 0 up to eight
-// columns, 1 two, 2 one, 3 narrow plan up to eight, 4 narrow plan one.  The
-// x-pass keeps the wide plan (a row stays inside one wavefront).
-template <int N, int V> struct Q1Var {
-  using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
-  static constexpr int CW = N < 256 ? 0 : (V == 1 ? 4 : (V == 2 || V == 4 ? 2 : 0));
-};
-template <int N, int V> struct Q3Var {
-  using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
-  static constexpr int CMAX = N < 256 ? 8 : (V == 1 ? 2 : (V == 2 || V == 4 ? 1 : 8));
-};
-
-template <int N, typename T, int VAR>
-static void launch_q1(const Geom& g, const double2* U, cplx<T>* B1, int nfield, const cplx<T>* tw,
-                      hipStream_t st) {
-  using QV = Q1Var<N, VAR>;
-  using CF = ColCfg<typename QV::PL, T, QV::CW>;
-  const long long nb1 = (long long)g.batch * nfield * ((g.Kx + CF::C - 1) / CF::C);
-  const long long nb1p = (nb1 + 7) / 8 * 8;
-  hipLaunchKernelGGL((k2_yinv<typename QV::PL, T, QV::CW>), dim3((unsigned)nb1p), dim3(CF::NT), 0, st, U, B1, g,
-                     nfield, nb1, tw);
-}
-template <int N, typename T, bool SCALAR, int VAR>
-static void launch_q3(const Geom& g, const cplx<T>* B2, const double2* U, double2* K, const RhsParams& p,
-                      const cplx<T>* tw, hipStream_t st) {
-  using QV = Q3Var<N, VAR>;
-  using QC = Q3Cfg<typename QV::PL, T, SCALAR ? 4 : 2, QV::CMAX>;
-  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX>), dim3((g.Kx + QC::C - 1) / QC::C, g.batch),
-                     dim3(QC::NT), 0, st, B2, U, K, g, p.nu, p.ri, p.kappa, tw);
-}
-
-template <int N, typename T, bool SCALAR>
-static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
-                        const RhsBufs& bufs, const void* twv, hipStream_t st) {
-  using V = cplx<T>;
-  using PL = Plan<N>;
-  using RC = RowCfg<PL, T>;
-  const V* tw = (const V*)twv;
-  V* B1 = (V*)bufs.a1;
-  V* B2 = (V*)bufs.a2;
-  const int nfield = SCALAR ? 4 : 3;
-  // variants only matter (and are only built) from 256 points on
-  const int v1 = N >= 256 ? bufs.variant[0] : 0, v3 = N >= 256 ? bufs.variant[4] : 0;
-#define NSK_MARK(id, ph) \
-  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, st)
-  NSK_MARK(PROF_P1, 0);
-  switch (v1) {
-    case 1: launch_q1<N, T, N >= 256 ? 1 : 0>(g, U, B1, nfield, tw, st); break;
-    case 2: launch_q1<N, T, N >= 256 ? 2 : 0>(g, U, B1, nfield, tw, st); break;
-    case 3: launch_q1<N, T, N >= 256 ? 3 : 0>(g, U, B1, nfield, tw, st); break;
-    case 4: launch_q1<N, T, N >= 256 ? 4 : 0>(g, U, B1, nfield, tw, st); break;
-    default: launch_q1<N, T, 0>(g, U, B1, nfield, tw, st);
-  }
-  NSK_MARK(PROF_P1, 1);
-  const long long rows = (long long)g.batch * N;
-  NSK_MARK(PROF_P3, 0);
-  hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
-                     dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
-  NSK_MARK(PROF_P3, 1);
-  NSK_MARK(PROF_P5, 0);
-  switch (v3) {
-    case 1: launch_q3<N, T, SCALAR, N >= 256 ? 1 : 0>(g, B2, U, K, p, tw, st); break;
-    case 2: launch_q3<N, T, SCALAR, N >= 256 ? 2 : 0>(g, B2, U, K, p, tw, st); break;
-    case 3: launch_q3<N, T, SCALAR, N >= 256 ? 3 : 0>(g, B2, U, K, p, tw, st); break;
-    case 4: launch_q3<N, T, SCALAR, N >= 256 ? 4 : 0>(g, B2, U, K, p, tw, st); break;
-    default: launch_q3<N, T, SCALAR, 0>(g, B2, U, K, p, tw, st);
-  }
-  NSK_MARK(PROF_P5, 1);
-#undef NSK_MARK
-  return hipGetLastError();
-}
+template <typename T, bool SCALAR>
+hipError_t dispatch2d_padded(const Geom& g, const double2* U, double2* K, const RhsParams& p,
+                             const RhsBufs& b, const void* tw, hipStream_t st);
 
 template <typename T, bool SCALAR>
 static hipError_t dispatch2d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
@@ -371,7 +21,7 @@ static hipError_t dispatch2d(const Geom& g, const double2* U, double2* K, const 
     case 256: return run2d<256, T, SCALAR>(g, U, K, p, b, tw, st);
     case 512: return run2d<512, T, SCALAR>(g, U, K, p, b, tw, st);
     case 1024: return run2d<1024, T, SCALAR>(g, U, K, p, b, tw, st);
-    default: return hipErrorInvalidValue;
+    default: return dispatch2d_padded<T, SCALAR>(g, U, K, p, b, tw, st);
   }
 }
 

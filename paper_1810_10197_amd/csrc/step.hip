@@ -363,6 +363,13 @@ hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, do
       case 256: launch_reduce<256, 2>(g, a, partials, nblk, nvel, st); break;
       case 512: launch_reduce<512, 2>(g, a, partials, nblk, nvel, st); break;
       case 1024: launch_reduce<1024, 2>(g, a, partials, nblk, nvel, st); break;
+      case 24: launch_reduce<24, 2>(g, a, partials, nblk, nvel, st); break;
+      case 48: launch_reduce<48, 2>(g, a, partials, nblk, nvel, st); break;
+      case 96: launch_reduce<96, 2>(g, a, partials, nblk, nvel, st); break;
+      case 192: launch_reduce<192, 2>(g, a, partials, nblk, nvel, st); break;
+      case 384: launch_reduce<384, 2>(g, a, partials, nblk, nvel, st); break;
+      case 768: launch_reduce<768, 2>(g, a, partials, nblk, nvel, st); break;
+      case 1536: launch_reduce<1536, 2>(g, a, partials, nblk, nvel, st); break;
       default: return hipErrorInvalidValue;
     }
   }

@@ -42,6 +42,7 @@ def test_host_only_entry_points(lib):
     assert ns.ns_workspace_bytes(ok) > 0
     assert ns.ns_workspace_bytes(ns.NsConfig(2, 1024, 1, 0, 1, 0.5, 1e-4, 0, 0)) > 0
     assert ns.ns_workspace_bytes(ns.NsConfig(2, 64, 3, 1, 0, 0, 0, 0, 0)) > 0
+    assert ns.ns_workspace_bytes(ns.NsConfig(2, 1024, 1, 0, 1, 0.5, 1e-4, 0, 0, 1)) > 0   # 3/2 rule
     for bad in [ns.NsConfig(3, 48, 1, 0, 0, 0, 0, 0, 0),     # not a power of two
                 ns.NsConfig(3, 1024, 1, 0, 0, 0, 0, 0, 0),   # 3D limited to 512
                 ns.NsConfig(4, 32, 1, 0, 0, 0, 0, 0, 0),
@@ -50,7 +51,6 @@ def test_host_only_entry_points(lib):
                 ns.NsConfig(3, 32, 1, 0, 1, 0, 0, 0, 0),     # scalar needs 2D
                 ns.NsConfig(2, 2048, 1, 0, 1, 0, 0, 0, 0),   # 2D limited to 1024
                 ns.NsConfig(3, 32, 1, 0, 0, 0, 0, 0, 0, 2),  # no such dealiasing rule
-                ns.NsConfig(2, 64, 1, 0, 0, 0, 0, 0, 0, 1),  # 3/2 rule: 3D only
                 ns.NsConfig(3, 8, 1, 0, 0, 0, 0, 0, 0, 1)]:  # 3/2 rule: n >= 16
         assert ns.ns_workspace_bytes(bad) == 0
     assert ns.ns_strerror(ns.NS_ERR_STEPFAIL).startswith("too many")

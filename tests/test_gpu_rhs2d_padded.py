@@ -1,0 +1,94 @@
+"""GPU parity of the 2D right-hand sides (plain and Boussinesq, Sec. 3.2)
+under the 3/2 rule of Sec. 2.1.1 (products on the zero-padded 3N/2 grid,
+truncated back to |k_j| <= N/2 - 1) against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, per_field_rel_l2
+from oracle import control, spectral
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ns():
+    from paper_1810_10197_amd import ns as mod
+    return mod
+
+
+def band_field(n, seed, ncomp):
+    """Random real state over the whole 3/2-rule band: a solenoidal velocity
+    from a stream function and (ncomp = 3) a scalar, spectra falling off as
+    exp(-|k|^2 / (n/4)^2) (test input)."""
+    rng = np.random.default_rng(seed)
+    keep = spectral.mask_padded(n, 2)
+    kx, ky = spectral.wavenumbers(n, 2)
+    env = np.exp(-(kx * kx + ky * ky) / (n / 4.0) ** 2) * keep
+    psi = spectral.forward(rng.standard_normal((n, n)), 2) * env
+    st = np.zeros((ncomp, n, n // 2 + 1), dtype=complex)
+    st[0] = 1j * ky * psi
+    st[1] = -1j * kx * psi
+    if ncomp == 3:
+        st[2] = spectral.forward(rng.standard_normal((n, n)), 2) * env
+    return spectral.forward(spectral.inverse(st, n, 2), 2) * keep
+
+
+def solver(ns, n, prec, scalar, nu, kappa=0.0, ri=0.0):
+    return ns.Solver(dim=2, n=n, nu=nu, rhs_precision=prec, scalar=scalar, ri=ri, kappa=kappa,
+                     dealias="3/2")
+
+
+@pytest.mark.parametrize("n,scalar", [(16, 0), (64, 0), (256, 0), (32, 1), (128, 1), (1024, 1)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_padded_rhs2d_matches_oracle(ns, n, scalar, prec):
+    announce("padded rhs2d n=%d scalar=%d %s" % (n, scalar, prec))
+    nu, kappa, ri = 1e-3, 2e-3, 0.5
+    st = band_field(n, 7 * n + scalar, 3 if scalar else 2)
+    s = solver(ns, n, prec, scalar, nu, kappa, ri)
+    got = s.rhs(st[None]).cpu().numpy()[0]
+    s.close()
+    ref = (spectral.rhs_ns2d_padded(st, nu, kappa, ri) if scalar
+           else spectral.rhs_ns2d_padded(st, nu))
+    err = max(per_field_rel_l2(got, ref))
+    assert err <= (1e-12 if prec == "fp64" else 3e-6), err
+    keep = np.broadcast_to(spectral.mask_padded(n, 2), got.shape[1:])
+    assert np.all(got[:, ~keep] == 0)
+
+
+@pytest.mark.parametrize("n", [256, 1024])
+def test_padded_rhs2d_every_launch_variant(ns, n):
+    """Every Q1/Q3 variant on the padded 384^2 and 1536^2 grids (the narrow
+    four-pass plan at 384), and the autotuner's pick."""
+    announce("padded rhs2d variants n=%d" % n)
+    nu, kappa, ri = 1e-3, 2e-3, 0.5
+    st = band_field(n, 11 * n, 3)
+    ref = spectral.rhs_ns2d_padded(st, nu, kappa, ri)
+    s = solver(ns, n, "fp32", 1, nu, kappa, ri)
+    for v in range(5):
+        s.tune([v, 0, 0, 0, 4 - v, 0])
+        got = s.rhs(st[None]).cpu().numpy()[0]
+        err = max(per_field_rel_l2(got, ref))
+        assert err <= 3e-6, (v, err)
+    s.set_state(st[None])
+    variants, ms = s.autotune(reps=2)
+    got = s.rhs(st[None]).cpu().numpy()[0]
+    assert max(per_field_rel_l2(got, ref)) <= 3e-6
+    s.close()
+
+
+def test_padded_boussinesq_integrate_matches_oracle_controller(ns):
+    """Adaptive BS5 (graph replay) on the 3/2-rule Boussinesq system: same
+    decisions, right-hand-side count and final state as the oracle (FP64)."""
+    n, nu, kappa, ri = 32, 2e-3, 2e-3, 0.5
+    announce("padded boussinesq integrate n=%d fp64" % n)
+    st = band_field(n, 97, 3) * 3.0
+    ref = control.integrate(lambda u: spectral.rhs_ns2d_padded(u, nu, kappa, ri), st, t_end=0.5,
+                            h0=0.1, atol=1e-8, rtol=1e-8)
+    s = solver(ns, n, "fp64", 1, nu, kappa, ri)
+    s.set_state(st[None])
+    stats = s.integrate(0.5, 0.1, 1e-8, 1e-8)[0]
+    got = s.get_state().cpu().numpy()[0]
+    s.close()
+    assert (stats["n_accept"], stats["n_reject"], stats["n_rhs"]) == \
+        (ref["n_accept"], ref["n_reject"], ref["n_rhs"])
+    assert np.abs(got - ref["u"]).max() <= 1e-12 * np.abs(ref["u"]).max()
