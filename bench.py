@@ -60,8 +60,9 @@ def pass_bytes(n, fp64=False, stage32=False):
     member): reads + writes of the retained-mode pencil model.  cb = bytes per
     complex value in the rhs precision; the state is read in FP64 (16 bytes),
     or (stage32: a stage of an FP32 step, whose input is written in FP32) in
-    FP32, and f is written in FP64.  The y/x/y passes run in slabs of z
-    planes; one launch covers its slab's share."""
+    FP32, and f is written in FP64 -- in a BS5 step 6 of the 7 stage
+    evaluations also write f's FP32 copy, counted here on average.  The y/x/y
+    passes run in slabs of z planes; one launch covers its slab's share."""
     K = (n - 1) // 3
     Kf, Kx = 2 * K + 1, K + 1
     mr = Kf * Kf * Kx
@@ -74,7 +75,7 @@ def pass_bytes(n, fp64=False, stage32=False):
         "yinv": 6 * c1 * cb + 6 * c2 * cb,
         "xpass": 6 * c2 * cb + 3 * c2 * cb,
         "yfwd": 3 * c2 * cb + 3 * c1 * cb,
-        "zfwd": 3 * c1 * cb + 3 * mr * sb + 3 * mr * 16,
+        "zfwd": 3 * c1 * cb + 3 * mr * sb + 3 * mr * 16 + (3 * mr * 8 * 6 // 7 if stage32 else 0),
     }
 
 

@@ -110,7 +110,7 @@ struct Layout {
   size_t tw32, tw64, nu, h, red_out, mask, alpha, red_part;
   size_t ctl_d[6], ctl_i[7], ctl_l[3];
   size_t mw, mmom, mvel, mgrad, mloss, mx, my, pend_x, pend_h, pend_ok, ring_x, ring_y, ring_n, rows, act;
-  size_t fields[10], stage32, dpart, a1, a2, total;
+  size_t fields[10], stage32, dpart, k32, a1, a2, total;
 };
 
 Layout make_layout(const ns_config* c) {
@@ -148,6 +148,10 @@ Layout make_layout(const ns_config* c) {
   for (int i = 0; i < 10; ++i) L.fields[i] = take((size_t)g.epm * B * 16);
   L.stage32 = take((size_t)g.epm * B * 8);   // FP32 stage input of an FP32 3D right-hand side
   L.dpart = take((size_t)g.epm * B * 16);    // sum_{j<S} (b_j - bh_j) k_j, from the last combination
+  // FP32 copies of the stage derivatives (3D FP32 right-hand side): the
+  // sources of the stage combinations whose result is an FP32 stage input
+  const bool s32 = c->dim == 3 && c->rhs_precision == NS_FP32;
+  L.k32 = take(s32 ? (size_t)g.epm * B * 8 * 8 : 0);
   const int fp64 = c->rhs_precision == NS_FP64;
   const size_t scratch = c->dim == 3 ? nsk::rhs3d_scratch_bytes(g, fp64) : nsk::rhs2d_scratch_bytes(g, fp64);
   const size_t cb = fp64 ? 16 : 8;
@@ -179,6 +183,7 @@ struct ns_solver {
   float2* U32;       // stage state rounded to FP32: the input of an FP32 3D right-hand side
   double2* dpart;    // embedded difference over all stages but the last (written with u_{n+1})
   double2* k[8];     // stage derivatives; k[0] = f(u_n) when k1_valid
+  float2* k32[8];    // their FP32 copies (3D FP32 right-hand side; else null), kept in step with k
   nsk::RhsBufs rb;
   nsk::CtlState ctl;
   // proposer network
@@ -233,11 +238,22 @@ static void prof_hook(void* ctx, int id, int phase, hipStream_t st) {
     if ((call) != hipSuccess) return NS_ERR_HIP;  \
   } while (0)
 
-static int rhs(ns_solver* s, const double2* U, double2* K) {
+// FP32 copy slot of a stage-derivative buffer (null if K is not one of them
+// or there are no copies).
+static float2* k32_of(const ns_solver* s, const double2* K) {
+  for (int j = 0; j < 8; ++j)
+    if (s->k[j] == K) return s->k32[j];
+  return nullptr;
+}
+
+// want32: also write the FP32 copy of K (a later FP32 stage combination
+// reads it).
+static int rhs(ns_solver* s, const double2* U, double2* K, bool want32 = false) {
   nsk::RhsParams p;
   p.nu = s->nu_d;
   p.ri = s->cfg.ri;
   p.kappa = s->cfg.kappa;
+  p.k32 = want32 ? k32_of(s, K) : nullptr;
   hipError_t e = s->g.dim == 3 ? nsk::rhs3d_compact(s->g, s->fp64, U, nullptr, K, p, s->rb, s->tw, s->st)
                                : nsk::rhs2d_compact(s->g, s->fp64, U, K, p, s->rb, s->tw, s->st);
   return e == hipSuccess ? NS_OK : NS_ERR_HIP;
@@ -250,11 +266,20 @@ static int rhs(ns_solver* s, const double2* U, double2* K) {
 static bool stage32(const ns_solver* s) { return s->g.dim == 3 && !s->fp64; }
 
 // U_i = u + h sum_j c_j k_j and k_i = f(U_i); keep64: also write U_i in FP64;
-// dpart (not null): also sum_j coef2_j k_j from the same loads.
-static int stage(ns_solver* s, const Combo& c, const double* h, bool keep64, double2* K,
+// dpart (not null): also sum_j coef2_j k_j from the same loads.  A stage that
+// is only an FP32 input reads the FP32 copies of the k_j; want32: write the
+// FP32 copy of k_i too.
+static int stage(ns_solver* s, Combo c, const double* h, bool keep64, double2* K, bool want32,
                  double2* dpart = nullptr) {
   prof_hook(s, nsk::PROF_COMBINE, 0, s->st);
-  if (stage32(s)) {
+  bool from32 = stage32(s) && !keep64 && !dpart && c.nterms > 0;
+  for (int j = 0; j < c.nterms && from32; ++j) {
+    c.src32[j] = k32_of(s, c.src[j]);
+    from32 = c.src32[j] != nullptr;
+  }
+  if (from32) {
+    NS_HIP(nsk::combine_s32(s->g, s->u, c, h, s->U32, s->st));
+  } else if (stage32(s)) {
     NS_HIP(nsk::combine2(s->g, s->u, c, h, keep64 ? s->U : nullptr, s->U32, dpart, s->st));
   } else if (dpart) {
     NS_HIP(nsk::combine2(s->g, s->u, c, h, s->U, nullptr, dpart, s->st));
@@ -262,18 +287,19 @@ static int stage(ns_solver* s, const Combo& c, const double* h, bool keep64, dou
     NS_HIP(nsk::combine(s->g, s->u, c, h, s->U, s->st));
   }
   prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
-  if (!stage32(s)) return rhs(s, s->U, K);
+  if (!stage32(s)) return rhs(s, s->U, K, want32);
   nsk::RhsParams p;
   p.nu = s->nu_d;
   p.ri = s->cfg.ri;
   p.kappa = s->cfg.kappa;
+  p.k32 = want32 ? k32_of(s, K) : nullptr;
   const hipError_t e = nsk::rhs3d_compact(s->g, 0, nullptr, s->U32, K, p, s->rb, s->tw, s->st);
   return e == hipSuccess ? NS_OK : NS_ERR_HIP;
 }
 
 static int ensure_k1(ns_solver* s) {
   if (s->k1_valid) return NS_OK;
-  int rc = rhs(s, s->u, s->k[0]);
+  int rc = rhs(s, s->u, s->k[0], true);
   if (rc == NS_OK) s->k1_valid = true;
   return rc;
 }
@@ -313,7 +339,11 @@ static int embedded_stages(ns_solver* s, const Pair& P, const double* h, double 
       ++c.nterms;
     }
     const bool last = i == S - 1;
-    int rc = stage(s, c, h, last, s->k[i], last && fused ? s->dpart : nullptr);
+    // FP32 copy of k_i: read by a later stage that is only an FP32 input, or
+    // (the last stage, FSAL) by the next attempt's
+    bool want32 = last;
+    for (int r = i + 1; r < S - 1; ++r) want32 = want32 || P.a(r, i) != 0.0;
+    int rc = stage(s, c, h, last, s->k[i], want32, last && fused ? s->dpart : nullptr);
     if (rc) return rc;
   }
   nsk::ReduceArgs ra;
@@ -397,6 +427,7 @@ static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
   if (nacc == s->g.batch) {
     std::swap(s->u, s->U);
     std::swap(s->k[0], s->k[last]);
+    std::swap(s->k32[0], s->k32[last]);
     if (s->gexec) {                            // the captured graph holds the old pointers
       (void)hipGraphExecDestroy(s->gexec);
       s->gexec = nullptr;
@@ -404,6 +435,7 @@ static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
   } else if (nacc > 0) {
     NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->mask_d, s->st));
     NS_HIP(nsk::masked_copy(s->g, s->k[last], s->k[0], s->mask_d, s->st));
+    if (s->k32[0]) NS_HIP(nsk::masked_copy32(s->g, s->k32[last], s->k32[0], s->mask_d, s->st));
   }
   if (nacc > 0) return apply_forcing(s, s->mask_d);
   return NS_OK;
@@ -428,10 +460,11 @@ static int integrate_attempt(ns_solver* s, const Pair& P, double atol, double rt
                              RING_CAP, s->g.batch, s->st));
   NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->ctl.accept, s->st));
   NS_HIP(nsk::masked_copy(s->g, s->k[P.stages - 1], s->k[0], s->ctl.accept, s->st));
+  if (s->k32[0]) NS_HIP(nsk::masked_copy32(s->g, s->k32[P.stages - 1], s->k32[0], s->ctl.accept, s->st));
   if (s->cfg.force_kf > 0.0) {
     rc = apply_forcing(s, s->ctl.accept);
     if (rc) return rc;
-    rc = rhs(s, s->u, s->k[0]);
+    rc = rhs(s, s->u, s->k[0], true);
     if (rc) return rc;
     s->k1_valid = true;
   }
@@ -474,6 +507,8 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->U32 = (float2*)(w + L.stage32);
   s->dpart = (double2*)(w + L.dpart);
   for (int i = 0; i < 8; ++i) s->k[i] = (double2*)(w + L.fields[2 + i]);
+  for (int i = 0; i < 8; ++i)
+    s->k32[i] = stage32(s) ? (float2*)(w + L.k32) + (size_t)i * s->g.epm * s->g.batch : nullptr;
   s->rb.a1 = w + L.a1;
   s->rb.a2 = w + L.a2;
   s->rb.hook = prof_hook;
@@ -608,7 +643,7 @@ int ns_step_rk4(ns_solver* s, double h) {
     c.nterms = 1;
     c.src[0] = s->k[i - 1];
     c.coef[0] = stage_a[i - 1];
-    rc = stage(s, c, s->h_d, false, s->k[i]);
+    rc = stage(s, c, s->h_d, false, s->k[i], i < 3);
     if (rc) return rc;
   }
   Combo c;

@@ -25,6 +25,7 @@ struct Geom {
 struct RhsParams {
   const double* nu;   // [batch]
   double ri, kappa;   // Boussinesq
+  float2* k32 = nullptr;   // 3D FP32 right-hand side: also write f rounded to FP32 (may be null)
 };
 
 // Optional timing hook called around every kernel launch: phase 0 before,
@@ -68,6 +69,7 @@ hipError_t rhs2d_compact(const Geom& g, int fp64, const double2* U, double2* k,
 constexpr int MAXTERMS = 9;
 struct Combo {
   const double2* src[MAXTERMS];
+  const float2* src32[MAXTERMS];   // FP32 copies of the sources (combine_s32)
   double coef[MAXTERMS];
   int nterms;
   double coef2[MAXTERMS];   // second combination of the same sources (combine2's out2)
@@ -112,6 +114,12 @@ hipError_t scale_band(const Geom& g, double2* u, const double* alpha, double kf2
 
 // Copy member slices src -> dst for members with mask[m] != 0 (host mask copied
 // as a device array).
+// out32 = FP32 rounding of base + h_m sum_j coef_j src32_j, accumulated in FP64
+// from the FP32 copies of the sources (an FP32 stage input: its own rounding
+// exceeds that of the copies by the factor |U| / (h sum |a_j k_j|)).
+hipError_t combine_s32(const Geom& g, const double2* base, const Combo& c, const double* h, float2* out32,
+                       hipStream_t st);
+hipError_t masked_copy32(const Geom& g, const float2* src, float2* dst, const int* mask_dev, hipStream_t st);
 hipError_t masked_copy(const Geom& g, const double2* src, double2* dst, const int* mask_dev,
                        hipStream_t st);
 

@@ -383,6 +383,7 @@ template <class PL, typename T, int CW, typename UT>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>* __restrict__ A4,
                                                            const UT* __restrict__ U,
                                                            double2* __restrict__ Kout,
+                                                           float2* __restrict__ K32,
                                                            const double* __restrict__ nu,
                                                            const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
@@ -417,6 +418,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
   const double num = nu[m];
   const UT* Um = U + (long long)m * 3 * MR;
   double2* Km = Kout + (long long)m * 3 * MR;
+  float2* K32m = K32 ? K32 + (long long)m * 3 * MR : nullptr;     // uniform per launch
   const unsigned lo = (unsigned)(col + t * NCOL) * 16u;
   constexpr unsigned USZ = (unsigned)sizeof(UT);
 #pragma unroll
@@ -455,6 +457,12 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
     *byte_at(kp, off) = f0;
     *byte_at(kp + MR, off) = f1;
     *byte_at(kp + 2 * MR, off) = f2;
+    if (K32m) {
+      float2* kq = K32m + rowb * NCOL;
+      *byte_at(kq, off / 2u) = make_float2((float)f0.x, (float)f0.y);
+      *byte_at(kq + MR, off / 2u) = make_float2((float)f1.x, (float)f1.y);
+      *byte_at(kq + 2 * MR, off / 2u) = make_float2((float)f2.x, (float)f2.y);
+    }
   }
 }
 
@@ -510,15 +518,15 @@ static void launch_yfwd(const Geom& g, const cplx<T>* A3s, cplx<T>* A4, int z0, 
                      dim3(CF::NT), 0, st, A3s, A4, z0, zs, tw);
 }
 template <int N, typename T, int V, typename UT>
-static void launch_zfwd(const Geom& g, const cplx<T>* A4, const UT* U, double2* K, const double* nu,
-                        const cplx<T>* tw, hipStream_t st) {
+static void launch_zfwd(const Geom& g, const cplx<T>* A4, const UT* U, double2* K, float2* K32,
+                        const double* nu, const cplx<T>* tw, hipStream_t st) {
   // P5 holds three transformed fields: a 64-column block would exceed the
   // registers of 1024 threads, so its variant 4 is variant 1
   using CV = ColVar<N, V == 4 ? 1 : V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = g.Kf * g.Kx;
   hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW, UT>), dim3((ncol + CF::C - 1) / CF::C, g.batch),
-                     dim3(CF::NT), 0, st, A4, U, K, nu, tw);
+                     dim3(CF::NT), 0, st, A4, U, K, K32, nu, tw);
 }
 
 // Scratch regions of one evaluation (T complex), each 256-byte aligned: A1,
@@ -604,12 +612,13 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
   }
   NSK_MARK(PROF_SLAB, 1, st);
   NSK_MARK(PROF_P5, 0, st);
+  float2* k32 = sizeof(T) == 4 ? p.k32 : nullptr;   // FP32 copies only of an FP32 right-hand side
   switch (tv[4]) {
-    case 1: launch_zfwd<N, T, 1, UT>(g, A4, U, K, p.nu, tw, st); break;
-    case 2: launch_zfwd<N, T, 2, UT>(g, A4, U, K, p.nu, tw, st); break;
-    case 3: launch_zfwd<N, T, 3, UT>(g, A4, U, K, p.nu, tw, st); break;
-      case 4: launch_zfwd<N, T, 4, UT>(g, A4, U, K, p.nu, tw, st); break;
-    default: launch_zfwd<N, T, 0, UT>(g, A4, U, K, p.nu, tw, st);
+    case 1: launch_zfwd<N, T, 1, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
+    case 2: launch_zfwd<N, T, 2, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
+    case 3: launch_zfwd<N, T, 3, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
+    case 4: launch_zfwd<N, T, 4, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
+    default: launch_zfwd<N, T, 0, UT>(g, A4, U, K, k32, p.nu, tw, st);
   }
   NSK_MARK(PROF_P5, 1, st);
   return hipGetLastError();

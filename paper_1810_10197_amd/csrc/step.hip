@@ -86,6 +86,30 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ bas
   }
 }
 
+// out32 = base + h_m sum_j coef_j src32_j (FP64 accumulation of FP32 sources),
+// rounded to FP32.
+template <int NT>
+__global__ __launch_bounds__(256) void k_combine_s32(const double2* __restrict__ base, Combo c,
+                                                     const double* __restrict__ h, float2* __restrict__ out32,
+                                                     long long epm) {
+  const long long off = (long long)blockIdx.y * epm;
+  const double hm = h[blockIdx.y];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < epm; i += stride) {
+    float2 v[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) v[j] = c.src32[j][off + i];
+    double2 r = base[off + i];
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      sx += c.coef[j] * (double)v[j].x;
+      sy += c.coef[j] * (double)v[j].y;
+    }
+    out32[off + i] = make_float2((float)(r.x + hm * sx), (float)(r.y + hm * sy));
+  }
+}
+
 static unsigned grid_for(long long total, int bs) {
   long long b = (total + bs - 1) / bs;
   if (b > 65536) b = 65536;
@@ -105,6 +129,25 @@ static hipError_t combine_to(const Geom& g, const double2* base, const Combo& c,
       break;
     NSK_COMBINE(0) NSK_COMBINE(1) NSK_COMBINE(2) NSK_COMBINE(3) NSK_COMBINE(4)
     NSK_COMBINE(5) NSK_COMBINE(6) NSK_COMBINE(7) NSK_COMBINE(8) NSK_COMBINE(9)
+#undef NSK_COMBINE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t combine_s32(const Geom& g, const double2* base, const Combo& c, const double* h, float2* out32,
+                       hipStream_t st) {
+  if (!base || !out32) return hipErrorInvalidValue;
+  for (int j = 0; j < c.nterms; ++j)
+    if (!c.src32[j]) return hipErrorInvalidValue;
+  const dim3 grid = member_grid(g.epm, g.batch);
+  switch (c.nterms) {
+#define NSK_COMBINE(k)                                                                                  \
+    case k:                                                                                             \
+      hipLaunchKernelGGL((k_combine_s32<k>), grid, dim3(256), 0, st, base, c, h, out32, g.epm); \
+      break;
+    NSK_COMBINE(1) NSK_COMBINE(2) NSK_COMBINE(3) NSK_COMBINE(4) NSK_COMBINE(5)
+    NSK_COMBINE(6) NSK_COMBINE(7) NSK_COMBINE(8) NSK_COMBINE(9)
 #undef NSK_COMBINE
     default: return hipErrorInvalidValue;
   }
@@ -377,7 +420,8 @@ hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, do
   return hipGetLastError();
 }
 
-__global__ void k_masked_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+template <typename E>
+__global__ void k_masked_copy(const E* __restrict__ src, E* __restrict__ dst,
                               const int* __restrict__ mask, long long epm, long long total) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
@@ -429,7 +473,14 @@ hipError_t fill(double* p, double v, int n, hipStream_t st) {
 hipError_t masked_copy(const Geom& g, const double2* src, double2* dst, const int* mask_dev,
                        hipStream_t st) {
   const long long total = g.epm * g.batch;
-  hipLaunchKernelGGL(k_masked_copy, dim3(grid_for(total, 256)), dim3(256), 0, st, src, dst,
+  hipLaunchKernelGGL(k_masked_copy<double2>, dim3(grid_for(total, 256)), dim3(256), 0, st, src, dst,
+                     mask_dev, g.epm, total);
+  return hipGetLastError();
+}
+
+hipError_t masked_copy32(const Geom& g, const float2* src, float2* dst, const int* mask_dev, hipStream_t st) {
+  const long long total = g.epm * g.batch;
+  hipLaunchKernelGGL(k_masked_copy<float2>, dim3(grid_for(total, 256)), dim3(256), 0, st, src, dst,
                      mask_dev, g.epm, total);
   return hipGetLastError();
 }
