@@ -2,23 +2,24 @@
 // pseudo-spectral right-hand side (Sec. 2.1: the nonlinear term is formed in
 // physical space and transformed back).
 //
-// A length-N complex DFT is done as a mixed-radix Stockham sequence of
-// passes; each of the N/E threads that own one transform holds E values in
-// registers, runs radix-R butterflies on them (R in {2,4,8,16}), multiplies by
-// the inter-pass twiddles and exchanges through LDS between passes.  Pass p
-// with radix R and span NS (product of the earlier radices) reads element
+// A length-N complex DFT is done as a mixed-radix Stockham sequence of up to
+// four passes; each of the N/E threads that own one transform holds E values
+// in registers, runs radix-R butterflies on them (the first pass R = E in
+// {8, 12, 16, 24}, later passes R in {2, 4, 8, 16}), multiplies by the
+// inter-pass twiddles and exchanges through LDS between passes.  Pass p with
+// radix R and span NS (product of the earlier radices) reads element
 // j + r*N/R of butterfly j and writes element (j/NS)*NS*R + j%NS + r*NS; the
 // output comes out in natural order.
 //
 // Lengths are 2^k, or 3 * 2^k with a radix-24 (3 x 8) or radix-12 (3 x 4)
-// first pass.  Twiddles
-// come from a table of exp(-2 pi i m / TWN), m < TWN, computed on the host in
-// double precision (std::cos/std::sin) and rounded once; a pass
-// with radix R loads log2(R) entries per butterfly and multiplies them
-// together for the rest (see Tw below).  The
-// radix-8/16 butterfly constants are cos/sin of multiples of pi/8, written
-// from their half-angle closed forms: cos(pi/4) = sqrt(2)/2,
-// cos(pi/8) = sqrt(2+sqrt(2))/2, sin(pi/8) = sqrt(2-sqrt(2))/2.
+// first pass.  Twiddles come from a table of exp(-2 pi i m / TWN), m < TWN,
+// computed on the host in double precision (std::cos/std::sin) and rounded
+// once; a pass with radix R loads log2(R) entries per butterfly and
+// multiplies them together for the rest (see Tw below).  The radix-8/16
+// butterfly constants are cos/sin of multiples of pi/8, written from their
+// half-angle closed forms: cos(pi/4) = sqrt(2)/2, cos(pi/8) =
+// sqrt(2+sqrt(2))/2, sin(pi/8) = sqrt(2-sqrt(2))/2; those of the radix-3/12/24
+// butterflies are multiples of 15 degrees (below).
 #pragma once
 #include <hip/hip_runtime.h>
 
