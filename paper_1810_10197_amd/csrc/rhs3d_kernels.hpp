@@ -12,8 +12,9 @@
 //                 along z of 2K+1 non-zero inputs, for 6 fields (u, omega)
 //   P2 y-inverse  per (field, z) plane: 2K+1 non-zero ky -> n values of y
 //   P3 x-pass     per (z, y) row: three paired C2R transforms (two real
-//                 fields per complex DFT), u x omega at every point, R2C of
-//                 (n_x + i n_y) and of n_z paired across two rows, keep kx <= K
+//                 fields per complex DFT), u x omega at every point, forward
+//                 DFTs of (n_x + i n_y) (split into the two half spectra) and
+//                 of (n_z + 0i), keep kx <= K
 //   P4 y-forward  n values of y -> the 2K+1 retained ky
 //   P5 z-forward  n values of z -> the 2K+1 retained kz, then the projection,
 //                 the viscous term and the cast to FP64, fused
