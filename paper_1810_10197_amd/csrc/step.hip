@@ -248,80 +248,91 @@ size_t reduce_scratch_bytes(const Geom& g) {
   return (size_t)reduce_blocks(g) * g.batch * NRED * sizeof(double);
 }
 
-// Partial sums of one member (blockIdx.y) over a fixed set of elements.  N
-// and DIM are compile-time so that decoding an element index into (component,
-// kz', ky', kx) divides by constants; NT >= 0 is the number of error terms
-// (loads all in flight), NT < 0 takes it from the arguments.
+// Partial sums of one member (blockIdx.y) over a fixed set of modes.  N and
+// DIM are compile-time so that decoding a mode index into (kz', ky', kx)
+// divides by constants; NT >= 0 is the number of error terms (loads all in
+// flight), NT < 0 takes it from the arguments.  A thread takes every
+// component of its modes, so the mode's wavenumber, weight and shell are
+// worked out once for all of them.
 template <int N, int DIM, int NT>
 __global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, double* __restrict__ partials, int nblk,
                                                 int nvel, int epm) {
   constexpr int K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1;
   constexpr int MRC = DIM == 3 ? KX * KF * KF : KX * KF;
   const int m = blockIdx.y;
+  const int ncomp = epm / MRC;
   double acc[NRED];
 #pragma unroll
   for (int q = 0; q < NRED; ++q) acc[q] = 0.0;
   const long long base = (long long)m * epm;
   const double hm = a.h ? a.h[m] : 0.0;
   const int nt = NT >= 0 ? NT : a.delta.nterms;
-  for (int i = blockIdx.x * RBS + threadIdx.x; i < epm; i += nblk * RBS) {
-    const long long gi = base + i;
-    const int c = i / MRC;
-    int q = i - c * MRC;
+  for (int q = blockIdx.x * RBS + threadIdx.x; q < MRC; q += nblk * RBS) {
     const int kx = q % KX;
-    q /= KX;
-    const int kyp = q % KF;
+    int r = q / KX;
+    const int kyp = r % KF;
     const int ky = kyp <= K ? kyp : kyp - KF;
     int kz = 0;
     if (DIM == 3) {
-      const int kzp = q / KF;
+      const int kzp = r / KF;
       kz = kzp <= K ? kzp : kzp - KF;
     }
-    const double2 un = a.un[gi];
-    if (nt > 0) {
-      double dx = 0.0, dy = 0.0;
+    const double w = kx == 0 ? 1.0 : 2.0;
+    // every load of the mode first (all in flight together), then the sums
+    constexpr int NC = 3;                          // at most three components
+    constexpr int NTL = NT > 0 ? NT : 1;
+    double2 un[NC], uo[NC], f[NC], v[NC][NTL];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const long long gi = base + (long long)(c < ncomp ? c : 0) * MRC + q;
+      un[c] = a.un[gi];
+      if (nt > 0) uo[c] = a.uo[gi];
       if (NT > 0) {
-        double2 v[NT > 0 ? NT : 1];
 #pragma unroll
-        for (int j = 0; j < (NT > 0 ? NT : 0); ++j) v[j] = a.delta.src[j][gi];
-#pragma unroll
-        for (int j = 0; j < (NT > 0 ? NT : 0); ++j) {
-          dx += a.delta.coef[j] * v[j].x;
-          dy += a.delta.coef[j] * v[j].y;
-        }
-      } else {
-        for (int j = 0; j < nt; ++j) {
-          const double2 v = a.delta.src[j][gi];
-          dx += a.delta.coef[j] * v.x;
-          dy += a.delta.coef[j] * v.y;
-        }
+        for (int j = 0; j < NTL; ++j) v[c][j] = a.delta.src[j][gi];
       }
-      dx *= hm;
-      dy *= hm;
-      const double2 uo = a.uo[gi];
-      const double mo = sqrt(uo.x * uo.x + uo.y * uo.y), mn = sqrt(un.x * un.x + un.y * un.y);
-      const double sc = a.atol + a.rtol * (mo > mn ? mo : mn);
-      const double r = (dx * dx + dy * dy) / (sc * sc);
-      acc[0] += c == 0 ? r : 0.0;
-      acc[1] += c == 1 ? r : 0.0;
-      acc[2] += c == 2 ? r : 0.0;
+      if (a.fk && c < nvel) f[c] = a.fk[gi];
     }
-    if (c < nvel) {
-      const double w = kx == 0 ? 1.0 : 2.0;
-      const double e = 0.5 * w * (un.x * un.x + un.y * un.y);
-      acc[3] += e;
-      if (a.fk) {
-        const double2 f = a.fk[gi];
-        acc[4] -= w * (un.x * f.x + un.y * f.y);
-      }
-      const int k2i = kx * kx + ky * ky + kz * kz;
-      const double kmag = sqrt((double)k2i);
-      int bin = (int)floor((16.0 * kmag) / (double)(K > 0 ? K : 1));
-      bin = bin > NBINS - 1 ? NBINS - 1 : bin;
+    double e = 0.0;
 #pragma unroll
-      for (int b = 0; b < NBINS; ++b) acc[5 + b] += (b == bin) ? e : 0.0;
-      acc[21] += (k2i > 0 && (double)k2i <= a.kf2) ? e : 0.0;
+    for (int c = 0; c < NC; ++c) {
+      if (c >= ncomp) break;
+      if (nt > 0) {
+        double dx = 0.0, dy = 0.0;
+        if (NT > 0) {
+#pragma unroll
+          for (int j = 0; j < NTL; ++j) {
+            dx += a.delta.coef[j] * v[c][j].x;
+            dy += a.delta.coef[j] * v[c][j].y;
+          }
+        } else {
+          const long long gi = base + (long long)c * MRC + q;
+          for (int j = 0; j < nt; ++j) {
+            const double2 vv = a.delta.src[j][gi];
+            dx += a.delta.coef[j] * vv.x;
+            dy += a.delta.coef[j] * vv.y;
+          }
+        }
+        dx *= hm;
+        dy *= hm;
+        const double mo = sqrt(uo[c].x * uo[c].x + uo[c].y * uo[c].y);
+        const double mn = sqrt(un[c].x * un[c].x + un[c].y * un[c].y);
+        const double sc = a.atol + a.rtol * (mo > mn ? mo : mn);
+        acc[c] += (dx * dx + dy * dy) / (sc * sc);
+      }
+      if (c < nvel) {
+        e += 0.5 * w * (un[c].x * un[c].x + un[c].y * un[c].y);
+        if (a.fk) acc[4] -= w * (un[c].x * f[c].x + un[c].y * f[c].y);
+      }
     }
+    acc[3] += e;
+    const int k2i = kx * kx + ky * ky + kz * kz;
+    const double kmag = sqrt((double)k2i);
+    int bin = (int)floor((16.0 * kmag) / (double)(K > 0 ? K : 1));
+    bin = bin > NBINS - 1 ? NBINS - 1 : bin;
+#pragma unroll
+    for (int b = 0; b < NBINS; ++b) acc[5 + b] += (b == bin) ? e : 0.0;
+    acc[21] += (k2i > 0 && (double)k2i <= a.kf2) ? e : 0.0;
   }
   __shared__ double red[RBS / 64][NRED];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -346,11 +357,22 @@ __global__ __launch_bounds__(RBS) void k_reduce_final(const double* __restrict__
   __shared__ double red[RBS / 64][NRED];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double* p = partials + (long long)m * nblk * NRED;
+  // all NRED sums of a partial block at once (their loads in flight
+  // together); per sum the same order as one sum at a time
+  double s[NRED];
+#pragma unroll
+  for (int q = 0; q < NRED; ++q) s[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += RBS) {
+    double v[NRED];
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) v[q] = p[(long long)b * NRED + q];
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) s[q] += v[q];
+  }
+#pragma unroll
   for (int q = 0; q < NRED; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RBS) s += p[(long long)b * NRED + q];
-    s = wave_sum(s);
-    if (lane == 0) red[wv][q] = s;
+    const double t = wave_sum(s[q]);
+    if (lane == 0) red[wv][q] = t;
   }
   __syncthreads();
   if (threadIdx.x < NRED) {
