@@ -234,8 +234,8 @@ def study_mlp(args):
                 "n_reject": int(sum(x["n_reject"] for x in st)),
                 "wall_s": dt, "max_rel_l2_err": err}
             log("%s tol=%g: %s" % (ctl, tol, res["%s_tol%g" % (ctl, tol)]))
-    np.save(os.path.join(ROOT, "gpurun_out", "proposer_weights.npy"), w) \
-        if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    if args.weights:
+        np.save(args.weights, w)
     print(json.dumps({"study": "proposer_gain", "results": res}))
 
 
@@ -625,7 +625,8 @@ def main():
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--rk4-dts", type=float, nargs="*", default=[0.02, 0.01, 0.005, 0.0025])
     ap.add_argument("--tols", type=float, nargs="*", default=[1e-4, 1e-5, 1e-6, 1e-7, 1e-8])
-    ap.add_argument("--weights", default=None, help="proposer weights (.npy) for --study tts")
+    ap.add_argument("--weights", default=None,
+                    help="proposer weights (.npy): read (or written after training) by --study tts, written by --study mlp")
     ap.add_argument("--bs5-precs", nargs="*", default=["fp32", "fp64"])
     ap.add_argument("--e1-dts", type=float, nargs="*", default=[0.1, 0.05, 0.02, 0.01, 0.005, 0.0025])
     ap.add_argument("--e1-tols", type=float, nargs="*",

@@ -8,7 +8,8 @@ integration for Fourier pseudo-spectral DNS of incompressible turbulence"
 leg of the benchmark may import it; the product path never does, and it shares
 no code with the HIP library (no kernels, headers, tables or helpers).
 
-Conventions used throughout (the readings are listed in the design doc):
+Conventions used throughout (readings of the paper where it is silent or
+garbled):
 
 * grid x_j = 2*pi*j/N on [0, 2*pi)^d, physical arrays indexed [z][y][x]
   (3D) or [y][x] (2D), x contiguous;

@@ -13,7 +13,7 @@ state with h_new.  dmax is 1 for the first step after a rejection (read as:
 the h_new produced by the first accepted attempt after a rejection may not
 grow).  The initial h is supplied by the caller.
 
-Additions (readings listed in the design doc): err = 0 gives the factor dmax; a
+Additions (readings where the paper is silent): err = 0 gives the factor dmax; a
 non-finite err rejects with the factor dmin; 50 consecutive rejections stop
 the run; the final step is clipped to land on t_end.  An optional PI term
 err_prev^beta (beta = 0 reproduces the paper exactly) and an optional

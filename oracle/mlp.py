@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper closes (Sec. 4) by expecting better step-size controllers to help;
-the proposer is this build's learned controller.  A 20-64-64-1 tanh network
+the proposer is a learned controller of that kind.  A 20-64-64-1 tanh network
 maps features of the accepted state to y = log(h_next / h):
 
     x  = [log10(E_b / E + 1e-30), b = 0..15]      (shell spectrum, Sec. 3.3)

@@ -60,8 +60,9 @@ def spectral_shape(n, dim):
 
 
 # ---------------------------------------------------------------------------
-# Transforms.  The normalised convention u_hat = DFT(u)/N^d is the reading of
-# the paper's kinetic-energy formula (Sec. 3.1) chosen in the design doc.
+# Transforms.  The normalised convention u_hat = DFT(u)/N^d reads the paper's
+# kinetic-energy formula (Sec. 3.1), E = (1/2N^6)||u_hat||^2 for the
+# unnormalised transform, as E = 1/2 sum w |u_hat|^2 for this one.
 # ---------------------------------------------------------------------------
 
 def forward(u, dim):
@@ -173,7 +174,8 @@ def rhs_ns3d(uh, nu):
     4. N_hat = mask * DFT(n) / N^3;
     5. pressure: p_hat = (k . N_hat)/|k|^2, with p_hat(0) = 0 -- the Leray
        projection that eliminates P (the stray factor i in the printed
-       projection term is a typo, see DESIGN.md);
+       projection term is a typo: with it, f would not be real in physical
+       space);
     6. f = N_hat - k p_hat - nu |k|^2 u_hat, and f = 0 at k = 0.
     """
     n = uh.shape[1]
