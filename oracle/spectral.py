@@ -367,3 +367,44 @@ def divergence3(uh):
     n = uh.shape[1]
     kx, ky, kz = wavenumbers(n, 3)
     return kx * uh[0] + ky * uh[1] + kz * uh[2]
+
+
+# ---------------------------------------------------------------------------
+# Right-hand side of a state with few modes, by direct convolution (no grid).
+# ---------------------------------------------------------------------------
+
+def rhs_ns3d_modes(modes, nu, K):
+    """f of Eq. (2) for a real velocity with finitely many nonzero modes.
+
+    modes: {(kx, ky, kz): complex 3-vector u_hat(k)} containing every nonzero
+    mode together with its conjugate partner -k (a real field), all with
+    |k_j| <= K.  The nonlinear term is the exact product of the Fourier
+    series, (u x omega)^(k) = sum_{p+q=k} u_hat(p) x (i q x u_hat(q)), kept on
+    the retained cube |k_j| <= K (what the dealiased pseudo-spectral product
+    gives there, alias-free); then the projection and the viscous term, with
+    f(0) = 0.  Returns {k: f(k)} for every k with kx >= 0 where f can be
+    nonzero (all other retained entries are zero).
+    """
+    keys = list(modes)
+    prod = {}
+    for p in keys:
+        up = np.asarray(modes[p], dtype=np.complex128)
+        for q in keys:
+            k = (p[0] + q[0], p[1] + q[1], p[2] + q[2])
+            if k[0] < 0 or max(abs(k[0]), abs(k[1]), abs(k[2])) > K:
+                continue
+            uq = np.asarray(modes[q], dtype=np.complex128)
+            qv = np.array(q, dtype=float)
+            wq = 1j * np.cross(qv, uq)
+            prod[k] = prod.get(k, 0.0) + np.cross(up, wq)
+    out = {}
+    for k in set(prod) | {m for m in keys if m[0] >= 0}:
+        kv = np.array(k, dtype=float)
+        kk = float(kv @ kv)
+        if kk == 0.0:
+            out[k] = np.zeros(3, dtype=np.complex128)
+            continue
+        nl = prod.get(k, np.zeros(3, dtype=np.complex128))
+        u = np.asarray(modes.get(k, np.zeros(3)), dtype=np.complex128)
+        out[k] = nl - kv * (kv @ nl) / kk - nu * kk * u
+    return out
