@@ -144,3 +144,20 @@ def test_every_launch_variant_matches_oracle(ns, n):
     got = s.rhs(u[None]).cpu().numpy()[0]
     assert max(per_field_rel_l2(got, ref)) <= 5e-6
     s.close()
+
+
+@pytest.mark.parametrize("prec,rel", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_rhs_512_full_size_against_direct_modes(ns, prec, rel):
+    """512^3 (the forced-turbulence size) against the oracle element by
+    element: a velocity with few modes, some on the band's faces, whose f the
+    oracle forms by direct convolution; every entry of the output compared."""
+    from gpu_util import compare_with_modes, modes_to_half_spectrum, sparse_modes
+    n, nu = 512, 0.005
+    K = spectral.cutoff(n)
+    announce("rhs 512 %s vs direct modes" % prec)
+    modes = sparse_modes(K, 12, 512 + (prec == "fp32"))
+    expect = spectral.rhs_ns3d_modes(modes, nu, K)
+    s = solver(ns, n, prec, nu=nu)
+    got = s.rhs(modes_to_half_spectrum(modes, n)[None]).cpu().numpy()[0]
+    s.close()
+    compare_with_modes(got, expect, n, rel)

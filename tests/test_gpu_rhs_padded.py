@@ -166,3 +166,19 @@ def test_padded_inviscid_invariants_512(ns):
         div = np.abs(kx * f[0] + ky * f[1] + kz * f[2]).max()
         assert div < 1e-5 * np.abs(f).max() * n
     assert max(per_field_rel_l2(fs[1], fs[0])) < 5e-6      # the two plans agree
+
+
+@pytest.mark.parametrize("prec,rel", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_padded_rhs_512_against_direct_modes(ns, prec, rel):
+    """N = 512 under the 3/2 rule (products on 768^3) against the oracle's
+    direct convolution of a few-mode velocity, element by element."""
+    from gpu_util import compare_with_modes, modes_to_half_spectrum, sparse_modes
+    n, nu = 512, 0.005
+    K = spectral.cutoff_padded(n)
+    announce("padded rhs 512 %s vs direct modes" % prec)
+    modes = sparse_modes(K, 12, 768 + (prec == "fp32"))
+    expect = spectral.rhs_ns3d_modes(modes, nu, K)
+    s = solver(ns, n, prec, nu=nu)
+    got = s.rhs(modes_to_half_spectrum(modes, n)[None]).cpu().numpy()[0]
+    s.close()
+    compare_with_modes(got, expect, n, rel)
