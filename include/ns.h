@@ -76,6 +76,10 @@ extern "C" {
 #define NS_INTEGRATE_HOST 0x100 /* ns_integrate: launch each attempt's kernels
                                    individually instead of replaying a graph */
 #define NS_METHOD_DP5 0x200     /* ns_integrate: the DP5 pair instead of BS5 */
+#define NS_INTEGRATE_RESUME 0x400 /* ns_integrate: continue the controller (step,
+                                   rejection flag, error history) of the last
+                                   ns_integrate or ns_checkpoint_load; h0 is
+                                   used only when there is none */
 
 #define NS_MLP_NPARAM 5569      /* W1 64x20, b1 64, W2 64x64, b2 64, W3 1x64, b3 1 */
 #define NS_MLP_NWEIGHTS 5609    /* parameters + feature mean [20] + feature scale [20] */
@@ -165,6 +169,24 @@ int ns_step_dp5(ns_solver* s, double h, double atol, double rtol, int flags,
  * rejections of a member (that member keeps its last accepted state). */
 int ns_integrate(ns_solver* s, double t_end, double h0, double atol,
                  double rtol, int controller, ns_stats* stats_host);
+
+/* Checkpoint and resume (a long run restarted from a saved time, as the
+ * paper's forced-turbulence runs are).  The checkpoint is one host buffer of
+ * ns_checkpoint_bytes(s) bytes holding: a header with the configuration, the
+ * per-member viscosity and time, the controller's continuation state (next
+ * step, rejection flag, consecutive rejections, last three accepted errors),
+ * the retained-mode state u_n, the cached first stage f(u_n) when valid
+ * (with its FP32 copy, 3D FP32 right-hand side) and the proposer's weights.
+ * Not included: the proposer's training rows and optimiser moments, the
+ * autotuner's choice.  save: host buffer owned by the caller, written
+ * synchronously.  load: into a solver created with the same configuration
+ * (dim, n, batch, precision, scalar, dealias; else NS_ERR_ARG) -- a run
+ * continued with ns_integrate(..., controller | NS_INTEGRATE_RESUME, ...) is
+ * then bitwise equal to the same calls made without the checkpoint.
+ * ns_set_state and the single-step calls leave no controller to resume. */
+size_t ns_checkpoint_bytes(const ns_solver* s);
+int ns_checkpoint_save(ns_solver* s, void* host_buf, size_t bytes);
+int ns_checkpoint_load(ns_solver* s, const void* host_buf, size_t bytes);
 
 /* Time of each member (host array of batch values); set_time resets it. */
 int ns_get_time(ns_solver* s, double* t_host);

@@ -207,6 +207,7 @@ struct ns_solver {
   long long adam_t = 0;
   bool have_state = false;
   bool k1_valid = false;
+  bool ctl_warm = false;          // the device controller state can be continued
   std::vector<double> t;          // per-member time
   std::vector<int> maskbuf;
   std::vector<double> red_host;   // per-member reductions
@@ -604,6 +605,7 @@ int ns_set_state(ns_solver* s, const void* uhat) {
   NS_HIP(nsk::pack_state(s->g, (const double2*)uhat, s->u, s->st));
   s->have_state = true;
   s->k1_valid = false;
+  s->ctl_warm = false;
   return NS_OK;
 }
 
@@ -633,6 +635,7 @@ int ns_refresh_rhs(ns_solver* s) {
 int ns_step_rk4(ns_solver* s, double h) {
   if (!s || !std::isfinite(h) || h < 0.0) return NS_ERR_ARG;
   if (!s->have_state) return NS_ERR_STATE;
+  s->ctl_warm = false;
   int rc = ensure_k1(s);
   if (rc) return rc;
   NS_HIP(nsk::fill(s->h_d, h, s->g.batch, s->st));
@@ -671,6 +674,7 @@ static int step_embedded(ns_solver* s, const Pair& P, double h, double atol, dou
   if (!s || !std::isfinite(h) || h < 0.0 || !(atol >= 0.0) || !(rtol >= 0.0) || atol + rtol <= 0.0)
     return NS_ERR_ARG;
   if (!s->have_state) return NS_ERR_STATE;
+  s->ctl_warm = false;
   int rc = ensure_k1(s);
   if (rc) return rc;
   NS_HIP(nsk::fill(s->h_d, h, s->g.batch, s->st));
@@ -714,17 +718,25 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
   if (!s->have_state) return NS_ERR_STATE;
   const int B = s->g.batch;
   const int use_mlp = ctrl == NS_CTRL_MLP;
-  // reset the controller: time from the host, h0, no history
+  const bool resume = (controller & NS_INTEGRATE_RESUME) && s->ctl_warm;
+  s->ctl_warm = false;                         // until this call completes
+  // reset the controller: time from the host, h0, no history -- or, when
+  // resuming, keep its step, rejection flag, consecutive rejections and
+  // error history
   {
     std::vector<double> hv(B, h0), ones(3 * (size_t)B, 1.0), zd(B, 0.0);
     std::vector<int> zi(B, 0);
     std::vector<long long> zl(B, 0);
     const nsk::CtlState& c = s->ctl;
     NS_HIP(hipMemcpyAsync(c.t, s->t.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
-    NS_HIP(hipMemcpyAsync(c.h, hv.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
-    NS_HIP(hipMemcpyAsync(c.err, zd.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
-    NS_HIP(hipMemcpyAsync(c.errhist, ones.data(), 24 * (size_t)B, hipMemcpyHostToDevice, s->st));
-    int* ints[] = {c.prev_rej, c.consec, c.clipped, c.accept, c.fail};
+    if (!resume) {
+      NS_HIP(hipMemcpyAsync(c.h, hv.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
+      NS_HIP(hipMemcpyAsync(c.err, zd.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
+      NS_HIP(hipMemcpyAsync(c.errhist, ones.data(), 24 * (size_t)B, hipMemcpyHostToDevice, s->st));
+      NS_HIP(hipMemcpyAsync(c.prev_rej, zi.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s->st));
+      NS_HIP(hipMemcpyAsync(c.consec, zi.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s->st));
+    }
+    int* ints[] = {c.clipped, c.accept, c.fail};
     for (int* p : ints) NS_HIP(hipMemcpyAsync(p, zi.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s->st));
     long long* lls[] = {c.nacc, c.nrej, c.nrhs};
     for (long long* p : lls) NS_HIP(hipMemcpyAsync(p, zl.data(), 8 * (size_t)B, hipMemcpyHostToDevice, s->st));
@@ -820,6 +832,7 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
   if (done_pinned) (void)hipHostFree(done_pinned);
   if (status) return status;
   s->k1_valid = true;
+  s->ctl_warm = true;
   // results back to the host
   std::vector<double> tt(B), hh(B), ee(B);
   std::vector<long long> na(B), nr(B), nh(B);
@@ -844,6 +857,115 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
     }
   }
   return status;
+}
+
+// ---------------------------------------------------------------- checkpoint
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int dim, n, batch, rhs_precision, scalar, dealias;
+  long long epm;
+  int k1_valid, has_k32, ctl_warm, mlp_loaded;
+};
+const char CKPT_MAGIC[8] = {'N', 'S', 'C', 'K', 'P', 'T', '1', 0};
+
+// Byte offsets of the parts of a checkpoint (every part present).
+struct CkptLayout {
+  size_t nu, t, h, errhist, prev_rej, consec, u, k0, k32, mw, total;
+};
+CkptLayout ckpt_layout(const ns_solver* s) {
+  const size_t B = (size_t)s->g.batch, E = (size_t)s->g.epm * B;
+  CkptLayout L;
+  size_t off = sizeof(CkptHeader);
+  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 15) / 16 * 16; return o; };
+  L.nu = take(8 * B);
+  L.t = take(8 * B);
+  L.h = take(8 * B);
+  L.errhist = take(24 * B);
+  L.prev_rej = take(4 * B);
+  L.consec = take(4 * B);
+  L.u = take(16 * E);
+  L.k0 = take(16 * E);
+  L.k32 = take(s->k32[0] ? 8 * E : 0);
+  L.mw = take(4 * (size_t)nsk::MLP_NWEIGHTS);
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+size_t ns_checkpoint_bytes(const ns_solver* s) { return s ? ckpt_layout(s).total : 0; }
+
+int ns_checkpoint_save(ns_solver* s, void* host_buf, size_t bytes) {
+  if (!s || !host_buf) return NS_ERR_ARG;
+  if (!s->have_state) return NS_ERR_STATE;
+  const CkptLayout L = ckpt_layout(s);
+  if (bytes < L.total) return NS_ERR_NOMEM;
+  const size_t B = (size_t)s->g.batch, E = (size_t)s->g.epm * B;
+  char* p = (char*)host_buf;
+  CkptHeader hd;
+  std::memcpy(hd.magic, CKPT_MAGIC, 8);
+  hd.dim = s->cfg.dim;
+  hd.n = s->cfg.n;
+  hd.batch = s->cfg.batch;
+  hd.rhs_precision = s->cfg.rhs_precision;
+  hd.scalar = s->cfg.scalar;
+  hd.dealias = s->cfg.dealias;
+  hd.epm = s->g.epm;
+  hd.k1_valid = s->k1_valid ? 1 : 0;
+  hd.has_k32 = s->k32[0] ? 1 : 0;
+  hd.ctl_warm = s->ctl_warm ? 1 : 0;
+  hd.mlp_loaded = s->mlp_loaded ? 1 : 0;
+  std::memcpy(p, &hd, sizeof(hd));
+  NS_HIP(hipStreamSynchronize(s->st));
+  std::memcpy(p + L.t, s->t.data(), 8 * B);
+  NS_HIP(hipMemcpy(p + L.nu, s->nu_d, 8 * B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(p + L.h, s->ctl.h, 8 * B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(p + L.errhist, s->ctl.errhist, 24 * B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(p + L.prev_rej, s->ctl.prev_rej, 4 * B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(p + L.consec, s->ctl.consec, 4 * B, hipMemcpyDeviceToHost));
+  NS_HIP(hipMemcpy(p + L.u, s->u, 16 * E, hipMemcpyDeviceToHost));
+  if (s->k1_valid) {
+    NS_HIP(hipMemcpy(p + L.k0, s->k[0], 16 * E, hipMemcpyDeviceToHost));
+    if (s->k32[0]) NS_HIP(hipMemcpy(p + L.k32, s->k32[0], 8 * E, hipMemcpyDeviceToHost));
+  }
+  if (s->mlp_loaded) NS_HIP(hipMemcpy(p + L.mw, s->mw, 4 * (size_t)nsk::MLP_NWEIGHTS, hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+int ns_checkpoint_load(ns_solver* s, const void* host_buf, size_t bytes) {
+  if (!s || !host_buf || bytes < sizeof(CkptHeader)) return NS_ERR_ARG;
+  const CkptLayout L = ckpt_layout(s);
+  if (bytes < L.total) return NS_ERR_ARG;
+  const char* p = (const char*)host_buf;
+  CkptHeader hd;
+  std::memcpy(&hd, p, sizeof(hd));
+  if (std::memcmp(hd.magic, CKPT_MAGIC, 8) != 0 || hd.dim != s->cfg.dim || hd.n != s->cfg.n ||
+      hd.batch != s->cfg.batch || hd.rhs_precision != s->cfg.rhs_precision || hd.scalar != s->cfg.scalar ||
+      hd.dealias != s->cfg.dealias || hd.epm != s->g.epm || hd.has_k32 != (s->k32[0] ? 1 : 0))
+    return NS_ERR_ARG;
+  const size_t B = (size_t)s->g.batch, E = (size_t)s->g.epm * B;
+  NS_HIP(hipStreamSynchronize(s->st));
+  std::memcpy(s->t.data(), p + L.t, 8 * B);
+  NS_HIP(hipMemcpy(s->nu_d, p + L.nu, 8 * B, hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(s->ctl.h, p + L.h, 8 * B, hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(s->ctl.errhist, p + L.errhist, 24 * B, hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(s->ctl.prev_rej, p + L.prev_rej, 4 * B, hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(s->ctl.consec, p + L.consec, 4 * B, hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(s->u, p + L.u, 16 * E, hipMemcpyHostToDevice));
+  if (hd.k1_valid) {
+    NS_HIP(hipMemcpy(s->k[0], p + L.k0, 16 * E, hipMemcpyHostToDevice));
+    if (s->k32[0]) NS_HIP(hipMemcpy(s->k32[0], p + L.k32, 8 * E, hipMemcpyHostToDevice));
+  }
+  if (hd.mlp_loaded) NS_HIP(hipMemcpy(s->mw, p + L.mw, 4 * (size_t)nsk::MLP_NWEIGHTS, hipMemcpyHostToDevice));
+  s->have_state = true;
+  s->k1_valid = hd.k1_valid != 0;
+  s->ctl_warm = hd.ctl_warm != 0;
+  if (hd.mlp_loaded) s->mlp_loaded = true;
+  if (s->gexec) {                              // captured with the solver's earlier buffers' roles
+    (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+  }
+  return NS_OK;
 }
 
 int ns_get_time(ns_solver* s, double* t_host) {

@@ -33,6 +33,7 @@ NS_CTRL_MLP = 1
 NS_FORCE_COMMIT = 1
 NS_INTEGRATE_HOST = 0x100
 NS_METHOD_DP5 = 0x200
+NS_INTEGRATE_RESUME = 0x400
 NS_MLP_NPARAM = 5569
 NS_MLP_NWEIGHTS = 5609
 
@@ -41,7 +42,7 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_set_time", "ns_diagnostics", "ns_refresh_rhs", "ns_mlp_set_weights",
            "ns_mlp_get_weights", "ns_mlp_forward", "ns_mlp_grad", "ns_mlp_train_batch",
            "ns_mlp_reset_optimizer", "ns_mlp_collect", "ns_mlp_rows", "ns_mlp_push_rows",
-           "ns_mlp_fit_stats",
+           "ns_mlp_fit_stats", "ns_checkpoint_bytes", "ns_checkpoint_save", "ns_checkpoint_load",
            "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
            "ns_profile_stop", "ns_strerror", "ns_free"]
 NS_NTUNE = 6
@@ -115,6 +116,9 @@ _sig = {
     "ns_profile_start": (_I, [_P]),
     "ns_profile_stop": (_I, [_P, ctypes.POINTER(NsKernelTimes)]),
     "ns_strerror": (ctypes.c_char_p, [_I]),
+    "ns_checkpoint_bytes": (ctypes.c_size_t, [_P]),
+    "ns_checkpoint_save": (_I, [_P, _P, ctypes.c_size_t]),
+    "ns_checkpoint_load": (_I, [_P, _P, ctypes.c_size_t]),
     "ns_free": (None, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -368,17 +372,32 @@ class Solver:
         st = ns_step_dp5(self.handle, h, atol, rtol, NS_FORCE_COMMIT if force else 0, errs)
         return st, errs
 
-    def integrate(self, t_end, h0, atol, rtol, controller="pi", graph=True, method="bs5"):
+    def integrate(self, t_end, h0, atol, rtol, controller="pi", graph=True, method="bs5",
+                  resume=False):
         stats = (NsStats * self.batch)()
         ctl = {"pi": NS_CTRL_PI, "mlp": NS_CTRL_MLP}[controller]
         if not graph:
             ctl |= NS_INTEGRATE_HOST
+        if resume:
+            ctl |= NS_INTEGRATE_RESUME
         if method == "dp5":
             ctl |= NS_METHOD_DP5
         elif method != "bs5":
             raise ValueError("method must be 'bs5' or 'dp5'")
         ns_integrate(self.handle, t_end, h0, atol, rtol, ctl, stats)
         return [s.as_dict() for s in stats]
+
+    # ---- checkpoint / resume
+    def checkpoint(self):
+        """The solver's checkpoint as a numpy uint8 array (host memory)."""
+        nbytes = _lib.ns_checkpoint_bytes(self.handle)
+        buf = np.zeros(nbytes, dtype=np.uint8)
+        _check(_lib.ns_checkpoint_save(self.handle, buf.ctypes.data_as(_P), nbytes), "ns_checkpoint_save")
+        return buf
+
+    def restore(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(_lib.ns_checkpoint_load(self.handle, buf.ctypes.data_as(_P), buf.size), "ns_checkpoint_load")
 
     # ---- step-size proposer
     def mlp_set_weights(self, w):

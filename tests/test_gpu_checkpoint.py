@@ -1,0 +1,73 @@
+"""Checkpoint and resume: a run continued from a checkpoint in a fresh solver
+is bitwise equal to the same calls made in one solver (state, times, step
+counts), for the Sec. 2.2.1 controller and for the proposer."""
+import numpy as np
+import pytest
+
+from gpu_util import announce
+from paper_1810_10197_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ns():
+    from paper_1810_10197_amd import ns as mod
+    return mod
+
+
+def _weights(ns, seed):
+    rng = np.random.default_rng(seed)
+    w = np.zeros(ns.NS_MLP_NWEIGHTS, dtype=np.float32)
+    w[:ns.NS_MLP_NPARAM] = rng.uniform(-0.05, 0.05, ns.NS_MLP_NPARAM)
+    w[ns.NS_MLP_NPARAM + 20:] = 1.0                     # feature scale
+    return w
+
+
+@pytest.mark.parametrize("controller,prec", [("pi", "fp32"), ("mlp", "fp32"), ("pi", "fp64")])
+def test_resume_from_checkpoint_is_bitwise_equal(ns, controller, prec):
+    n, tol = 32, 1e-9
+    announce("checkpoint/resume %s %s" % (controller, prec))
+    fields, nus = inputs.ensemble_members(2, n)
+
+    def fresh():
+        s = ns.Solver(dim=3, n=n, batch=2, nu=nus, rhs_precision=prec)
+        return s
+
+    # the reference: both halves in one solver
+    a = fresh()
+    a.mlp_set_weights(_weights(ns, 5))
+    a.set_state(fields)
+    a.integrate(0.25, 0.05, tol, tol, controller=controller)
+    ref_stats = a.integrate(0.5, 0.05, tol, tol, controller=controller, resume=True)
+    ref = a.get_state().cpu().numpy()
+    a.close()
+    # the first half, a checkpoint, the second half in a new solver
+    b = fresh()
+    b.mlp_set_weights(_weights(ns, 5))
+    b.set_state(fields)
+    b.integrate(0.25, 0.05, tol, tol, controller=controller)
+    buf = b.checkpoint()
+    b.close()
+    c = fresh()                                         # no weights, no state
+    c.restore(buf)
+    stats = c.integrate(0.5, 123.0, tol, tol, controller=controller, resume=True)   # h0 unused
+    got = c.get_state().cpu().numpy()
+    c.close()
+    for m in range(2):
+        assert (stats[m]["t"], stats[m]["n_rhs"], stats[m]["n_accept"], stats[m]["n_reject"]) == \
+            (ref_stats[m]["t"], ref_stats[m]["n_rhs"], ref_stats[m]["n_accept"], ref_stats[m]["n_reject"])
+    assert np.array_equal(got.view(np.float64), ref.view(np.float64))
+
+
+def test_checkpoint_of_another_configuration_is_refused(ns):
+    announce("checkpoint config mismatch")
+    fields, nus = inputs.ensemble_members(2, 16)
+    s = ns.Solver(dim=3, n=16, batch=2, nu=nus, rhs_precision="fp32")
+    s.set_state(fields)
+    buf = s.checkpoint()
+    s.close()
+    t = ns.Solver(dim=3, n=16, batch=1, nu=nus[0], rhs_precision="fp32")
+    with pytest.raises(ns.NsError):
+        t.restore(buf)
+    t.close()
