@@ -1155,11 +1155,13 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
   const bool was_on = s->prof_on;
   int rc = NS_OK;
   // 3D: the slab first (it changes what the passes read from), then every
-  // pass; 2D: the two column passes (Q1 in slot 0, Q3 in slot 4)
+  // pass; 2D: the layout between the x-pass and Q3 (slot 2, timed over the
+  // whole right-hand side), then the two column passes (Q1 in slot 0, Q3 in
+  // slot 4)
   const bool d3 = s->g.dim == 3;
   const int order3[NS_NTUNE] = {5, 0, 1, 2, 3, 4};
-  const int order2[2] = {0, 4};
-  const int nq = d3 ? NS_NTUNE : (s->g.n >= 256 ? 2 : 0);
+  const int order2[3] = {2, 0, 4};
+  const int nq = d3 ? NS_NTUNE : (s->g.n >= 256 ? 3 : 0);
   for (int q = 0; q < nq && !rc; ++q) {
     const int p = d3 ? order3[q] : order2[q];
     const int nv = tune_nvariants(p);
@@ -1182,6 +1184,9 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
       double ms = 1e300;
       if (d3 && (p == 1 || p == 2 || p == 3 || p == 5)) {
         if (kt.count[nsk::PROF_SLAB]) ms = kt.ms[nsk::PROF_SLAB] / (double)kt.count[nsk::PROF_SLAB];
+      } else if (!d3 && p == 2) {
+        if (kt.count[nsk::PROF_P1])
+          ms = (kt.ms[nsk::PROF_P1] + kt.ms[nsk::PROF_P3] + kt.ms[nsk::PROF_P5]) / (double)kt.count[nsk::PROF_P1];
       } else if (kt.count[p]) {
         ms = kt.ms[p] / (double)kt.count[p];
       }

@@ -13,7 +13,7 @@
 //   Q2 x-pass     per (member, y) row: C2R transforms of (u + iv), omega and
 //                 rho, the products at every point, R2C of
 //                 (v omega - i u omega) and (rho u + i rho v), keep kx <= K
-//                                                                 B2 [m][4][y][kx]
+//                                      B2 [m][4][y][kx], or (COLB2) [m][4][kx][y]
 //   Q3 y-forward  n values of y -> 2K+1 retained ky, then projection,
 //                 buoyancy, diffusion and the cast to FP64, fused.
 //
@@ -103,7 +103,9 @@ __device__ __forceinline__ void split_pair(const V (&z)[PL::E], int i, int t, in
   bh = mk<V>(half * (zk.y + pv.y), half * (pv.x - zk.x));
 }
 
-template <class PL, typename T, bool SCALAR>
+// COLB2: write B2 column-major, [m][4][kx][y], so that Q3's columns are
+// contiguous (each block's rows then fill RPB consecutive entries per kx).
+template <class PL, typename T, bool SCALAR, bool COLB2>
 __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k2_xpass(const cplx<T>* __restrict__ B1,
                                                                cplx<T>* __restrict__ B2, Geom g,
                                                                long long nrows,
@@ -180,7 +182,10 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k2_xpass(const cplx<T>* _
     fft_regs<PL, -1, V, true, true>(qq, t, buf, tw);
   }
   const int partner = (TT - t) & (TT - 1);
-  V* out = B2 + (m * 4 * N + y) * Kx;
+  // element (field f, kx) of this row: row-major f * fs + kx, column-major
+  // f * fs + kx * N (fs = N * Kx either way)
+  V* out = COLB2 ? B2 + m * 4 * fs + y : B2 + (m * 4 * N + y) * Kx;
+  const long long ks = COLB2 ? N : 1;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     V nx, ny, qx, qy;
@@ -188,11 +193,11 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k2_xpass(const cplx<T>* _
     if constexpr (SCALAR) split_pair<PL, V, T>(qq, i, t, partner, qx, qy);
     const int pos = out_pos<PL>(t, i);
     if (valid && pos <= K) {
-      out[pos] = nx;
-      out[fs + pos] = ny;
+      out[pos * ks] = nx;
+      out[fs + pos * ks] = ny;
       if constexpr (SCALAR) {
-        out[2 * fs + pos] = qx;
-        out[3 * fs + pos] = qy;
+        out[2 * fs + pos * ks] = qx;
+        out[3 * fs + pos * ks] = qy;
       }
     }
   }
@@ -214,7 +219,7 @@ template <class PL, typename T, int NF, int CMAX = 8> struct Q3Cfg {
   static constexpr int NT = C * TT * NF;
 };
 
-template <class PL, typename T, bool SCALAR, int CMAX>
+template <class PL, typename T, bool SCALAR, int CMAX, bool COLB2>
 __global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_yfwd(const cplx<T>* __restrict__ B2,
                                                                           const double2* __restrict__ U,
                                                                           double2* __restrict__ Kout, Geom g,
@@ -229,30 +234,37 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_y
   __shared__ V lds[NF * C * LD];
   const int f = threadIdx.x / (C * TT);
   const int rem = threadIdx.x - f * (C * TT);
-  const int lc = rem % C, t = rem / C;
-  const int kx = blockIdx.x * C + lc;
+  // transform phase: lanes along the column when it is contiguous (COLB2),
+  // else across the tile's columns
+  const int lc = COLB2 ? rem / TT : rem % C, t = COLB2 ? rem % TT : rem / C;
   const int m = blockIdx.y;
-  const bool valid = kx < g.Kx;
-  V* buf = lds + (f * C + lc) * LD;
-  V o[E];
   {
-    const V* in = B2 + ((long long)(m * 4 + f) * N) * g.Kx + (valid ? kx : 0);
+    const int kxt = blockIdx.x * C + lc;
+    const bool vt = kxt < g.Kx;
+    V* buf = lds + (f * C + lc) * LD;
+    V o[E];
+    const V* in = COLB2 ? B2 + ((long long)(m * 4 + f) * g.Kx + (vt ? kxt : 0)) * N
+                        : B2 + ((long long)(m * 4 + f) * N) * g.Kx + (vt ? kxt : 0);
+    const long long ys = COLB2 ? 1 : g.Kx;
 #pragma unroll
-    for (int i = 0; i < E; ++i) o[i] = in[(long long)in_pos<PL>(t, i) * g.Kx];
+    for (int i = 0; i < E; ++i) o[i] = in[(long long)in_pos<PL>(t, i) * ys];
+    fft_regs<PL, -1>(o, t, buf, tw);
+    __syncthreads();                             // every group done with its exchanges
+#pragma unroll
+    for (int i = 0; i < E; ++i) buf[out_pos<PL>(t, i)] = o[i];
+    __syncthreads();
   }
-  fft_regs<PL, -1>(o, t, buf, tw);
-  __syncthreads();                               // every group done with its exchanges
-#pragma unroll
-  for (int i = 0; i < E; ++i) buf[out_pos<PL>(t, i)] = o[i];
-  __syncthreads();
-  if (!valid) return;
+  // epilogue: lanes across the tile's columns (adjacent kx of the state)
+  const int elc = rem % C, et = rem / C;
+  const int kx = blockIdx.x * C + elc;
+  if (kx >= g.Kx) return;
   const double scale = 1.0 / ((double)N * (double)N);
   const double num = nu[m];
   const long long cs = g.mr;
-  const V* col0 = lds + lc * LD;                 // field c of this column: col0 + c * C * LD
+  const V* col0 = lds + elc * LD;                // field c of this column: col0 + c * C * LD
 #pragma unroll
   for (int i = f; i < E; i += NF) {
-    const int e = out_pos<PL>(t, i);
+    const int e = out_pos<PL>(et, i);
     if (!((e <= g.K) || (e >= N - g.K))) continue;
     const int ky = e <= g.K ? e : e - N;
     const long long idx = (long long)m * g.ncomp * cs + (long long)(ky >= 0 ? ky : ky + g.Kf) * g.Kx + kx;
@@ -292,8 +304,9 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_y
 // Launch variants (the autotuner's choice; grids below 256 points use 0):
 // Q1 (tuning slot 0) 0 default tile, 1 four columns, 2 two columns, 3 narrow
 // plan default tile, 4 narrow plan two columns; Q3 (slot 4) 0 up to eight
-// columns, 1 two, 2 one, 3 narrow plan up to eight, 4 narrow plan one.  The
-// x-pass keeps the wide plan (a row stays inside one wavefront).
+// columns, 1 two, 2 one, 3 narrow plan up to eight, 4 narrow plan one; the
+// layout of B2 (slot 2) 0 row-major, 1 column-major.  The x-pass keeps the
+// wide plan (a row stays inside one wavefront).
 template <int N, int V> struct Q1Var {
   using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
   static constexpr int CW = N < 256 ? 0 : (V == 1 ? 4 : (V == 2 || V == 4 ? 2 : 0));
@@ -313,13 +326,25 @@ static void launch_q1(const Geom& g, const double2* U, cplx<T>* B1, int nfield, 
   hipLaunchKernelGGL((k2_yinv<typename QV::PL, T, QV::CW>), dim3((unsigned)nb1p), dim3(CF::NT), 0, st, U, B1, g,
                      nfield, nb1, tw);
 }
-template <int N, typename T, bool SCALAR, int VAR>
+template <int N, typename T, bool SCALAR, int VAR, bool COLB2>
 static void launch_q3(const Geom& g, const cplx<T>* B2, const double2* U, double2* K, const RhsParams& p,
                       const cplx<T>* tw, hipStream_t st) {
   using QV = Q3Var<N, VAR>;
   using QC = Q3Cfg<typename QV::PL, T, SCALAR ? 4 : 2, QV::CMAX>;
-  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX>), dim3((g.Kx + QC::C - 1) / QC::C, g.batch),
-                     dim3(QC::NT), 0, st, B2, U, K, g, p.nu, p.ri, p.kappa, tw);
+  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX, COLB2>),
+                     dim3((g.Kx + QC::C - 1) / QC::C, g.batch), dim3(QC::NT), 0, st, B2, U, K, g, p.nu, p.ri,
+                     p.kappa, tw);
+}
+template <int N, typename T, bool SCALAR, bool COLB2>
+static void launch_q3v(int v3, const Geom& g, const cplx<T>* B2, const double2* U, double2* K,
+                       const RhsParams& p, const cplx<T>* tw, hipStream_t st) {
+  switch (v3) {
+    case 1: launch_q3<N, T, SCALAR, N >= 256 ? 1 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
+    case 2: launch_q3<N, T, SCALAR, N >= 256 ? 2 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
+    case 3: launch_q3<N, T, SCALAR, N >= 256 ? 3 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
+    case 4: launch_q3<N, T, SCALAR, N >= 256 ? 4 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
+    default: launch_q3<N, T, SCALAR, 0, COLB2>(g, B2, U, K, p, tw, st);
+  }
 }
 
 template <int N, typename T, bool SCALAR>
@@ -334,6 +359,7 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   const int nfield = SCALAR ? 4 : 3;
   // variants only matter (and are only built) from 256 points on
   const int v1 = N >= 256 ? bufs.variant[0] : 0, v3 = N >= 256 ? bufs.variant[4] : 0;
+  const bool colb2 = N >= 256 && bufs.variant[2] == 1;
 #define NSK_MARK(id, ph) \
   if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, st)
   NSK_MARK(PROF_P1, 0);
@@ -347,17 +373,16 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   NSK_MARK(PROF_P1, 1);
   const long long rows = (long long)g.batch * N;
   NSK_MARK(PROF_P3, 0);
-  hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
-                     dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
+  if (colb2)
+    hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR, N >= 256>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
+                       dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
+  else
+    hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR, false>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
+                       dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
   NSK_MARK(PROF_P3, 1);
   NSK_MARK(PROF_P5, 0);
-  switch (v3) {
-    case 1: launch_q3<N, T, SCALAR, N >= 256 ? 1 : 0>(g, B2, U, K, p, tw, st); break;
-    case 2: launch_q3<N, T, SCALAR, N >= 256 ? 2 : 0>(g, B2, U, K, p, tw, st); break;
-    case 3: launch_q3<N, T, SCALAR, N >= 256 ? 3 : 0>(g, B2, U, K, p, tw, st); break;
-    case 4: launch_q3<N, T, SCALAR, N >= 256 ? 4 : 0>(g, B2, U, K, p, tw, st); break;
-    default: launch_q3<N, T, SCALAR, 0>(g, B2, U, K, p, tw, st);
-  }
+  if (colb2) launch_q3v<N, T, SCALAR, N >= 256>(v3, g, B2, U, K, p, tw, st);
+  else launch_q3v<N, T, SCALAR, false>(v3, g, B2, U, K, p, tw, st);
   NSK_MARK(PROF_P5, 1);
 #undef NSK_MARK
   return hipGetLastError();

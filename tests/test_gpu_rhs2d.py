@@ -120,14 +120,15 @@ def test_rhs2d_every_launch_variant(ns, n, scalar):
     ref = spectral.rhs_ns2d(u, nu, kappa, ri) if scalar else spectral.rhs_ns2d(u, nu)
     s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision="fp32", scalar=scalar, ri=ri if scalar else 0.0,
                   kappa=kappa if scalar else 0.0)
-    for v in range(5):
-        s.tune([v, 0, 0, 0, 4 - v, 0])
+    for v in range(10):
+        s.tune([v % 5, 0, v // 5, 0, 4 - v % 5, 0])
         got = s.rhs(u[None]).cpu().numpy()[0]
         err = max(per_field_rel_l2(got, ref))
         assert err <= 3e-6, (v, err)
     s.set_state(u[None])
     variants, ms = s.autotune(reps=2)
     assert ms[0][variants[0]] == min(x for x in ms[0][:5] if x > 0)
+    assert ms[2][variants[2]] == min(x for x in ms[2][:2] if x > 0)
     assert ms[4][variants[4]] == min(x for x in ms[4][:5] if x > 0)
     got = s.rhs(u[None]).cpu().numpy()[0]
     assert max(per_field_rel_l2(got, ref)) <= 3e-6

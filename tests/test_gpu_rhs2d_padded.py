@@ -64,8 +64,8 @@ def test_padded_rhs2d_every_launch_variant(ns, n):
     st = band_field(n, 11 * n, 3)
     ref = spectral.rhs_ns2d_padded(st, nu, kappa, ri)
     s = solver(ns, n, "fp32", 1, nu, kappa, ri)
-    for v in range(5):
-        s.tune([v, 0, 0, 0, 4 - v, 0])
+    for v in range(10):
+        s.tune([v % 5, 0, v // 5, 0, 4 - v % 5, 0])
         got = s.rhs(st[None]).cpu().numpy()[0]
         err = max(per_field_rel_l2(got, ref))
         assert err <= 3e-6, (v, err)
