@@ -146,7 +146,7 @@ def collect_rows(ns, fields, nus, n, t_end, tols, h0=1e-3, chunks=1):
         torch.cuda.synchronize()
         h = h0
         for c in range(chunks):
-            st = s.integrate(t_end * (c + 1) / chunks, h, tol, tol)
+            st = s.integrate(t_end * (c + 1) / chunks, h, tol, tol, resume=c > 0)
             h = float(np.min([x["h_next"] for x in st]))
             nrhs += sum(x["n_rhs"] for x in st)
         log("collect n=%d B=%d tol=%g: %d rows" % (n, B, tol, s.mlp_rows(0)[2]))
@@ -445,7 +445,7 @@ def study_problem(args):
         h, tot = h0, {"n_rhs": 0, "n_accept": 0, "n_reject": 0}
         nch = int(math.ceil(4 * T - 1e-9))
         for c in range(nch):
-            st = s.integrate(min(T, 0.25 * (c + 1)), h, tol, tol, controller=ctl)[0]
+            st = s.integrate(min(T, 0.25 * (c + 1)), h, tol, tol, controller=ctl, resume=c > 0)[0]
             h = st["h_next"]
             for k in tot:
                 tot[k] += st[k]
@@ -486,7 +486,7 @@ def study_problem(args):
             s.set_time(np.zeros(1))
             h = h0
             for c in range(int(math.ceil(train_T - 1e-12))):
-                st = s.integrate(min(train_T, c + 1.0), h, tol, tol)[0]
+                st = s.integrate(min(train_T, c + 1.0), h, tol, tol, resume=c > 0)[0]
                 h = st["h_next"]
         x2, y2, _ = s.mlp_rows()
         s.close()
@@ -575,12 +575,12 @@ def study_tts(args):
             s.set_state(u0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            # unit-time chunks, each continuing with the step the controller
-            # proposed at the end of the previous one (progress lines between)
+            # unit-time chunks, each continuing the controller of the previous
+            # one (progress lines between)
             h, tot = 1e-3, {"n_rhs": 0, "n_accept": 0, "n_reject": 0}
             nchunk = int(math.ceil(T - 1e-12))
             for c in range(nchunk):
-                st = s.integrate(min(T, c + 1.0), h, tol, tol, controller=ctl)[0]
+                st = s.integrate(min(T, c + 1.0), h, tol, tol, controller=ctl, resume=c > 0)[0]
                 h = st["h_next"]
                 for k in tot:
                     tot[k] += st[k]
