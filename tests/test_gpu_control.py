@@ -19,18 +19,20 @@ def ns():
     return mod
 
 
-def test_graph_and_host_paths_agree(ns):
+@pytest.mark.parametrize("prec,method", [("fp64", "bs5"), ("fp32", "bs5"), ("fp32", "dp5")])
+def test_graph_and_host_paths_agree(ns, prec, method):
     n, nu = 16, 0.01
-    announce("integrate graph vs host n=%d" % n)
+    announce("integrate graph vs host n=%d %s %s" % (n, prec, method))
     u0 = inputs.random_isotropic(n, 31)
     out = []
     for graph in (True, False):
-        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp64")
+        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision=prec)
         s.set_state(u0[None])
-        st = s.integrate(0.5, 0.2, 1e-9, 1e-9, graph=graph)[0]
+        st = s.integrate(0.5, 0.2, 1e-9, 1e-9, graph=graph, method=method)[0]
         out.append((st, s.get_state().cpu().numpy()[0]))
         s.close()
     (s1, u1), (s2, u2) = out
+    assert s1["n_reject"] >= 1                 # h0 = 0.2 is too long: rejections happen
     assert (s1["n_accept"], s1["n_reject"], s1["n_rhs"]) == (s2["n_accept"], s2["n_reject"], s2["n_rhs"])
     assert np.array_equal(u1.view(np.float64), u2.view(np.float64))
 
