@@ -182,3 +182,25 @@ def test_padded_rhs_512_against_direct_modes(ns, prec, rel):
     got = s.rhs(modes_to_half_spectrum(modes, n)[None]).cpu().numpy()[0]
     s.close()
     compare_with_modes(got, expect, n, rel)
+
+
+def test_padded_ensemble_members_equal_single_runs(ns):
+    """3/2 rule with a batch: each member of an adaptive ensemble run (own nu,
+    own steps) is bitwise equal to the same run alone."""
+    n, B = 32, 3
+    announce("padded ensemble == single n=%d B=%d" % (n, B))
+    fields = np.stack([field(n, 40 + m) for m in range(B)])
+    nus = [0.01, 0.02, 0.005]
+    sb = solver(ns, n, "fp32", nu=nus, batch=B)
+    sb.set_state(fields)
+    stats = sb.integrate(0.2, 0.05, 1e-9, 1e-9)
+    ub = sb.get_state().cpu().numpy()
+    sb.close()
+    for m in range(B):
+        s1 = solver(ns, n, "fp32", nu=nus[m])
+        s1.set_state(fields[m][None])
+        st1 = s1.integrate(0.2, 0.05, 1e-9, 1e-9)[0]
+        u1 = s1.get_state().cpu().numpy()[0]
+        s1.close()
+        assert st1["n_rhs"] == stats[m]["n_rhs"]
+        assert np.array_equal(u1.view(np.float64), ub[m].view(np.float64))
