@@ -86,7 +86,8 @@ extern "C" {
 
 typedef struct ns_config {
   int dim;              /* 3, or 2 */
-  int n;                /* points per direction: power of two, 8..512 (3D), 8..1024 (2D) */
+  int n;                /* points per direction: power of two, 8..1024 (3D at 1024:
+                           about 175 GB of workspace with an FP32 right-hand side) */
   int batch;            /* ensemble members B >= 1, stepped together */
   int rhs_precision;    /* NS_FP32 or NS_FP64; state and reductions are always FP64 */
   int scalar;           /* 2D only: 1 = Boussinesq density as third component */
@@ -94,7 +95,7 @@ typedef struct ns_config {
   double kappa;         /* Boussinesq scalar diffusivity */
   double force_kf;      /* 3D: forcing band 0 < |k| <= kf after each accepted step; <= 0 off */
   double force_e0;      /* energy the forcing restores */
-  int dealias;          /* NS_DEALIAS_23, or NS_DEALIAS_32 (n >= 16) */
+  int dealias;          /* NS_DEALIAS_23, or NS_DEALIAS_32 (n >= 16; 3D n <= 512) */
 } ns_config;
 
 typedef struct ns_solver ns_solver;

@@ -73,10 +73,13 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool valid_config(const ns_config* c) {
   if (!c) return false;
   if (c->dim != 2 && c->dim != 3) return false;
-  const int maxn = c->dim == 3 ? 512 : 1024;
+  // 3D up to 1024 points (about 175 GB of workspace with an FP32 right-hand
+  // side); the padded grids of the 3/2 rule up to 768 in 3D (n <= 512), whose
+  // kernels' 32-bit byte offsets would not hold a 1536-point grid
+  const int maxn = 1024;
   if (c->n < 8 || c->n > maxn || (c->n & (c->n - 1))) return false;
   if (c->dealias != NS_DEALIAS_23 && c->dealias != NS_DEALIAS_32) return false;
-  if (c->dealias == NS_DEALIAS_32 && c->n < 16) return false;
+  if (c->dealias == NS_DEALIAS_32 && (c->n < 16 || (c->dim == 3 && c->n > 512))) return false;
   if (c->batch < 1 || c->batch > 65535) return false;
   if (c->rhs_precision != NS_FP32 && c->rhs_precision != NS_FP64) return false;
   if (c->scalar != 0 && !(c->dim == 2 && c->scalar == 1)) return false;

@@ -36,6 +36,7 @@ static hipError_t dispatch3d(const Geom& g, const UT* U, double2* K, const RhsPa
     case 128: return run3d<128, T, UT>(g, U, K, p, b, tw, st);
     case 256: return run3d<256, T, UT>(g, U, K, p, b, tw, st);
     case 512: return run3d<512, T, UT>(g, U, K, p, b, tw, st);
+    case 1024: return run3d<1024, T, UT>(g, U, K, p, b, tw, st);
     default: return dispatch3d_padded<T, UT>(g, U, K, p, b, tw, st);
   }
 }

@@ -503,7 +503,8 @@ static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2s, int z0, 
 template <int N, typename T, int V>
 static void launch_xpass(const Geom& g, const cplx<T>* A2s, cplx<T>* A3s, int zs, const cplx<T>* tw,
                          hipStream_t st) {
-  using PL = typename std::conditional<(V == 1 && N >= 64), PlanS<N>, Plan<N>>::type;
+  // the narrow plan only where a row's threads still fit in one wavefront
+  using PL = typename std::conditional<(V == 1 && N >= 64 && PlanS<N>::TT <= 64), PlanS<N>, Plan<N>>::type;
   using RC = RowCfg<PL, T>;
   const long long rows = (long long)zs * N;       // per member
   hipLaunchKernelGGL((k_xpass<PL, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB), g.batch), dim3(RC::NT),

@@ -410,6 +410,7 @@ hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, do
       case 128: launch_reduce<128, 3>(g, a, partials, nblk, nvel, st); break;
       case 256: launch_reduce<256, 3>(g, a, partials, nblk, nvel, st); break;
       case 512: launch_reduce<512, 3>(g, a, partials, nblk, nvel, st); break;
+      case 1024: launch_reduce<1024, 3>(g, a, partials, nblk, nvel, st); break;
       case 24: launch_reduce<24, 3>(g, a, partials, nblk, nvel, st); break;
       case 48: launch_reduce<48, 3>(g, a, partials, nblk, nvel, st); break;
       case 96: launch_reduce<96, 3>(g, a, partials, nblk, nvel, st); break;

@@ -42,9 +42,12 @@ def test_host_only_entry_points(lib):
     assert ns.ns_workspace_bytes(ok) > 0
     assert ns.ns_workspace_bytes(ns.NsConfig(2, 1024, 1, 0, 1, 0.5, 1e-4, 0, 0)) > 0
     assert ns.ns_workspace_bytes(ns.NsConfig(2, 64, 3, 1, 0, 0, 0, 0, 0)) > 0
+    w1024 = ns.ns_workspace_bytes(ns.NsConfig(3, 1024, 1, 0, 0, 0, 0, 0, 0))
+    assert 150e9 < w1024 < 200e9              # fits the 288 GB of one MI355X
     assert ns.ns_workspace_bytes(ns.NsConfig(2, 1024, 1, 0, 1, 0.5, 1e-4, 0, 0, 1)) > 0   # 3/2 rule
     for bad in [ns.NsConfig(3, 48, 1, 0, 0, 0, 0, 0, 0),     # not a power of two
-                ns.NsConfig(3, 1024, 1, 0, 0, 0, 0, 0, 0),   # 3D limited to 512
+                ns.NsConfig(3, 2048, 1, 0, 0, 0, 0, 0, 0),   # limited to 1024
+                ns.NsConfig(3, 1024, 1, 0, 0, 0, 0, 0, 0, 1),  # 3/2 rule: 3D up to 512
                 ns.NsConfig(4, 32, 1, 0, 0, 0, 0, 0, 0),
                 ns.NsConfig(3, 32, 0, 0, 0, 0, 0, 0, 0),
                 ns.NsConfig(3, 32, 1, 2, 0, 0, 0, 0, 0),
