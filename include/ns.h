@@ -263,9 +263,10 @@ int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
  * tile (16, 32 or 64 columns per block).  Parameter 5 is the slab schedule of
  * the y/x/y passes: variant v < 5 runs them over slabs of n >> v planes of z
  * (at least 1) through slab buffers that are reused, so that small slabs stay
- * in the memory-side cache; v >= 5 uses slabs of n >> (v - 4) planes that
+ * in the memory-side cache; 5 <= v < 9 uses slabs of n >> (v - 4) planes that
  * alternate between two streams and two buffers, so that one slab's passes
- * overlap the next one's.  ns_autotune times every variant of every
+ * overlap the next one's; 9, 10 (one stream) and 11, 12 (two streams) use
+ * the finer slabs n >> 5 and n >> 6.  ns_autotune times every variant of every
  * parameter on the current state (reps evaluations each, HIP events: the z
  * passes per launch, the y/x/y passes and the slab schedule by the wall time
  * of the y/x/y phase per evaluation) and keeps the fastest; ms_host
@@ -278,7 +279,7 @@ int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
  * the whole right-hand side; the other parameters are accepted and ignored,
  * as are all of them below 256 points. */
 #define NS_NTUNE 6
-#define NS_TUNE_MAXV 9
+#define NS_TUNE_MAXV 13
 int ns_autotune(ns_solver* s, int reps, double* ms_host);
 int ns_tune_get(ns_solver* s, int* variant_host);
 int ns_tune_set(ns_solver* s, const int* variant_host);

@@ -44,12 +44,13 @@ struct RhsBufs {
   hipStream_t side;   // second stream of the two-stream slab schedule (default priority)
   hipEvent_t fork, join;   // order `side` after / before the solver's stream
 };
-constexpr int NVARIANT_COL = 5, NVARIANT_ROW = 2, NVARIANT_SLAB = 9;
+constexpr int NVARIANT_COL = 5, NVARIANT_ROW = 2, NVARIANT_SLAB = 13;
 // 3D slab schedule of the y/x/y passes, variant v: v < 5 one stream with
-// slabs of n >> v planes; v >= 5 slabs of n >> (v - 4) planes alternating
+// slabs of n >> v planes; 5 <= v < 9 slabs of n >> (v - 4) planes alternating
 // between two streams and two slab buffers, so that the passes of one slab
-// overlap those of the next.  The default is the largest one-stream slab
-// whose buffers fit in 96 MiB.
+// overlap those of the next; 9, 10 one stream and 11, 12 two streams with the
+// finer slabs n >> 5 and n >> 6 (for the large grids, whose planes are big).
+// The default is the largest one-stream slab whose buffers fit in 96 MiB.
 int slab_planes(const Geom& g, int v);
 bool slab_two_streams(int v);
 int default_slab_variant(const Geom& g, int fp64);

@@ -10,10 +10,10 @@ template <typename T, typename UT>
 hipError_t dispatch3d_padded(const Geom& g, const UT* U, double2* K, const RhsParams& p,
                              const RhsBufs& b, const void* tw, hipStream_t st);
 
-bool slab_two_streams(int v) { return v >= 5; }
+bool slab_two_streams(int v) { return (v >= 5 && v < 9) || v >= 11; }
 
 int slab_planes(const Geom& g, int v) {
-  const int sh = v < 0 ? 0 : (v >= 5 ? v - 4 : v);
+  const int sh = v < 0 ? 0 : (v < 5 ? v : (v < 9 ? v - 4 : (v < 11 ? v - 4 : v - 6)));
   const int zs = g.n >> sh;
   return zs < 1 ? 1 : zs;
 }

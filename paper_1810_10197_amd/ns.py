@@ -46,7 +46,7 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
            "ns_profile_stop", "ns_strerror", "ns_free"]
 NS_NTUNE = 6
-NS_TUNE_MAXV = 9
+NS_TUNE_MAXV = 13
 NS_DEALIAS = {"2/3": 0, "3/2": 1}
 PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other", "slab"]
 

@@ -133,7 +133,7 @@ def test_every_launch_variant_matches_oracle(ns, n):
     u = inputs.random_isotropic(n, 300 + n)
     ref = spectral.rhs_ns3d(u, nu)
     s = solver(ns, n, "fp32", nu=nu)
-    for v in range(9):
+    for v in range(13):
         s.tune([v % 5, v % 5, v % 2, v % 5, v % 5, v])
         got = s.rhs(u[None]).cpu().numpy()[0]
         errs = per_field_rel_l2(got, ref)
