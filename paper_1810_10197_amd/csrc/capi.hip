@@ -1150,6 +1150,19 @@ int ns_tune_set(ns_solver* s, const int* v) {
   return NS_OK;
 }
 
+// The right-hand side the autotuner times: the one the steps run.  With an
+// FP32 3D right-hand side that is the stage form, whose input is the FP32
+// stage state (here u_n rounded once into the stage buffer).
+static int tune_rhs(ns_solver* s) {
+  if (!stage32(s)) return rhs(s, s->u, s->k[7]);
+  nsk::RhsParams p;
+  p.nu = s->nu_d;
+  p.ri = s->cfg.ri;
+  p.kappa = s->cfg.kappa;
+  const hipError_t e = nsk::rhs3d_compact(s->g, 0, nullptr, s->U32, s->k[7], p, s->rb, s->tw, s->st);
+  return e == hipSuccess ? NS_OK : NS_ERR_HIP;
+}
+
 int ns_autotune(ns_solver* s, int reps, double* ms_host) {
   if (!s || reps < 1) return NS_ERR_ARG;
   if (!s->have_state) return NS_ERR_STATE;
@@ -1157,6 +1170,12 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
     for (int i = 0; i < NS_NTUNE * NS_TUNE_MAXV; ++i) ms_host[i] = 0.0;
   const bool was_on = s->prof_on;
   int rc = NS_OK;
+  if (stage32(s)) {                            // the stage input: u_n in FP32
+    Combo c;
+    c.nterms = 0;
+    NS_HIP(nsk::fill(s->h_d, 0.0, s->g.batch, s->st));
+    NS_HIP(nsk::combine2(s->g, s->u, c, s->h_d, nullptr, s->U32, nullptr, s->st));
+  }
   // 3D: the slab first (it changes what the passes read from), then every
   // pass; 2D: the layout between the x-pass and Q3 (slot 2, timed over the
   // whole right-hand side), then the two column passes (Q1 in slot 0, Q3 in
@@ -1172,10 +1191,10 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
     int best_v = s->rb.variant[p];
     for (int v = 0; v < nv && !rc; ++v) {
       s->rb.variant[p] = v;
-      rc = rhs(s, s->u, s->k[7]);               // warm-up (and first-launch costs)
+      rc = tune_rhs(s);                         // warm-up (and first-launch costs)
       if (rc) break;
       rc = ns_profile_start(s);
-      for (int r = 0; r < reps && !rc; ++r) rc = rhs(s, s->u, s->k[7]);
+      for (int r = 0; r < reps && !rc; ++r) rc = tune_rhs(s);
       ns_kernel_times kt;
       const int rc2 = ns_profile_stop(s, &kt);
       if (rc || rc2) {
