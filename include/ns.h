@@ -188,6 +188,11 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol,
 size_t ns_checkpoint_bytes(const ns_solver* s);
 int ns_checkpoint_save(ns_solver* s, void* host_buf, size_t bytes);
 int ns_checkpoint_load(ns_solver* s, const void* host_buf, size_t bytes);
+/* The same in one pair of calls: ns_save with host_blob NULL writes the size
+ * a checkpoint needs to *bytes (host); with a buffer of *bytes bytes it saves
+ * and sets *bytes to the size written.  ns_load is ns_checkpoint_load. */
+int ns_save(ns_solver* s, void* host_blob, size_t* bytes);
+int ns_load(ns_solver* s, const void* host_blob, size_t bytes);
 
 /* Time of each member (host array of batch values); set_time resets it. */
 int ns_get_time(ns_solver* s, double* t_host);

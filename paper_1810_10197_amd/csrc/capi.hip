@@ -971,6 +971,20 @@ int ns_checkpoint_load(ns_solver* s, const void* host_buf, size_t bytes) {
   return NS_OK;
 }
 
+int ns_save(ns_solver* s, void* host_blob, size_t* bytes) {
+  if (!s || !bytes) return NS_ERR_ARG;
+  const size_t need = ns_checkpoint_bytes(s);
+  if (!host_blob) {
+    *bytes = need;
+    return NS_OK;
+  }
+  const int rc = ns_checkpoint_save(s, host_blob, *bytes);
+  if (rc == NS_OK) *bytes = need;
+  return rc;
+}
+
+int ns_load(ns_solver* s, const void* host_blob, size_t bytes) { return ns_checkpoint_load(s, host_blob, bytes); }
+
 int ns_get_time(ns_solver* s, double* t_host) {
   if (!s || !t_host) return NS_ERR_ARG;
   for (int m = 0; m < s->g.batch; ++m) t_host[m] = s->t[m];

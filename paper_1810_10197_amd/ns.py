@@ -43,6 +43,7 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_mlp_get_weights", "ns_mlp_forward", "ns_mlp_grad", "ns_mlp_train_batch",
            "ns_mlp_reset_optimizer", "ns_mlp_collect", "ns_mlp_rows", "ns_mlp_push_rows",
            "ns_mlp_fit_stats", "ns_checkpoint_bytes", "ns_checkpoint_save", "ns_checkpoint_load",
+           "ns_save", "ns_load",
            "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
            "ns_profile_stop", "ns_strerror", "ns_free"]
 NS_NTUNE = 6
@@ -119,6 +120,8 @@ _sig = {
     "ns_checkpoint_bytes": (ctypes.c_size_t, [_P]),
     "ns_checkpoint_save": (_I, [_P, _P, ctypes.c_size_t]),
     "ns_checkpoint_load": (_I, [_P, _P, ctypes.c_size_t]),
+    "ns_save": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "ns_load": (_I, [_P, _P, ctypes.c_size_t]),
     "ns_free": (None, [_P]),
 }
 for _name, (_res, _args) in _sig.items():

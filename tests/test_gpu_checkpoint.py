@@ -71,3 +71,25 @@ def test_checkpoint_of_another_configuration_is_refused(ns):
     with pytest.raises(ns.NsError):
         t.restore(buf)
     t.close()
+
+
+def test_save_and_load_pair(ns):
+    """ns_save reports the size with a NULL buffer, then saves; ns_load restores:
+    the state read back is the one saved."""
+    import ctypes
+    announce("ns_save / ns_load")
+    fields, nus = inputs.ensemble_members(2, 16)
+    s = ns.Solver(dim=3, n=16, batch=2, nu=nus, rhs_precision="fp32")
+    s.set_state(fields)
+    s.integrate(0.1, 0.05, 1e-8, 1e-8)
+    size = ctypes.c_size_t(0)
+    assert ns._lib.ns_save(s.handle, None, ctypes.byref(size)) == ns.NS_OK and size.value > 0
+    buf = np.zeros(size.value, dtype=np.uint8)
+    assert ns._lib.ns_save(s.handle, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(size)) == ns.NS_OK
+    u = s.get_state().cpu().numpy()
+    s.close()
+    t = ns.Solver(dim=3, n=16, batch=2, nu=nus, rhs_precision="fp32")
+    assert ns._lib.ns_load(t.handle, buf.ctypes.data_as(ctypes.c_void_p), size.value) == ns.NS_OK
+    assert np.array_equal(t.get_state().cpu().numpy().view(np.float64), u.view(np.float64))
+    t.close()
+
