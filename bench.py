@@ -252,10 +252,10 @@ def study_e1(args):
     from paper_1810_10197_amd import inputs, ns
     n, nu, T = args.n if args.n != 256 else 64, 1.0 / 280, 9.4
     u0 = inputs.tgv3d(n)[None]
-    out = {"study": "tgv_re280", "n": n, "T": T, "nu": nu, "precision": "fp64"}
+    out = {"study": "tgv_re280", "n": n, "T": T, "nu": nu, "precision": "fp64", "dealias": args.dealias}
 
     def solver():
-        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp64")
+        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp64", dealias=args.dealias)
         s.set_state(u0)
         return s
 
@@ -677,7 +677,8 @@ def bench_throughput(args):
     fp64 = args.prec == "fp64"
     padded = args.dealias == "3/2"
     if padded and wl == "ensemble":
-        raise SystemExit("--dealias 3/2 applies to the Taylor-Green and Rayleigh-Taylor workloads")
+        raise SystemExit("--dealias 3/2 applies to the Taylor-Green and Rayleigh-Taylor workloads "
+                         "(and to --study e1)")
     if wl == "tgv":
         n, batch, dim = args.n, 1, 3
         nu = 1.0 / 1600
