@@ -197,6 +197,36 @@ def test_tgv_c1_fp64_rk4_and_bs5(ns):
     s.close()
 
 
+def test_bs5_attempts_256_full_size_autotuned(ns):
+    """Two BS5 attempts at 256^3 with an FP32 right-hand side, in the launch
+    configuration the throughput benchmark times (autotuned passes, the host
+    step path, FSAL k1 and FP32 stage-derivative copies on the second
+    attempt), against the oracle's FP64 attempts on a field that fills the
+    2/3-rule band.  The embedded estimate carries the FP32 rounding of the
+    stage derivatives, about h * sum|b - b^| * 1e-6 * |k| per mode, at most a
+    few percent of the difference per mode at this h; being uncorrelated with
+    it, that noise moves the root-mean-square norm by about half its squared
+    ratio (< 5e-4), so the estimate is compared at 1e-3."""
+    n, nu, h, tol = 256, 1.0 / 1600, 0.02, 1e-6
+    announce("bs5 attempts full n=%d fp32 autotuned" % n)
+    u0 = inputs.random_isotropic(n, 1810, k0=n / 8.0)
+    rhs = lambda u: spectral.rhs_ns3d(u, nu)
+    s = mk(ns, n, "fp32", nu)
+    s.set_state(u0[None])
+    s.autotune(reps=1)
+    ref1 = stepping.bs5_attempt(rhs, u0, h, tol, tol)
+    ref2 = stepping.bs5_attempt(rhs, ref1["u_new"], h, tol, tol, k1=ref1["k"][-1])
+    for ref in (ref1, ref2):
+        st, errs = s.step_bs5(h, tol, tol)
+        assert st == ns.NS_OK
+        got = s.get_state().cpu().numpy()[0]
+        e = per_field_rel_l2(got, ref["u_new"])
+        print("u_new rel L2", e, "err", errs[0], "oracle", ref["err"])
+        assert max(e) <= 1e-6, e
+        assert abs(errs[0] / ref["err"] - 1) <= 1e-3, (errs[0], ref["err"])
+    s.close()
+
+
 def test_fp32_rhs_against_fp64_tgv256_to_t1(ns):
     """Mixed precision at full size: the 256^3 Taylor-Green vortex to T = 1
     with an FP32 right-hand side stays within 1e-5 per-field relative L2 of
