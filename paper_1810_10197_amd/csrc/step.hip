@@ -42,6 +42,22 @@ __device__ __forceinline__ long long full_offset(const Geom& g, const Modes& md)
   return (long long)iy * nh + md.kx;
 }
 
+// Streaming loads (the nontemporal hint) for operands that a kernel reads
+// once: the state and stage-derivative arrays are far larger than the caches
+// and are next read a whole right-hand side later, so keeping them out of the
+// caches leaves those to the lines being written.  The values are those of a
+// plain load.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(v.x, v.y);
+}
+
 // Grid of the element-wise kernels: one element per thread, blockIdx.y =
 // member (no per-element division to find the member).
 static dim3 member_grid(long long per_member, int batch) {
@@ -66,8 +82,8 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ bas
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < epm; i += stride) {
     double2 v[NT > 0 ? NT : 1];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) v[j] = c.src[j][off + i];
-    double2 r = base ? base[off + i] : make_double2(0.0, 0.0);
+    for (int j = 0; j < NT; ++j) v[j] = ld_stream(c.src[j] + off + i);
+    double2 r = base ? ld_stream(base + off + i) : make_double2(0.0, 0.0);
     double sx = 0.0, sy = 0.0, dx = 0.0, dy = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
@@ -98,8 +114,8 @@ __global__ __launch_bounds__(256) void k_combine_s32(const double2* __restrict__
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < epm; i += stride) {
     float2 v[NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) v[j] = c.src32[j][off + i];
-    double2 r = base[off + i];
+    for (int j = 0; j < NT; ++j) v[j] = ld_stream(c.src32[j] + off + i);
+    double2 r = ld_stream(base + off + i);
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
@@ -285,13 +301,13 @@ __global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, double* __restrict
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const long long gi = base + (long long)(c < ncomp ? c : 0) * MRC + q;
-      un[c] = a.un[gi];
-      if (nt > 0) uo[c] = a.uo[gi];
+      un[c] = ld_stream(a.un + gi);
+      if (nt > 0) uo[c] = ld_stream(a.uo + gi);
       if (NT > 0) {
 #pragma unroll
-        for (int j = 0; j < NTL; ++j) v[c][j] = a.delta.src[j][gi];
+        for (int j = 0; j < NTL; ++j) v[c][j] = ld_stream(a.delta.src[j] + gi);
       }
-      if (a.fk && c < nvel) f[c] = a.fk[gi];
+      if (a.fk && c < nvel) f[c] = ld_stream(a.fk + gi);
     }
     double e = 0.0;
 #pragma unroll
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, double* __restrict
         } else {
           const long long gi = base + (long long)c * MRC + q;
           for (int j = 0; j < nt; ++j) {
-            const double2 vv = a.delta.src[j][gi];
+            const double2 vv = ld_stream(a.delta.src[j] + gi);
             dx += a.delta.coef[j] * vv.x;
             dy += a.delta.coef[j] * vv.y;
           }
