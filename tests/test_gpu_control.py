@@ -55,6 +55,34 @@ def test_integrate_rejections_match_oracle(ns):
     assert np.abs(got - ref["u"]).max() <= 1e-12 * np.abs(ref["u"]).max()
 
 
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("mean", [0.0, 0.3])
+def test_fixed_point_steps_grow_by_the_cap(ns, graph, mean):
+    """Degenerate cases: u = 0 and a uniform flow (only the k = 0 mode) are
+    fixed points (f = 0 exactly), every error is exactly 0, so the Sec. 2.2.1
+    factor takes its upper bound (2) at every step, with no division by zero;
+    the oracle's controller gives the same step sequence, the state does not
+    move, and a member beside it whose field is not a fixed point keeps its
+    own sequence (an ensemble of two)."""
+    n, nu = 16, 0.01
+    announce("fixed-point integrate n=%d mean=%g graph=%s" % (n, mean, graph))
+    u0 = np.zeros((3, n, n, n // 2 + 1), dtype=np.complex128)
+    u0[0, 0, 0, 0] = mean
+    ref = control.integrate(lambda u: spectral.rhs_ns3d(u, nu), u0, t_end=1.0, h0=0.01,
+                            atol=1e-8, rtol=1e-8)
+    assert ref["n_reject"] == 0 and np.array_equal(ref["u"], u0)
+    u1 = inputs.random_isotropic(n, 4)
+    s = ns.Solver(dim=3, n=n, batch=2, nu=nu, rhs_precision="fp64")
+    s.set_state(np.stack([u0, u1]))
+    st = s.integrate(1.0, 0.01, 1e-8, 1e-8, graph=graph)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    assert (st[0]["n_accept"], st[0]["n_reject"], st[0]["n_rhs"]) == (ref["n_accept"], 0, ref["n_rhs"])
+    assert st[0]["t"] == 1.0 and st[1]["t"] == 1.0
+    assert np.array_equal(got[0], u0)
+    assert np.all(np.isfinite(got[1].view(np.float64))) and np.abs(got[1]).max() > 0
+
+
 def test_ensemble_members_equal_single_runs(ns):
     """Each member of a batched adaptive run (own nu, own step sequence) is
     bitwise equal to the same run alone."""
