@@ -338,7 +338,11 @@ class Solver:
             x = t.from_numpy(np.ascontiguousarray(x, dtype=np.complex128))
         x = x.to(device=self.device, dtype=t.complex128).contiguous()
         if tuple(x.shape) != self.shape:
-            x = x.reshape(self.shape)
+            # one member may come without its batch axis; nothing else is reshaped
+            if self.batch == 1 and tuple(x.shape) == self.shape[1:]:
+                x = x.reshape(self.shape)
+            else:
+                raise ValueError("state shape %s, expected %s" % (tuple(x.shape), self.shape))
         return x
 
     def set_state(self, uhat):
