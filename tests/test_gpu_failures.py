@@ -74,3 +74,28 @@ def test_repeated_runs_are_bitwise_equal(ns):
         s.close()
     assert [x["n_rhs"] for x in res[0][0]] == [x["n_rhs"] for x in res[1][0]]
     assert np.array_equal(res[0][1].view(np.float64), res[1][1].view(np.float64))
+
+
+def test_bad_arguments_are_refused_without_a_launch(ns):
+    """Argument errors come back as errors before any kernel runs: a state of
+    the wrong shape (the binding), an unsupported size and a non-positive
+    step (the C ABI); the solver stays usable afterwards."""
+    n = 16
+    announce("argument errors")
+    with pytest.raises(ValueError):
+        ns.Solver(dim=3, n=20, nu=0.01)
+    s = ns.Solver(dim=3, n=n, batch=2, nu=0.01, rhs_precision="fp32")
+    u = inputs.random_isotropic(n, 2)
+    with pytest.raises(ValueError):
+        s.set_state(u)                          # one member for a batch of two
+    with pytest.raises(ValueError):
+        s.set_state(np.stack([u, u]).reshape(2, 3, n, n // 2 + 1, n))   # same size, other shape
+    s.set_state(np.stack([u, u]))
+    with pytest.raises(ns.NsError) as ei:
+        s.step_rk4(-0.1)
+    assert ei.value.status == ns.NS_ERR_ARG
+    s.step_rk4(0.01)
+    got = s.get_state().cpu().numpy()
+    assert np.all(np.isfinite(got.view(np.float64)))
+    assert np.array_equal(got[0].view(np.float64), got[1].view(np.float64))
+    s.close()
