@@ -219,32 +219,41 @@ template <class PL, typename T, int NF, int CMAX = 8> struct Q3Cfg {
   static constexpr int NT = C * TT * NF;
 };
 
-template <class PL, typename T, bool SCALAR, int CMAX, bool COLB2>
-__global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_yfwd(const cplx<T>* __restrict__ B2,
-                                                                          const double2* __restrict__ U,
-                                                                          double2* __restrict__ Kout, Geom g,
-                                                                          const double* __restrict__ nu,
-                                                                          double ri, double kappa,
-                                                                          const cplx<T>* __restrict__ tw) {
+// With SPLIT (Boussinesq only) a block takes two of the four fields: group 0
+// the velocity pair (n_x, n_y) and its projection, group 1 the density flux
+// (q_x, q_y) and its divergence; blockIdx.y = 2 member + group.  Half the
+// fields per block leaves room for twice the columns per tile.
+template <bool SCALAR, bool SPLIT> struct Q3Fields {
+  static constexpr int NF = SCALAR ? 4 : 2;
+  static constexpr int NFB = (SCALAR && SPLIT) ? 2 : NF;   // fields per block
+};
+
+template <class PL, typename T, bool SCALAR, int CMAX, bool COLB2, bool SPLIT>
+__global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::NT)) void k2_yfwd(
+    const cplx<T>* __restrict__ B2, const double2* __restrict__ U, double2* __restrict__ Kout, Geom g,
+    const double* __restrict__ nu, double ri, double kappa, const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N;
-  constexpr int NF = SCALAR ? 4 : 2;
+  constexpr int NFB = Q3Fields<SCALAR, SPLIT>::NFB;
+  constexpr bool SP = SCALAR && SPLIT;
   using V = cplx<T>;
-  using QC = Q3Cfg<PL, T, NF, CMAX>;
+  using QC = Q3Cfg<PL, T, NFB, CMAX>;
   constexpr int E = PL::E, C = QC::C, TT = QC::TT, LD = QC::LD;
-  __shared__ V lds[NF * C * LD];
+  __shared__ V lds[NFB * C * LD];
   const int f = threadIdx.x / (C * TT);
   const int rem = threadIdx.x - f * (C * TT);
   // transform phase: lanes along the column when it is contiguous (COLB2),
   // else across the tile's columns
   const int lc = COLB2 ? rem / TT : rem % C, t = COLB2 ? rem % TT : rem / C;
-  const int m = blockIdx.y;
+  const int grp = SP ? (int)(blockIdx.y & 1) : 0;
+  const int m = SP ? (int)(blockIdx.y >> 1) : (int)blockIdx.y;
+  const int fg = grp * 2 + f;                    // field of B2 this thread group transforms
   {
     const int kxt = blockIdx.x * C + lc;
     const bool vt = kxt < g.Kx;
     V* buf = lds + (f * C + lc) * LD;
     V o[E];
-    const V* in = COLB2 ? B2 + ((long long)(m * 4 + f) * g.Kx + (vt ? kxt : 0)) * N
-                        : B2 + ((long long)(m * 4 + f) * N) * g.Kx + (vt ? kxt : 0);
+    const V* in = COLB2 ? B2 + ((long long)(m * 4 + fg) * g.Kx + (vt ? kxt : 0)) * N
+                        : B2 + ((long long)(m * 4 + fg) * N) * g.Kx + (vt ? kxt : 0);
     const long long ys = COLB2 ? 1 : g.Kx;
 #pragma unroll
     for (int i = 0; i < E; ++i) o[i] = in[(long long)in_pos<PL>(t, i) * ys];
@@ -262,36 +271,43 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_y
   const double num = nu[m];
   const long long cs = g.mr;
   const V* col0 = lds + elc * LD;                // field c of this column: col0 + c * C * LD
+  const bool vel = !SP || grp == 0;              // this block writes f_u, f_v
+  const bool sca = SCALAR && (!SP || grp == 1);  // this block writes f_rho
 #pragma unroll
-  for (int i = f; i < E; i += NF) {
+  for (int i = f; i < E; i += NFB) {
     const int e = out_pos<PL>(et, i);
     if (!((e <= g.K) || (e >= N - g.K))) continue;
     const int ky = e <= g.K ? e : e - N;
     const long long idx = (long long)m * g.ncomp * cs + (long long)(ky >= 0 ? ky : ky + g.Kf) * g.Kx + kx;
     const double k2 = (double)(kx * kx + ky * ky);
-    const V v0 = col0[e], v1 = col0[C * LD + e];
-    double nx = (double)v0.x * scale, nxi = (double)v0.y * scale;
-    double ny = (double)v1.x * scale, nyi = (double)v1.y * scale;
     if (k2 == 0.0) {
-      Kout[idx] = make_double2(0.0, 0.0);
-      Kout[idx + cs] = make_double2(0.0, 0.0);
-      if constexpr (SCALAR) Kout[idx + 2 * cs] = make_double2(0.0, 0.0);
+      if (vel) {
+        Kout[idx] = make_double2(0.0, 0.0);
+        Kout[idx + cs] = make_double2(0.0, 0.0);
+      }
+      if (sca) Kout[idx + 2 * cs] = make_double2(0.0, 0.0);
       continue;
     }
-    const double2 u0 = U[idx], u1 = U[idx + cs];
     double2 rh = make_double2(0.0, 0.0);
-    if constexpr (SCALAR) {
-      rh = U[idx + 2 * cs];
-      ny -= ri * rh.x;               // buoyancy -Ri rho e_y, before the projection
-      nyi -= ri * rh.y;
+    if constexpr (SCALAR) rh = U[idx + 2 * cs];
+    if (vel) {
+      const V v0 = col0[e], v1 = col0[C * LD + e];
+      double nx = (double)v0.x * scale, nxi = (double)v0.y * scale;
+      double ny = (double)v1.x * scale, nyi = (double)v1.y * scale;
+      const double2 u0 = U[idx], u1 = U[idx + cs];
+      if constexpr (SCALAR) {
+        ny -= ri * rh.x;               // buoyancy -Ri rho e_y, before the projection
+        nyi -= ri * rh.y;
+      }
+      const double px = (kx * nx + ky * ny) / k2, py = (kx * nxi + ky * nyi) / k2;
+      const double vk = num * k2;
+      Kout[idx] = make_double2(nx - kx * px - vk * u0.x, nxi - kx * py - vk * u0.y);
+      Kout[idx + cs] = make_double2(ny - ky * px - vk * u1.x, nyi - ky * py - vk * u1.y);
     }
-    const double px = (kx * nx + ky * ny) / k2, py = (kx * nxi + ky * nyi) / k2;
-    const double vk = num * k2;
-    Kout[idx] = make_double2(nx - kx * px - vk * u0.x, nxi - kx * py - vk * u0.y);
-    Kout[idx + cs] = make_double2(ny - ky * px - vk * u1.x, nyi - ky * py - vk * u1.y);
-    if constexpr (SCALAR) {
-      // -i k . q_hat - kappa |k|^2 rho_hat
-      const V v2 = col0[2 * C * LD + e], v3 = col0[3 * C * LD + e];
+    if (sca) {
+      // -i k . q_hat - kappa |k|^2 rho_hat (q_x, q_y are this block's fields 0, 1 when split)
+      constexpr int q0 = SP ? 0 : 2;
+      const V v2 = col0[q0 * C * LD + e], v3 = col0[(q0 + 1) * C * LD + e];
       const double sx = kx * ((double)v2.x * scale) + ky * ((double)v3.x * scale);
       const double sy = kx * ((double)v2.y * scale) + ky * ((double)v3.y * scale);
       const double kk2 = kappa * k2;
@@ -304,16 +320,19 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, SCALAR ? 4 : 2, CMAX>::NT)) void k2_y
 // Launch variants (the autotuner's choice; grids below 256 points use 0):
 // Q1 (tuning slot 0) 0 default tile, 1 four columns, 2 two columns, 3 narrow
 // plan default tile, 4 narrow plan two columns; Q3 (slot 4) 0 up to eight
-// columns, 1 two, 2 one, 3 narrow plan up to eight, 4 narrow plan one; the
-// layout of B2 (slot 2) 0 row-major, 1 column-major.  The x-pass keeps the
-// wide plan (a row stays inside one wavefront).
+// columns, 1 two, 2 one (Boussinesq: the fields split over two blocks, up to
+// eight columns), 3 narrow plan up to eight, 4 narrow plan one (Boussinesq:
+// split, up to eight); the layout of B2 (slot 2) 0 row-major, 1
+// column-major.  The x-pass keeps the wide plan (a row stays inside one
+// wavefront).
 template <int N, int V> struct Q1Var {
   using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
   static constexpr int CW = N < 256 ? 0 : (V == 1 ? 4 : (V == 2 || V == 4 ? 2 : 0));
 };
-template <int N, int V> struct Q3Var {
+template <int N, int V, bool SCALAR> struct Q3Var {
   using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
-  static constexpr int CMAX = N < 256 ? 8 : (V == 1 ? 2 : (V == 2 || V == 4 ? 1 : 8));
+  static constexpr bool SPLIT = SCALAR && N >= 256 && (V == 2 || V == 4);
+  static constexpr int CMAX = N < 256 ? 8 : (V == 1 ? 2 : ((V == 2 || V == 4) && !SPLIT ? 1 : 8));
 };
 
 template <int N, typename T, int VAR>
@@ -329,11 +348,11 @@ static void launch_q1(const Geom& g, const double2* U, cplx<T>* B1, int nfield, 
 template <int N, typename T, bool SCALAR, int VAR, bool COLB2>
 static void launch_q3(const Geom& g, const cplx<T>* B2, const double2* U, double2* K, const RhsParams& p,
                       const cplx<T>* tw, hipStream_t st) {
-  using QV = Q3Var<N, VAR>;
-  using QC = Q3Cfg<typename QV::PL, T, SCALAR ? 4 : 2, QV::CMAX>;
-  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX, COLB2>),
-                     dim3((g.Kx + QC::C - 1) / QC::C, g.batch), dim3(QC::NT), 0, st, B2, U, K, g, p.nu, p.ri,
-                     p.kappa, tw);
+  using QV = Q3Var<N, VAR, SCALAR>;
+  using QC = Q3Cfg<typename QV::PL, T, Q3Fields<SCALAR, QV::SPLIT>::NFB, QV::CMAX>;
+  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX, COLB2, QV::SPLIT>),
+                     dim3((g.Kx + QC::C - 1) / QC::C, g.batch * (QV::SPLIT ? 2 : 1)), dim3(QC::NT), 0, st, B2,
+                     U, K, g, p.nu, p.ri, p.kappa, tw);
 }
 template <int N, typename T, bool SCALAR, bool COLB2>
 static void launch_q3v(int v3, const Geom& g, const cplx<T>* B2, const double2* U, double2* K,
