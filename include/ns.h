@@ -281,9 +281,9 @@ int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
  * parameter 0 is the y-inverse's and parameter 4 the y-forward's variant
  * (radix plan and column tile, 0-4; with the Boussinesq scalar, y-forward
  * variants 2 and 4 split the four fields over two blocks), timed per launch;
- * parameter 2 the layout
- * the x-pass hands to the y-forward (0 row-major, 1 column-major), timed over
- * the whole right-hand side; the other parameters are accepted and ignored,
+ * parameter 2 the layout the x-pass hands to the y-forward (0 row-major, 1
+ * column-major), timed over the whole right-hand side; the other parameters
+ * are accepted and ignored,
  * as are all of them below 256 points. */
 #define NS_NTUNE 6
 #define NS_TUNE_MAXV 13
