@@ -283,8 +283,7 @@ int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
  * variants 2 and 4 split the four fields over two blocks), timed per launch;
  * parameter 2 the layout the x-pass hands to the y-forward (0 row-major, 1
  * column-major), timed over the whole right-hand side; the other parameters
- * are accepted and ignored,
- * as are all of them below 256 points. */
+ * are accepted and ignored, as are all of them below 256 points. */
 #define NS_NTUNE 6
 #define NS_TUNE_MAXV 13
 int ns_autotune(ns_solver* s, int reps, double* ms_host);
