@@ -113,6 +113,32 @@ def cpu_baseline(n, nu, budget_s, padded=False):
                       % (count, "3/2" if padded else "2/3", n, dt)}
 
 
+def quadratic_interpolant(tref, yref):
+    """Reference curve of the Re = 280 test (Sec. 3.1): between samples
+    (tref, yref) of the reference run, the quadratic through the three samples
+    nearest to t (Lagrange form)."""
+    import numpy as np
+    tref = np.asarray(tref, dtype=float)
+    yref = np.asarray(yref, dtype=float)
+    if len(tref) < 3:
+        raise ValueError("a quadratic needs three samples")
+
+    def at(t):
+        j = int(np.clip(np.searchsorted(tref, t) - 1, 1, len(tref) - 2))
+        x, y = tref[j - 1:j + 2], yref[j - 1:j + 2]
+        return (y[0] * (t - x[1]) * (t - x[2]) / ((x[0] - x[1]) * (x[0] - x[2]))
+                + y[1] * (t - x[0]) * (t - x[2]) / ((x[1] - x[0]) * (x[1] - x[2]))
+                + y[2] * (t - x[0]) * (t - x[1]) / ((x[2] - x[0]) * (x[2] - x[1])))
+    return at
+
+
+def max_deviation(ts, ys, ref):
+    """An arm's error in the Re = 280 test: max |y(t) - ref(t)| over the arm's
+    own output times (inf if any value is not finite)."""
+    d = [abs(y - ref(t)) for t, y in zip(ts, ys)]
+    return float(max(d)) if d and all(math.isfinite(x) for x in d) else float("inf")
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -282,17 +308,10 @@ def study_e1(args):
     out["ref_wall_s"] = time.perf_counter() - t0
     log("reference: %d samples, %.1f s" % (len(tref), out["ref_wall_s"]))
 
-    def eps_ref(t):
-        # quadratic through the three samples around t
-        j = int(np.clip(np.searchsorted(tref, t) - 1, 1, len(tref) - 2))
-        x, y = tref[j - 1:j + 2], eref[j - 1:j + 2]
-        return (y[0] * (t - x[1]) * (t - x[2]) / ((x[0] - x[1]) * (x[0] - x[2]))
-                + y[1] * (t - x[0]) * (t - x[2]) / ((x[1] - x[0]) * (x[1] - x[2]))
-                + y[2] * (t - x[0]) * (t - x[1]) / ((x[2] - x[0]) * (x[2] - x[1])))
+    eps_ref = quadratic_interpolant(tref, eref)
 
     def err_of(ts, es):
-        d = [abs(e - eps_ref(t)) for t, e in zip(ts, es)]
-        return float(max(d)) if all(math.isfinite(x) for x in d) else float("inf")
+        return max_deviation(ts, es, eps_ref)
 
     out["rk4"] = []
     for dt in args.e1_dts:

@@ -17,7 +17,7 @@ the retained set of the 3/2 rule).
   workload): for every retained mode a vector of unit-modulus random phases
   times A(|k|) = |k| exp(-(|k|/k0)^2), made solenoidal by taking k_unit x a
   (so k . u_hat = 0 by construction, no projection), Hermitian on the kx = 0
-  plane, scaled so that 1/2 sum w |u_hat|^2 = E0 (w = 2 off the kx = 0 plane).
+  plane, scaled so that half the mean of |u|^2 over the physical grid is E0.
 * Rayleigh--Taylor (Sec. 3.2, 2D workload): u = v = 0 and
   rho = tanh((y - pi + 0.05 cos 4x)/0.02) sampled on the grid, transformed
   with numpy.fft and restricted to the retained modes.
@@ -84,9 +84,11 @@ def _hermitian_kx0(a, n, K=None):
 
 
 def _energy_scale(u, e0):
-    w = np.full(u.shape[1:], 2.0)
-    w[..., 0] = 1.0
-    e = 0.5 * float(np.sum(w * np.sum(np.abs(u) ** 2, axis=0)))
+    """Scale u so that half the mean of |u|^2 over the physical grid is e0
+    (the field is synthesised in physical space by numpy's inverse FFT)."""
+    n = u.shape[1]
+    phys = np.fft.irfftn(u * float(n) ** 3, s=(n, n, n), axes=(1, 2, 3))
+    e = 0.5 * float(np.mean(np.sum(phys * phys, axis=0)))
     return u * np.sqrt(e0 / e)
 
 

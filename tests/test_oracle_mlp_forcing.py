@@ -68,7 +68,10 @@ def test_features_layout():
 def test_random_isotropic_field(n, seed):
     u = inputs.random_isotropic(n, seed)
     assert np.abs(spectral.divergence3(u)).max() < 1e-15
-    assert diagnostics.energy(u, 3) == pytest.approx(0.125, rel=1e-15)
+    # the oracle's half-spectrum energy against the physical-space mean (Parseval)
+    phys = spectral.inverse(u, n, 3)
+    assert 0.5 * float(np.mean(np.sum(phys * phys, axis=0))) == pytest.approx(0.125, rel=1e-14)
+    assert diagnostics.energy(u, 3) == pytest.approx(0.125, rel=1e-14)
     # real-valued in physical space: round trip is exact
     back = spectral.forward(spectral.inverse(u, n, 3), 3)
     assert np.abs(back - u).max() < 1e-15

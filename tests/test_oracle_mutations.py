@@ -85,3 +85,46 @@ def test_padding_that_keeps_the_nyquist_mode_is_caught(monkeypatch):
 def test_unpadded_2d_product_is_caught(monkeypatch):
     monkeypatch.setattr(spectral, "padded_size", lambda n: n)
     assert _fails(ts.test_padded_rhs2d_against_direct_convolution, 10, 3, 52)
+
+
+def test_shell_bins_scaled_by_half_the_grid_are_caught(monkeypatch):
+    # bins relative to N/2 instead of the cutoff K
+    import test_oracle_diagnostics as td
+    from oracle import diagnostics
+    monkeypatch.setattr(diagnostics, "cutoff", lambda n: n // 2)
+    assert _fails(td.test_bins_are_relative_to_the_cutoff)
+    assert _fails(td.test_single_mode_lands_in_its_bin, (0, 3, 4), 8)
+
+
+def test_dropped_half_spectrum_weight_is_caught(monkeypatch):
+    # every half-spectrum entry counted once (the conjugate twins forgotten)
+    import test_oracle_diagnostics as td
+    from oracle import diagnostics
+    monkeypatch.setattr(diagnostics, "weights",
+                        lambda n, dim: np.ones((n,) * (dim - 1) + (n // 2 + 1,)))
+    assert _fails(td.test_energy_and_shells_against_physical_space, 16, 3)
+    assert _fails(td.test_single_mode_lands_in_its_bin, (6, 0, 0), 9)
+
+
+def test_flipped_buoyancy_sign_is_caught(monkeypatch):
+    # gravity along +y: the heavy-over-light interface becomes stable
+    import test_oracle_rt as tr
+    orig = spectral.rhs_ns2d
+    monkeypatch.setattr(spectral, "rhs_ns2d", lambda uh, nu, kappa=0.0, ri=0.0: orig(uh, nu, kappa, -ri))
+    assert _fails(tr.test_mode4_grows_at_the_linear_rate)
+
+
+def test_unclipped_last_rk4_step_is_caught(monkeypatch):
+    # ceil(t_end/h) full steps: the run overshoots t_end
+    import math
+    import test_oracle_stepping as tst
+    from oracle import control, stepping
+
+    def overshoot(rhs, u0, t_end, h):
+        n = max(1, int(math.ceil(t_end / h - 1e-9)))
+        u = u0.copy()
+        for _ in range(n):
+            u = stepping.rk4_step(rhs, u, h)
+        return u, n
+    monkeypatch.setattr(control, "rk4_fixed", overshoot)
+    assert _fails(tst.test_rk4_fixed_clips_the_last_step, 0.37, 0.1, 4, 0.07)

@@ -139,3 +139,19 @@ def test_local_error_estimate_scales_as_h5():
         res = stepping.bs5_attempt(rhs, u0, h, 1.0, 0.0)
         d.append(np.abs(res["delta"]).max())
     assert 4.6 < np.log2(d[0] / d[1]) < 5.6
+
+
+@pytest.mark.parametrize("t_end,h,steps,last", [(0.37, 0.1, 4, 0.07), (0.3, 0.1, 3, 0.1),
+                                                (0.05, 0.1, 1, 0.05)])
+def test_rk4_fixed_clips_the_last_step(t_end, h, steps, last):
+    """Fixed-step RK4 to a t_end that is not a multiple of h: ceil(t_end/h)
+    steps, the last one shortened to land on t_end.  On the 2D TGV every step
+    multiplies the state by R_RK4(-2 nu h), so the end state is
+    R(-2 nu h)^(steps-1) R(-2 nu last) u0 exactly."""
+    n, nu = 8, 0.5
+    u0 = inputs.tgv2d_in3d(n)
+    rhs = lambda u: spectral.rhs_ns3d(u, nu)
+    u, count = control.rk4_fixed(rhs, u0, t_end, h)
+    assert count == steps
+    expect = peval(R_RK4, -2 * nu * h) ** (steps - 1) * peval(R_RK4, -2 * nu * last) * u0
+    assert np.abs(u - expect).max() < 1e-15
