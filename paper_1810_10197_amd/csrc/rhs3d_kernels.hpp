@@ -158,19 +158,27 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
 
 // ---------------------------------------------------------------- P2
 // Columns (zl, kx) of one (member, field) in the slab z0 .. z0+zs-1: 2K+1
-// non-zero ky' -> N values of y.
+// non-zero ky' -> N values of y.  Logical block id = (member, field, column
+// tile), remapped so that each XCD takes a contiguous range: neighbouring
+// tiles, whose output rows share cache lines at the tile edges, then write
+// through the same L2 (about 1% faster than the plain 2D grid at 256^3).
 template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
                                                              cplx<T>* __restrict__ A2s, int z0, int zs,
+                                                             long long nblocks,
                                                              const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
-  const long long bf = blockIdx.y;                // member * 6 + field
+  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;                       // uniform per block
+  const int ntx = (zs * KX + C - 1) / C;
+  const long long bf = L / ntx;                   // member * 6 + field
+  const int bx = (int)(L - bf * ntx);
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int cz = blockIdx.x * C + lc;             // slab column zl * KX + kx
+  const int cz = bx * C + lc;                     // slab column zl * KX + kx
   const bool valid = cz < zs * KX;
   const int czc = valid ? cz : 0;
   Tw<PL, V> w;
@@ -332,20 +340,26 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
 
 // ---------------------------------------------------------------- P4
 // Columns (zl, kx) of one (member, component) in the slab: N values of y ->
-// 2K+1 retained ky, written to plane z0 + zl of A4.
+// 2K+1 retained ky, written to plane z0 + zl of A4 (blocks XCD-grouped as in
+// P2).
 template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3s,
                                                              cplx<T>* __restrict__ A4, int z0, int zs,
+                                                             long long nblocks,
                                                              const cplx<T>* __restrict__ tw) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
-  const long long bc = blockIdx.y;                // member * 3 + component
-  const int lc = threadIdx.x % C, t = threadIdx.x / C;
   const int nkxs = zs * KX;                       // row length of the slab buffer
-  const int cz = blockIdx.x * C + lc;
+  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;                       // uniform per block
+  const int ntx = (nkxs + C - 1) / C;
+  const long long bc = L / ntx;                   // member * 3 + component
+  const int bx = (int)(L - bc * ntx);
+  const int lc = threadIdx.x % C, t = threadIdx.x / C;
+  const int cz = bx * C + lc;
   const bool valid = cz < nkxs;
   const int czc = valid ? cz : 0;
   Tw<PL, V> w;
@@ -497,8 +511,10 @@ static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2s, int z0, 
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = zs * g.Kx;
-  hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch * 6),
-                     dim3(CF::NT), 0, st, A1, A2s, z0, zs, tw);
+  const int ntx = (ncol + CF::C - 1) / CF::C;
+  const long long nb = (long long)ntx * g.batch * 6;
+  const dim3 grid((unsigned)((nb + 7) / 8 * 8));
+  hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), grid, dim3(CF::NT), 0, st, A1, A2s, z0, zs, nb, tw);
 }
 template <int N, typename T, int V>
 static void launch_xpass(const Geom& g, const cplx<T>* A2s, cplx<T>* A3s, int zs, const cplx<T>* tw,
@@ -516,8 +532,10 @@ static void launch_yfwd(const Geom& g, const cplx<T>* A3s, cplx<T>* A4, int z0, 
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = zs * g.Kx;
-  hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), dim3((ncol + CF::C - 1) / CF::C, g.batch * 3),
-                     dim3(CF::NT), 0, st, A3s, A4, z0, zs, tw);
+  const int ntx = (ncol + CF::C - 1) / CF::C;
+  const long long nb = (long long)ntx * g.batch * 3;
+  const dim3 grid((unsigned)((nb + 7) / 8 * 8));
+  hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), grid, dim3(CF::NT), 0, st, A3s, A4, z0, zs, nb, tw);
 }
 template <int N, typename T, int V, typename UT>
 static void launch_zfwd(const Geom& g, const cplx<T>* A4, const UT* U, double2* K, float2* K32,
