@@ -61,6 +61,7 @@ extern "C" {
 #define NS_ERR_STEPFAIL (-5)    /* too many consecutive rejected steps */
 #define NS_ERR_UNSUPPORTED (-6) /* size or mode not built */
 #define NS_ERR_STATE (-7)       /* call out of order (e.g. no state set) */
+#define NS_ERR_SCRATCH (-8)     /* ns_rhs_static: the problem exceeds its static scratch */
 
 #define NS_DEALIAS_23 0         /* 2/3 rule: |k_j| <= (n-1)/3, products on the n grid */
 #define NS_DEALIAS_32 1         /* 3/2 rule (Sec. 2.1.1): |k_j| <= n/2-1, products on
@@ -132,6 +133,36 @@ int ns_set_nu(ns_solver* s, const double* nu_host);
 /* f(u_hat) of Eq. (2) (or Eqs. (4a-b)) for every member: uhat and f in the
  * state layout, may not alias.  Does not touch the solver's state. */
 int ns_rhs(ns_solver* s, const void* uhat, void* f);
+
+/* Allocation-free right-hand side, for callers that cannot allocate device
+ * memory or create a solver: code under HIP stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Computes what ns_rhs computes,
+ * f(u_hat) for every member of cfg, with the same pass kernels (default
+ * launch variants, one stream), but takes no solver and no workspace: the
+ * compact state, f, the transform intermediates, the twiddle table and the
+ * viscosities live in one file-scope device array of NS_STATIC_SCRATCH_BYTES
+ * that each GPU the library runs on holds until the process ends.
+ *   cfg      configuration as for ns_init (forcing fields are ignored), with
+ *            batch <= NS_STATIC_MAX_BATCH
+ *   nu_host  [batch] viscosities (host memory, read before the call returns)
+ *   uhat, f  device buffers in the state layout; may not alias
+ *   stream   hipStream_t or NULL; the work is stream-ordered and asynchronous
+ * Returns NS_ERR_ARG for an invalid cfg, batch or pointer, NS_ERR_SCRATCH
+ * (nothing launched) when the problem's buffers exceed the array, e.g. a 3D
+ * grid above 64^3 (the sizes that fit are those ns_rhs_static_bytes accepts),
+ * NS_ERR_HIP on a failed launch.  Calls no allocating routine.  Every call on
+ * one GPU uses that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller; nothing in
+ * the array needs to start at zero (every buffer is written before it is
+ * read within the call). */
+#define NS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+#define NS_STATIC_MAX_BATCH 64
+int ns_rhs_static(const ns_config* cfg, const double* nu_host, const void* uhat, void* f,
+                  void* stream);
+
+/* Bytes of the static array ns_rhs_static would use for cfg (0 if cfg is
+ * invalid); the call is accepted iff 0 < bytes <= NS_STATIC_SCRATCH_BYTES. */
+size_t ns_rhs_static_bytes(const ns_config* cfg);
 
 /* One classical RK4 step of size h for every member (committed). */
 int ns_step_rk4(ns_solver* s, double h);

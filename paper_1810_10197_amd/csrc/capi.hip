@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1293,6 +1294,7 @@ const char* ns_strerror(int status) {
     case NS_ERR_STEPFAIL: return "too many consecutive rejected steps";
     case NS_ERR_UNSUPPORTED: return "size or mode not supported";
     case NS_ERR_STATE: return "call out of order (state or weights not set)";
+    case NS_ERR_SCRATCH: return "problem exceeds the static scratch of ns_rhs_static";
     default: return "unknown status";
   }
 }
@@ -1306,6 +1308,119 @@ void ns_free(ns_solver* s) {
   if (s->rb.join) (void)hipEventDestroy(s->rb.join);
   for (auto& e : s->prof_ev) (void)hipEventDestroy(e);
   delete s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free right-hand side
+// ns_rhs_static: the right-hand side of ns_rhs for callers that cannot
+// allocate.  Every buffer comes from `scratch`, one file-scope device array;
+// its device address on each GPU is looked up once (hipGetSymbolAddress, with
+// that device current) and kept per device: the array's name in host code is
+// only a host-side stand-in, so kernels always receive the looked-up address.
+static __device__ __align__(256) char scratch[NS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[STATIC_MAX_DEVICES];        // device address of `scratch` per device
+
+struct NuArg { double v[NS_STATIC_MAX_BATCH]; };
+
+// viscosities from the kernel argument, twiddles exp(-2 pi i m / TWN) from
+// the device's double-precision sincospi, in the right-hand side's precision
+__global__ void k_static_setup(double* nu, NuArg a, int batch, void* tw, int fp64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < batch) nu[i] = a.v[i];
+  if (i < nsk::TWN_TABLE) {
+    double sn, cs;
+    sincospi(-2.0 * (double)i / (double)nsk::TWN_TABLE, &sn, &cs);
+    if (fp64) ((double2*)tw)[i] = make_double2(cs, sn);
+    else ((float2*)tw)[i] = make_float2((float)cs, (float)sn);
+  }
+}
+
+struct StaticLayout { size_t tw, nu, u, k, a1, a2, total; };
+
+StaticLayout static_layout(const ns_config* c, const Geom& g) {
+  const int fp64 = c->rhs_precision == NS_FP64;
+  const size_t B = (size_t)g.batch;
+  const size_t sc = g.dim == 3 ? nsk::rhs3d_scratch_bytes(g, fp64) : nsk::rhs2d_scratch_bytes(g, fp64);
+  const size_t a1 = g.dim == 3 ? sc : sc / 2;  // as the solver's workspace splits it
+  StaticLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  L.tw = take((size_t)nsk::TWN_TABLE * 16);
+  L.nu = take(B * 8);
+  L.u = take((size_t)g.epm * B * 16);
+  L.k = take((size_t)g.epm * B * 16);
+  L.a1 = take(a1);
+  L.a2 = take(sc - a1);
+  L.total = off;
+  return L;
+}
+
+// the array's device address on the current device (looked up on first use)
+void* static_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_static_ptr[dev] = p;
+  }
+  return g_static_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ns_rhs_static_bytes(const ns_config* cfg) {
+  if (!valid_config(cfg) || cfg->batch > NS_STATIC_MAX_BATCH) return 0;
+  return static_layout(cfg, make_geom(cfg)).total;
+}
+
+int ns_rhs_static(const ns_config* cfg, const double* nu_host, const void* uhat, void* f, void* stream) {
+  if (!valid_config(cfg) || cfg->batch > NS_STATIC_MAX_BATCH || !nu_host || !uhat || !f || uhat == f)
+    return NS_ERR_ARG;
+  const Geom g = make_geom(cfg);
+  const StaticLayout L = static_layout(cfg, g);
+  if (L.total > NS_STATIC_SCRATCH_BYTES) return NS_ERR_SCRATCH;
+  char* base = (char*)static_scratch();
+  if (!base) return NS_ERR_HIP;
+  const hipStream_t st = (hipStream_t)stream;
+  const int fp64 = cfg->rhs_precision == NS_FP64;
+  NuArg a;
+  for (int m = 0; m < NS_STATIC_MAX_BATCH; ++m) a.v[m] = m < g.batch ? nu_host[m] : 0.0;
+  double* nu = (double*)(base + L.nu);
+  void* tw = base + L.tw;
+  const int nset = nsk::TWN_TABLE > g.batch ? nsk::TWN_TABLE : g.batch;
+  hipLaunchKernelGGL(k_static_setup, dim3((nset + 255) / 256), dim3(256), 0, st, nu, a, g.batch, tw, fp64);
+  NS_HIP(hipGetLastError());
+  double2* U = (double2*)(base + L.u);
+  double2* K = (double2*)(base + L.k);
+  NS_HIP(nsk::pack_state(g, (const double2*)uhat, U, st));
+  nsk::RhsBufs rb;
+  rb.a1 = base + L.a1;
+  rb.a2 = base + L.a2;
+  rb.hook = nullptr;
+  rb.hook_ctx = nullptr;
+  for (int i = 0; i < NS_NTUNE; ++i) rb.variant[i] = 0;
+  if (g.dim == 3) rb.variant[5] = nsk::default_slab_variant(g, fp64);   // a one-stream schedule
+  rb.side = nullptr;
+  rb.fork = rb.join = nullptr;
+  nsk::RhsParams p;
+  p.nu = nu;
+  p.ri = cfg->ri;
+  p.kappa = cfg->kappa;
+  const hipError_t e = g.dim == 3 ? nsk::rhs3d_compact(g, fp64, U, nullptr, K, p, rb, tw, st)
+                                  : nsk::rhs2d_compact(g, fp64, U, K, p, rb, tw, st);
+  NS_HIP(e);
+  NS_HIP(nsk::unpack_state(g, K, (double2*)f, st));
+  return NS_OK;
 }
 
 }  // extern "C"

@@ -26,6 +26,7 @@ NS_ERR_NONFINITE = -4
 NS_ERR_STEPFAIL = -5
 NS_ERR_UNSUPPORTED = -6
 NS_ERR_STATE = -7
+NS_ERR_SCRATCH = -8
 NS_FP32 = 0
 NS_FP64 = 1
 NS_CTRL_PI = 0
@@ -36,6 +37,8 @@ NS_METHOD_DP5 = 0x200
 NS_INTEGRATE_RESUME = 0x400
 NS_MLP_NPARAM = 5569
 NS_MLP_NWEIGHTS = 5609
+NS_STATIC_SCRATCH_BYTES = 64 << 20
+NS_STATIC_MAX_BATCH = 64
 
 EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_set_nu",
            "ns_rhs", "ns_step_rk4", "ns_step_bs5", "ns_step_dp5", "ns_integrate", "ns_get_time",
@@ -45,7 +48,7 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_mlp_fit_stats", "ns_checkpoint_bytes", "ns_checkpoint_save", "ns_checkpoint_load",
            "ns_save", "ns_load",
            "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
-           "ns_profile_stop", "ns_strerror", "ns_free"]
+           "ns_profile_stop", "ns_strerror", "ns_free", "ns_rhs_static", "ns_rhs_static_bytes"]
 NS_NTUNE = 6
 NS_TUNE_MAXV = 13
 NS_DEALIAS = {"2/3": 0, "3/2": 1}
@@ -123,6 +126,8 @@ _sig = {
     "ns_save": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
     "ns_load": (_I, [_P, _P, ctypes.c_size_t]),
     "ns_free": (None, [_P]),
+    "ns_rhs_static": (_I, [ctypes.POINTER(NsConfig), _DP, _P, _P, _P]),
+    "ns_rhs_static_bytes": (ctypes.c_size_t, [ctypes.POINTER(NsConfig)]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -303,6 +308,16 @@ def ns_profile_stop(h, out):
 
 def ns_free(h):
     _lib.ns_free(h)
+
+
+def ns_rhs_static(cfg, nu, uhat_ptr, f_ptr, stream_ptr):
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    return _check(_lib.ns_rhs_static(ctypes.byref(cfg), _dptr(nu), _P(uhat_ptr), _P(f_ptr),
+                                     _P(stream_ptr)), "ns_rhs_static")
+
+
+def ns_rhs_static_bytes(cfg):
+    return int(_lib.ns_rhs_static_bytes(ctypes.byref(cfg)))
 
 
 # ---------------------------------------------------------------- wrapper
