@@ -111,7 +111,7 @@ Geom make_geom(const ns_config* c) {
 }
 
 struct Layout {
-  size_t tw32, tw64, nu, h, red_out, mask, alpha, red_part;
+  size_t tw32, tw64, nu, h, red_out, mask, alpha, red_part, bandb;
   size_t ctl_d[6], ctl_i[7], ctl_l[3];
   size_t mw, mmom, mvel, mgrad, mloss, mx, my, pend_x, pend_h, pend_ok, ring_x, ring_y, ring_n, rows, act;
   size_t fields[10], stage32, dpart, k32, a1, a2, total;
@@ -131,6 +131,7 @@ Layout make_layout(const ns_config* c) {
   L.mask = take(B * 4);
   L.alpha = take(B * 8);
   L.red_part = take(nsk::reduce_scratch_bytes(g));
+  L.bandb = take(B * nsk::NBINS * 8);
   for (int i = 0; i < 6; ++i) L.ctl_d[i] = take(B * 8 * (i == 5 ? 3 : 1));
   for (int i = 0; i < 7; ++i) L.ctl_i[i] = take(B * 4);
   for (int i = 0; i < 3; ++i) L.ctl_l[i] = take(B * 8);
@@ -179,6 +180,7 @@ struct ns_solver {
   double* h_d;
   double* red_out;
   double* red_part;
+  double* bandb;     // per member: energy of the forcing band in each shell
   int* mask_d;
   double* alpha_d;
   void* tw;          // twiddles in the rhs precision
@@ -253,12 +255,14 @@ static float2* k32_of(const ns_solver* s, const double2* K) {
 
 // want32: also write the FP32 copy of K (a later FP32 stage combination
 // reads it).
-static int rhs(ns_solver* s, const double2* U, double2* K, bool want32 = false) {
+// active (3D, may be null): device flags of the members to evaluate.
+static int rhs(ns_solver* s, const double2* U, double2* K, bool want32 = false, const int* active = nullptr) {
   nsk::RhsParams p;
   p.nu = s->nu_d;
   p.ri = s->cfg.ri;
   p.kappa = s->cfg.kappa;
   p.k32 = want32 ? k32_of(s, K) : nullptr;
+  p.active = active;
   hipError_t e = s->g.dim == 3 ? nsk::rhs3d_compact(s->g, s->fp64, U, nullptr, K, p, s->rb, s->tw, s->st)
                                : nsk::rhs2d_compact(s->g, s->fp64, U, K, p, s->rb, s->tw, s->st);
   return e == hipSuccess ? NS_OK : NS_ERR_HIP;
@@ -397,10 +401,14 @@ static int reduce_committed(ns_solver* s, const double2* fk) {
 
 // Sec. 3.3.1 forcing after committed steps: rescale 0 < |k| <= kf of every
 // member whose mask_dev entry is set (all if mask_dev is null) to restore E0.
-static int apply_forcing(ns_solver* s, const int* mask_dev) {
+// have_reduction: red_out already holds E and the band energy of the
+// committed state of those members (the reduction of the accepted attempt).
+static int apply_forcing(ns_solver* s, const int* mask_dev, bool have_reduction = false) {
   if (s->cfg.force_kf <= 0.0) return NS_OK;
-  int rc = reduce_committed(s, nullptr);
-  if (rc) return rc;
+  if (!have_reduction) {
+    int rc = reduce_committed(s, nullptr);
+    if (rc) return rc;
+  }
   NS_HIP(nsk::force_alpha(s->red_out, mask_dev, s->cfg.force_e0, s->alpha_d, s->g.batch, s->st));
   NS_HIP(nsk::scale_band(s->g, s->u, s->alpha_d, forcing_kf2(s), s->st));
   s->k1_valid = false;
@@ -442,21 +450,26 @@ static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
     NS_HIP(nsk::masked_copy(s->g, s->k[last], s->k[0], s->mask_d, s->st));
     if (s->k32[0]) NS_HIP(nsk::masked_copy32(s->g, s->k32[last], s->k32[0], s->mask_d, s->st));
   }
-  if (nacc > 0) return apply_forcing(s, s->mask_d);
+  if (nacc > 0) return apply_forcing(s, s->mask_d, true);   // red_out: the attempt's reduction
   return NS_OK;
 }
 
 // One attempt of ns_integrate, all on the device: stages, reduction, the
 // proposer's features (and proposal), the controller, row collection, the
-// masked commit and the forcing.  Captured once into a graph.
+// masked commit and the forcing.  Captured once into a graph.  In a forced
+// run the proposer sees the state after the forcing (as the oracle's
+// proposer does): its shell features take the band rescaled by alpha^2,
+// from the attempt's reduction and the band's energy per shell.
 static int integrate_attempt(ns_solver* s, const Pair& P, double atol, double rtol, double t_end, int use_mlp) {
   int rc = embedded_stages(s, P, s->ctl.hc, atol, rtol);
   if (rc) return rc;
   const double M = (double)s->g.full;
   const bool need_x = use_mlp || s->collect;
+  const bool forced = s->cfg.force_kf > 0.0;
+  if (need_x && forced) NS_HIP(nsk::band_bins(s->g, s->U, forcing_kf2(s), s->bandb, s->st));
   if (need_x)
     NS_HIP(nsk::mlp_propose(s->red_out, s->ctl.errhist, M, s->g.ncomp, s->mw, use_mlp, s->mx, s->my,
-                            s->g.batch, s->st));
+                            s->g.batch, forced ? s->bandb : nullptr, s->cfg.force_e0, s->st));
   const int extra = s->cfg.force_kf > 0.0 ? 1 : 0;
   NS_HIP(nsk::control_step(s->ctl, s->red_out, M, s->g.ncomp, t_end, s->g.batch, s->my, use_mlp, P.stages - 1,
                            extra, s->st));
@@ -466,10 +479,13 @@ static int integrate_attempt(ns_solver* s, const Pair& P, double atol, double rt
   NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->ctl.accept, s->st));
   NS_HIP(nsk::masked_copy(s->g, s->k[P.stages - 1], s->k[0], s->ctl.accept, s->st));
   if (s->k32[0]) NS_HIP(nsk::masked_copy32(s->g, s->k32[P.stages - 1], s->k32[0], s->ctl.accept, s->st));
-  if (s->cfg.force_kf > 0.0) {
-    rc = apply_forcing(s, s->ctl.accept);
+  if (forced) {
+    // E and the band energy of the accepted members' new state are in the
+    // attempt's reduction; only those members are forced, and only their
+    // first stage is evaluated again (the others keep theirs)
+    rc = apply_forcing(s, s->ctl.accept, true);
     if (rc) return rc;
-    rc = rhs(s, s->u, s->k[0], true);
+    rc = rhs(s, s->u, s->k[0], true, s->ctl.accept);
     if (rc) return rc;
     s->k1_valid = true;
   }
@@ -504,6 +520,7 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->h_d = (double*)(w + L.h);
   s->red_out = (double*)(w + L.red_out);
   s->red_part = (double*)(w + L.red_part);
+  s->bandb = (double*)(w + L.bandb);
   s->mask_d = (int*)(w + L.mask);
   s->alpha_d = (double*)(w + L.alpha);
   s->tw = w + (s->fp64 ? L.tw64 : L.tw32);

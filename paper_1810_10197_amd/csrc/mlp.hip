@@ -53,13 +53,25 @@ __device__ __forceinline__ float mlp_forward_block(const float* __restrict__ w, 
 __global__ __launch_bounds__(64) void k_mlp_propose(const double* __restrict__ red,
                                                     const double* __restrict__ errhist, double M,
                                                     int ncomp, const float* __restrict__ w, int infer,
-                                                    float* __restrict__ xout, float* __restrict__ yout) {
+                                                    float* __restrict__ xout, float* __restrict__ yout,
+                                                    const double* __restrict__ bandbins, double e0) {
   const int m = blockIdx.x, j = threadIdx.x;
   __shared__ float xs[MI], zs[MI], a1s[MH], a2s[MH];
   const double* r = red + (long long)m * NRED;
   if (j < 16) {
-    const double e = r[3] > 1e-300 ? r[3] : 1e-300;
-    xs[j] = (float)log10(r[5 + j] / e + 1e-30);
+    double e = r[3], sb = r[5 + j];
+    if (bandbins) {
+      // the state after the forcing: the band's modes scaled by alpha
+      const double eb = r[21];
+      if (eb > 0.0) {
+        const double rest = e0 - (e - eb);
+        const double a2 = (rest > 0.0 ? rest : 0.0) / eb;
+        sb += (a2 - 1.0) * bandbins[m * 16 + j];
+        e += (a2 - 1.0) * eb;
+      }
+    }
+    e = e > 1e-300 ? e : 1e-300;
+    xs[j] = (float)log10(sb / e + 1e-30);
   } else if (j < 19) {
     const double v = errhist[m * 3 + (j - 16)];
     xs[j] = (float)log10(v > 1e-30 ? v : 1e-30);
@@ -197,8 +209,10 @@ __global__ void k_mlp_stats(float* __restrict__ w, const float* __restrict__ x, 
 
 // ---------------------------------------------------------------- host side
 hipError_t mlp_propose(const double* red, const double* errhist, double M, int ncomp, const float* w,
-                       int infer, float* xout, float* yout, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_propose, dim3(batch), dim3(64), 0, st, red, errhist, M, ncomp, w, infer, xout, yout);
+                       int infer, float* xout, float* yout, int batch, const double* bandbins, double e0,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_propose, dim3(batch), dim3(64), 0, st, red, errhist, M, ncomp, w, infer, xout, yout,
+                     bandbins, e0);
   return hipGetLastError();
 }
 

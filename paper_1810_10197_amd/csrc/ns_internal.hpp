@@ -26,6 +26,8 @@ struct RhsParams {
   const double* nu;   // [batch]
   double ri, kappa;   // Boussinesq
   float2* k32 = nullptr;   // 3D FP32 right-hand side: also write f rounded to FP32 (may be null)
+  const int* active = nullptr;   // 3D: [batch] device flags, evaluate only members with a nonzero
+                                 // flag (their f and copies are left as they are); null: all
 };
 
 // Optional timing hook called around every kernel launch: phase 0 before,
@@ -127,8 +129,17 @@ hipError_t masked_copy(const Geom& g, const double2* src, double2* dst, const in
 // ---- step-size proposer network (mlp.hip) ----
 constexpr int MLP_NPARAM = 5569;     // W1 64x20, b1, W2 64x64, b2, W3 1x64, b3
 constexpr int MLP_NWEIGHTS = 5609;   // + feature mean [20] and scale [20]
+// Features (and, with infer, the proposal) of every member from its
+// reduction and error history.  With bandbins (non-null) the features are
+// those of the state after the Sec. 3.3.1 forcing: bandbins[m][b] is the
+// energy of the forcing band's modes in shell b, and the band is rescaled by
+// alpha^2 = max(e0 - (E - E_band), 0) / E_band as the forcing does.
 hipError_t mlp_propose(const double* red, const double* errhist, double M, int ncomp, const float* w,
-                       int infer, float* xout, float* yout, int batch, hipStream_t st);
+                       int infer, float* xout, float* yout, int batch, const double* bandbins, double e0,
+                       hipStream_t st);
+// bandbins[m][b]: energy 1/2 w |u_hat|^2 of the modes 0 < |k|^2 <= kf2 of
+// member m that fall in shell b (3D).
+hipError_t band_bins(const Geom& g, const double2* u, double kf2, double* bandbins, hipStream_t st);
 hipError_t mlp_forward(const float* w, const float* x, float* y, int n, hipStream_t st);
 size_t mlp_act_floats(int nmax);
 hipError_t mlp_grad(const float* w, const float* x, const float* t, const int* rows, int n, float* act,

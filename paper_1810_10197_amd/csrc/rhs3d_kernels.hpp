@@ -100,7 +100,8 @@ __device__ __forceinline__ void zinv_loads(const UT* pa, const UT* pb, unsigned 
 template <class PL, typename T, int CW, typename UT>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __restrict__ U,
                                                              cplx<T>* __restrict__ A1, long long nblocks,
-                                                             const cplx<T>* __restrict__ tw) {
+                                                             const cplx<T>* __restrict__ tw,
+                                                             const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
   constexpr long long MR = (long long)NCOL * KF;
   using V = cplx<T>;
@@ -114,6 +115,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
   const long long q = L / 6;
   const int tile = (int)(q % ntiles);
   const int m = (int)(q / ntiles);
+  if (active && !active[m]) return;             // member not evaluated (uniform per block)
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
   const int col = tile * C + lc;
   const bool valid = col < NCOL;
@@ -166,7 +168,8 @@ template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
                                                              cplx<T>* __restrict__ A2s, int z0, int zs,
                                                              long long nblocks,
-                                                             const cplx<T>* __restrict__ tw) {
+                                                             const cplx<T>* __restrict__ tw,
+                                                             const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
@@ -177,6 +180,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
   const int ntx = (zs * KX + C - 1) / C;
   const long long bf = L / ntx;                   // member * 6 + field
   const int bx = (int)(L - bf * ntx);
+  if (active && !active[bf / 6]) return;
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
   const int cz = bx * C + lc;                     // slab column zl * KX + kx
   const bool valid = cz < zs * KX;
@@ -230,7 +234,8 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
 template <class PL, typename T>
 __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2s,
                                                               cplx<T>* __restrict__ A3s, int zs,
-                                                              const cplx<T>* __restrict__ tw) {
+                                                              const cplx<T>* __restrict__ tw,
+                                                              const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KX = K + 1;
   using V = cplx<T>;
   using RC = RowCfg<PL, T>;
@@ -239,6 +244,7 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
   const int grp = threadIdx.x / TT, t = threadIdx.x % TT;
   const long long RPM = (long long)zs * N;        // rows (zl, y) per member in the slab
   const long long m = blockIdx.y;
+  if (active && !active[m]) return;
   const long long row = (long long)blockIdx.x * RC::RPB + grp;
   const bool valid = row < RPM;
   const long long rr = valid ? row : 0;
@@ -346,7 +352,8 @@ template <class PL, typename T, int CW>
 __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3s,
                                                              cplx<T>* __restrict__ A4, int z0, int zs,
                                                              long long nblocks,
-                                                             const cplx<T>* __restrict__ tw) {
+                                                             const cplx<T>* __restrict__ tw,
+                                                             const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
@@ -358,6 +365,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>*
   const int ntx = (nkxs + C - 1) / C;
   const long long bc = L / ntx;                   // member * 3 + component
   const int bx = (int)(L - bc * ntx);
+  if (active && !active[bc / 3]) return;
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
   const int cz = bx * C + lc;
   const bool valid = cz < nkxs;
@@ -400,7 +408,8 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
                                                            double2* __restrict__ Kout,
                                                            float2* __restrict__ K32,
                                                            const double* __restrict__ nu,
-                                                           const cplx<T>* __restrict__ tw) {
+                                                           const cplx<T>* __restrict__ tw,
+                                                           const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
   constexpr int NCOLP = (NCOL + 31) / 32 * 32;      // line-aligned z-row pitch of A4
   constexpr long long MR = (long long)NCOL * KF;
@@ -411,6 +420,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
   const int col = blockIdx.x * C + lc;
   const int m = blockIdx.y;
+  if (active && !active[m]) return;
   const bool valid = col < NCOL;
   const int colc = valid ? col : 0;
   Tw<PL, V> w;
@@ -496,57 +506,60 @@ template <int N, int V> struct ColVar {
   if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, stream)
 
 template <int N, typename T, int V, typename UT>
-static void launch_zinv(const Geom& g, const UT* U, cplx<T>* A1, const cplx<T>* tw, hipStream_t st) {
+static void launch_zinv(const Geom& g, const UT* U, cplx<T>* A1, const cplx<T>* tw, const int* act,
+                        hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = g.Kf * g.Kx;
   const long long nb = (long long)g.batch * 6 * ((ncol + CF::C - 1) / CF::C);
   const long long nbp = (nb + 7) / 8 * 8;
   hipLaunchKernelGGL((k_zinv<typename CV::PL, T, CV::CW, UT>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, U, A1,
-                     nb, tw);
+                     nb, tw, act);
 }
 template <int N, typename T, int V>
 static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2s, int z0, int zs, const cplx<T>* tw,
-                        hipStream_t st) {
+                        const int* act, hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = zs * g.Kx;
   const int ntx = (ncol + CF::C - 1) / CF::C;
   const long long nb = (long long)ntx * g.batch * 6;
   const dim3 grid((unsigned)((nb + 7) / 8 * 8));
-  hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), grid, dim3(CF::NT), 0, st, A1, A2s, z0, zs, nb, tw);
+  hipLaunchKernelGGL((k_yinv<typename CV::PL, T, CV::CW>), grid, dim3(CF::NT), 0, st, A1, A2s, z0, zs, nb, tw,
+                     act);
 }
 template <int N, typename T, int V>
 static void launch_xpass(const Geom& g, const cplx<T>* A2s, cplx<T>* A3s, int zs, const cplx<T>* tw,
-                         hipStream_t st) {
+                         const int* act, hipStream_t st) {
   // the narrow plan only where a row's threads still fit in one wavefront
   using PL = typename std::conditional<(V == 1 && N >= 64 && PlanS<N>::TT <= 64), PlanS<N>, Plan<N>>::type;
   using RC = RowCfg<PL, T>;
   const long long rows = (long long)zs * N;       // per member
   hipLaunchKernelGGL((k_xpass<PL, T>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB), g.batch), dim3(RC::NT),
-                     0, st, A2s, A3s, zs, tw);
+                     0, st, A2s, A3s, zs, tw, act);
 }
 template <int N, typename T, int V>
 static void launch_yfwd(const Geom& g, const cplx<T>* A3s, cplx<T>* A4, int z0, int zs, const cplx<T>* tw,
-                        hipStream_t st) {
+                        const int* act, hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = zs * g.Kx;
   const int ntx = (ncol + CF::C - 1) / CF::C;
   const long long nb = (long long)ntx * g.batch * 3;
   const dim3 grid((unsigned)((nb + 7) / 8 * 8));
-  hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), grid, dim3(CF::NT), 0, st, A3s, A4, z0, zs, nb, tw);
+  hipLaunchKernelGGL((k_yfwd<typename CV::PL, T, CV::CW>), grid, dim3(CF::NT), 0, st, A3s, A4, z0, zs, nb, tw,
+                     act);
 }
 template <int N, typename T, int V, typename UT>
 static void launch_zfwd(const Geom& g, const cplx<T>* A4, const UT* U, double2* K, float2* K32,
-                        const double* nu, const cplx<T>* tw, hipStream_t st) {
+                        const double* nu, const cplx<T>* tw, const int* act, hipStream_t st) {
   // P5 holds three transformed fields: a 64-column block would exceed the
   // registers of 1024 threads, so its variant 4 is variant 1
   using CV = ColVar<N, V == 4 ? 1 : V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = g.Kf * g.Kx;
   hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW, UT>), dim3((ncol + CF::C - 1) / CF::C, g.batch),
-                     dim3(CF::NT), 0, st, A4, U, K, K32, nu, tw);
+                     dim3(CF::NT), 0, st, A4, U, K, K32, nu, tw, act);
 }
 
 // Scratch regions of one evaluation (T complex), each 256-byte aligned: A1,
@@ -582,15 +595,16 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
   V* A1 = (V*)(base + sc.a1);
   V* A4 = (V*)(base + sc.a4);
   const int* tv = bufs.variant;
+  const int* act = p.active;                       // members to evaluate (null: all)
   const bool two = slab_two_streams(tv[5]) && bufs.side && N >= 2;
   const int zs = slab_planes(g, tv[5]);
   NSK_MARK(PROF_P1, 0, st);
   switch (tv[0]) {
-    case 1: launch_zinv<N, T, 1, UT>(g, U, A1, tw, st); break;
-    case 2: launch_zinv<N, T, 2, UT>(g, U, A1, tw, st); break;
-    case 3: launch_zinv<N, T, 3, UT>(g, U, A1, tw, st); break;
-      case 4: launch_zinv<N, T, 4, UT>(g, U, A1, tw, st); break;
-    default: launch_zinv<N, T, 0, UT>(g, U, A1, tw, st);
+    case 1: launch_zinv<N, T, 1, UT>(g, U, A1, tw, act, st); break;
+    case 2: launch_zinv<N, T, 2, UT>(g, U, A1, tw, act, st); break;
+    case 3: launch_zinv<N, T, 3, UT>(g, U, A1, tw, act, st); break;
+      case 4: launch_zinv<N, T, 4, UT>(g, U, A1, tw, act, st); break;
+    default: launch_zinv<N, T, 0, UT>(g, U, A1, tw, act, st);
   }
   NSK_MARK(PROF_P1, 1, st);
   // the slab phase is timed as a whole: its launches may overlap on two
@@ -609,20 +623,20 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
     V* A2s = (V*)(base + sc.a2s[b]);
     V* A3s = (V*)(base + sc.a3s[b]);
     switch (tv[1]) {
-      case 1: launch_yinv<N, T, 1>(g, A1, A2s, z0, nz, tw, ss); break;
-      case 2: launch_yinv<N, T, 2>(g, A1, A2s, z0, nz, tw, ss); break;
-      case 3: launch_yinv<N, T, 3>(g, A1, A2s, z0, nz, tw, ss); break;
-      case 4: launch_yinv<N, T, 4>(g, A1, A2s, z0, nz, tw, ss); break;
-      default: launch_yinv<N, T, 0>(g, A1, A2s, z0, nz, tw, ss);
+      case 1: launch_yinv<N, T, 1>(g, A1, A2s, z0, nz, tw, act, ss); break;
+      case 2: launch_yinv<N, T, 2>(g, A1, A2s, z0, nz, tw, act, ss); break;
+      case 3: launch_yinv<N, T, 3>(g, A1, A2s, z0, nz, tw, act, ss); break;
+      case 4: launch_yinv<N, T, 4>(g, A1, A2s, z0, nz, tw, act, ss); break;
+      default: launch_yinv<N, T, 0>(g, A1, A2s, z0, nz, tw, act, ss);
     }
-    if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2s, A3s, nz, tw, ss);
-    else launch_xpass<N, T, 0>(g, A2s, A3s, nz, tw, ss);
+    if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2s, A3s, nz, tw, act, ss);
+    else launch_xpass<N, T, 0>(g, A2s, A3s, nz, tw, act, ss);
     switch (tv[3]) {
-      case 1: launch_yfwd<N, T, 1>(g, A3s, A4, z0, nz, tw, ss); break;
-      case 2: launch_yfwd<N, T, 2>(g, A3s, A4, z0, nz, tw, ss); break;
-      case 3: launch_yfwd<N, T, 3>(g, A3s, A4, z0, nz, tw, ss); break;
-      case 4: launch_yfwd<N, T, 4>(g, A3s, A4, z0, nz, tw, ss); break;
-      default: launch_yfwd<N, T, 0>(g, A3s, A4, z0, nz, tw, ss);
+      case 1: launch_yfwd<N, T, 1>(g, A3s, A4, z0, nz, tw, act, ss); break;
+      case 2: launch_yfwd<N, T, 2>(g, A3s, A4, z0, nz, tw, act, ss); break;
+      case 3: launch_yfwd<N, T, 3>(g, A3s, A4, z0, nz, tw, act, ss); break;
+      case 4: launch_yfwd<N, T, 4>(g, A3s, A4, z0, nz, tw, act, ss); break;
+      default: launch_yfwd<N, T, 0>(g, A3s, A4, z0, nz, tw, act, ss);
     }
   }
   if (two) {
@@ -634,11 +648,11 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
   NSK_MARK(PROF_P5, 0, st);
   float2* k32 = sizeof(T) == 4 ? p.k32 : nullptr;   // FP32 copies only of an FP32 right-hand side
   switch (tv[4]) {
-    case 1: launch_zfwd<N, T, 1, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
-    case 2: launch_zfwd<N, T, 2, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
-    case 3: launch_zfwd<N, T, 3, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
-    case 4: launch_zfwd<N, T, 4, UT>(g, A4, U, K, k32, p.nu, tw, st); break;
-    default: launch_zfwd<N, T, 0, UT>(g, A4, U, K, k32, p.nu, tw, st);
+    case 1: launch_zfwd<N, T, 1, UT>(g, A4, U, K, k32, p.nu, tw, act, st); break;
+    case 2: launch_zfwd<N, T, 2, UT>(g, A4, U, K, k32, p.nu, tw, act, st); break;
+    case 3: launch_zfwd<N, T, 3, UT>(g, A4, U, K, k32, p.nu, tw, act, st); break;
+    case 4: launch_zfwd<N, T, 4, UT>(g, A4, U, K, k32, p.nu, tw, act, st); break;
+    default: launch_zfwd<N, T, 0, UT>(g, A4, U, K, k32, p.nu, tw, act, st);
   }
   NSK_MARK(PROF_P5, 1, st);
   return hipGetLastError();

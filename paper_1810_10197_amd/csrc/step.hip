@@ -489,6 +489,61 @@ __global__ void k_scale_band(double2* __restrict__ u, const double* __restrict__
   *p = make_double2(p->x * a, p->y * a);
 }
 
+// Energy of the band 0 < |k|^2 <= kf2 per shell: one thread per member walks
+// the band's cube |k_j| <= kc in a fixed order (a few hundred modes), so the
+// sums are deterministic.  Shells as in k_reduce.
+template <int N>
+__global__ void k_band_bins(const double2* __restrict__ u, Geom g, double kf2, int kc, double* __restrict__ out) {
+  constexpr int K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1;
+  constexpr long long MRC = (long long)KX * KF * KF;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= g.batch) return;
+  double acc[NBINS];
+  for (int b = 0; b < NBINS; ++b) acc[b] = 0.0;
+  const long long base = (long long)m * g.epm;
+  const int kcc = kc < K ? kc : K;
+  for (int kz = -kcc; kz <= kcc; ++kz)
+    for (int ky = -kcc; ky <= kcc; ++ky)
+      for (int kx = 0; kx <= kcc; ++kx) {
+        const int k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 == 0 || (double)k2 > kf2) continue;
+        const long long q = ((long long)(kz >= 0 ? kz : kz + KF) * KF + (ky >= 0 ? ky : ky + KF)) * KX + kx;
+        const double w = kx == 0 ? 1.0 : 2.0;
+        double e = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          const double2 v = u[base + c * MRC + q];
+          e += 0.5 * w * (v.x * v.x + v.y * v.y);
+        }
+        int bin = (int)floor((16.0 * sqrt((double)k2)) / (double)(K > 0 ? K : 1));
+        bin = bin > NBINS - 1 ? NBINS - 1 : bin;
+        acc[bin] += e;
+      }
+  for (int b = 0; b < NBINS; ++b) out[m * NBINS + b] = acc[b];
+}
+
+hipError_t band_bins(const Geom& g, const double2* u, double kf2, double* out, hipStream_t st) {
+  const int kc = (int)floor(sqrt(kf2));
+  const dim3 grid((g.batch + 63) / 64), blk(64);
+  switch (g.n) {
+    case 8: hipLaunchKernelGGL(k_band_bins<8>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 16: hipLaunchKernelGGL(k_band_bins<16>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 24: hipLaunchKernelGGL(k_band_bins<24>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 32: hipLaunchKernelGGL(k_band_bins<32>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 48: hipLaunchKernelGGL(k_band_bins<48>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 64: hipLaunchKernelGGL(k_band_bins<64>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 96: hipLaunchKernelGGL(k_band_bins<96>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 128: hipLaunchKernelGGL(k_band_bins<128>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 192: hipLaunchKernelGGL(k_band_bins<192>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 256: hipLaunchKernelGGL(k_band_bins<256>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 384: hipLaunchKernelGGL(k_band_bins<384>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 512: hipLaunchKernelGGL(k_band_bins<512>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 768: hipLaunchKernelGGL(k_band_bins<768>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    case 1024: hipLaunchKernelGGL(k_band_bins<1024>, grid, blk, 0, st, u, g, kf2, kc, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t scale_band(const Geom& g, double2* u, const double* alpha, double kf2, hipStream_t st) {
   int kc = (int)floor(sqrt(kf2));
   if (kc > g.K) kc = g.K;

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from gpu_util import announce
-from oracle import control, diagnostics, mlp, spectral
+from oracle import control, diagnostics, forcing, mlp, spectral
 from paper_1810_10197_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -152,3 +152,94 @@ def test_pushed_rows_append_to_ring(ns):
     s.close()
     assert cnt == 42
     assert np.array_equal(x, np.concatenate([x1, x2])) and np.array_equal(y, np.concatenate([y1, y2]))
+
+
+M64 = (1 << 64) - 1
+
+
+def splitmix64(z):
+    """splitmix64 (Steele, Lea & Flood, OOPSLA 2014): the counter-based
+    generator of the device's minibatch rows, from its published definition."""
+    z = (z + 0x9E3779B97F4A7C15) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def test_fit_stats_and_train_match_oracle(ns):
+    """ns_mlp_fit_stats: mean and population standard deviation of the
+    recorded rows; ns_mlp_train: minibatches drawn by splitmix64(seed + it *
+    batch + sample) mod rows, each an MSE gradient and an Adam step, against
+    the FP64 oracle fed the same rows; then the loss over all rows falls."""
+    announce("mlp fit_stats + train")
+    rng = np.random.default_rng(9)
+    nrows, batch, iters, seed = 300, 32, 5, 77
+    x = (rng.standard_normal((nrows, 20)) * rng.uniform(0.2, 3.0, 20) + rng.standard_normal(20)).astype(np.float32)
+    y = (0.3 * np.tanh(x[:, 3]) - 0.2 * x[:, 17] / 3.0).astype(np.float32)
+    p, _, _ = weights(10)
+    s = ns.Solver(dim=3, n=8, nu=0.01, rhs_precision="fp32")
+    s.mlp_set_weights(packed(p, np.zeros(20), np.ones(20)))
+    s.mlp_push_rows(x, y)
+    s.mlp_fit_stats()
+    w = s.mlp_get_weights()
+    mean, scale = w[mlp.NPARAM:mlp.NPARAM + 20].astype(np.float64), w[mlp.NPARAM + 20:].astype(np.float64)
+    xd = x.astype(np.float64)
+    assert np.abs(mean - xd.mean(0)).max() <= 1e-6 * np.abs(xd).max()
+    assert np.abs(scale / xd.std(0) - 1).max() <= 1e-6
+    s.mlp_reset_optimizer()
+    s.mlp_train(iters, batch, 1e-3, seed)
+    got = s.mlp_get_weights()[:mlp.NPARAM].astype(np.float64)
+    z = (xd - mean) / scale
+    pref, m, v = w[:mlp.NPARAM].astype(np.float64), np.zeros(mlp.NPARAM), np.zeros(mlp.NPARAM)
+    for it in range(iters):
+        rows = [splitmix64(seed + it * batch + j) % nrows for j in range(batch)]
+        _, g = mlp.loss_and_grad(pref, z[rows], y[rows].astype(np.float64))
+        pref, m, v = mlp.adam_step(pref, g, m, v, it + 1, lr=1e-3)
+    assert np.abs(got - pref).max() <= 2e-5
+    loss0, _ = mlp.loss_and_grad(got, z, y.astype(np.float64))
+    s.mlp_train(300, batch, 1e-3, seed + 1)
+    loss1, _ = mlp.loss_and_grad(s.mlp_get_weights()[:mlp.NPARAM].astype(np.float64), z, y.astype(np.float64))
+    s.close()
+    print("full-data loss %.5f -> %.5f" % (loss0, loss1))
+    assert loss1 < 0.5 * loss0
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_mlp_controller_trained_like_weights_match_oracle(ns, forced):
+    """A network whose output depends on the features (random weights, bias
+    near log 1.3) inside the adaptive loop, against the oracle's controller
+    with the oracle's proposer on the oracle's features; with forcing
+    (Sec. 3.3.1) the proposer sees the forced state on both sides.  The
+    proposal goes through FP32 on the device, so step sizes agree to FP32
+    rounding: decisions equal, states within 1e-8."""
+    n, nu, kf = 16, 0.02, 2.0
+    announce("mlp controller, feature-dependent network, forced=%s" % forced)
+    p, mean, scale = weights(31)
+    p *= 0.5
+    mlp.unpack(p)["b3"][...] = math.log(1.3)
+    w = packed(p, mean * 0.0 - 2.0, scale + 1.0)
+    p64, mean64, scale64 = f64(w)
+    u0 = inputs.random_isotropic(n, 15)
+    e0 = diagnostics.energy(u0, 3)
+    rhs = lambda u: spectral.rhs_ns3d(u, nu)
+    ys = []
+
+    def prop(u, h, errs):
+        x = mlp.features(diagnostics.shells(u, 3), diagnostics.energy(u, 3), errs)
+        x = x.astype(np.float32).astype(np.float64)
+        y, _ = mlp.forward(p64, ((x - mean64) / scale64)[None])
+        ys.append(float(y[0]))
+        return float(np.float32(y[0]))
+    post = (lambda u: forcing.force(u, kf, e0)) if forced else None
+    ref = control.integrate(rhs, u0, 1.5, 1.0, 1e-10, 1e-10, proposer=prop, post_step=post)
+    kw = {"force_kf": kf, "force_e0": e0} if forced else {}
+    s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp64", **kw)
+    s.mlp_set_weights(w)
+    s.set_state(u0[None])
+    st = s.integrate(1.5, 1.0, 1e-10, 1e-10, controller="mlp")[0]
+    got = s.get_state().cpu().numpy()[0]
+    s.close()
+    print("oracle proposals", np.round(ys, 3), "accept/reject", ref["n_accept"], ref["n_reject"])
+    assert ref["n_reject"] >= 1 and len(set(np.round(ys, 4))) > 3   # the features matter
+    assert (st["n_accept"], st["n_reject"]) == (ref["n_accept"], ref["n_reject"])
+    assert np.abs(got - ref["u"]).max() <= 1e-8 * np.abs(ref["u"]).max()
