@@ -14,10 +14,15 @@ the 2D Boussinesq Rayleigh--Taylor problem at 1024^2.
 The dominant kernel's roofline figure divides its algorithmic bytes per launch
 (reads + writes of the pruned pass model in pass_bytes) by its average launch
 duration, from HIP events recorded around every launch on the launch's stream
-in a second run of the same steps (the events themselves cost about a tenth of
-the step time, so the timed region that gives value runs without them).  The
-CPU baseline times the FP64 NumPy oracle's right-hand side at the same size on
-the host, on a bounded sample.
+in a separate run of the same steps (the events themselves cost about a tenth
+of the step time, so the timed region that gives value runs without them; a
+second events run brackets the y/x/y phase as a whole for the right-hand
+side's wall time).  The CPU baseline times the FP64 NumPy oracle's
+right-hand side at the same size on the host, on a bounded sample, and the
+oracle's time to solution of the 32^3 Taylor-Green runs.  The default
+workload also reports the time to a 1e-6 relative energy error at T = 10
+(FP64 RK4 against BS5 with an FP32 right-hand side, with and without the
+trained proposer; about a minute, --no-tts skips it).
 """
 import argparse
 import json
@@ -90,11 +95,75 @@ def pass_bytes_2d(n, fp64=False):
     return {"zinv": 3 * mr * 16 + col, "xpass": 2 * col, "zfwd": col + 2 * 3 * mr * 16}
 
 
+def host_cpu():
+    """CPU model name and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "logical_cpus": os.cpu_count()}
+
+
+def c1_oracle_time_to_solution():
+    """The oracle on the 32^3 Taylor-Green vortex (nu = 1/1600) to T = 1:
+    RK4 at dt = 0.01 and BS5 with the Sec. 2.2.1 controller at
+    atol = rtol = 1e-8 (h0 = 0.01); wall time and right-hand sides."""
+    from oracle import control, spectral
+    from paper_1810_10197_amd import inputs
+    n, nu = 32, 1.0 / 1600
+    u0 = inputs.tgv3d(n)
+    rhs = lambda u: spectral.rhs_ns3d(u, nu)
+    t0 = time.perf_counter()
+    _, steps = control.rk4_fixed(rhs, u0, 1.0, 0.01)
+    rk4 = {"wall_s": time.perf_counter() - t0, "n_rhs": 4 * steps}
+    t0 = time.perf_counter()
+    ref = control.integrate(rhs, u0, 1.0, 0.01, 1e-8, 1e-8)
+    bs5 = {"wall_s": time.perf_counter() - t0, "n_rhs": ref["n_rhs"], "n_accept": ref["n_accept"],
+           "n_reject": ref["n_reject"]}
+    return {"rk4_dt0.01": rk4, "bs5_tol1e-8": bs5}
+
+
+def c1_gpu_time_to_solution(ns, inputs):
+    """The same two C1 runs on the GPU (FP64 right-hand side and state)."""
+    import torch
+    n, nu = 32, 1.0 / 1600
+    u0 = inputs.tgv3d(n)[None]
+    s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp64")
+    s.set_state(u0)
+    s.step_rk4(0.01)                          # first-launch costs outside the timing
+    s.set_state(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        s.step_rk4(0.01)
+    torch.cuda.synchronize()
+    rk4 = {"wall_s": time.perf_counter() - t0, "n_rhs": 400}
+    s.set_state(u0)
+    s.set_time(0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.integrate(1.0, 0.01, 1e-8, 1e-8)[0]
+    torch.cuda.synchronize()
+    bs5 = {"wall_s": time.perf_counter() - t0, "n_rhs": st["n_rhs"], "n_accept": st["n_accept"],
+           "n_reject": st["n_reject"]}
+    s.close()
+    return {"rk4_dt0.01": rk4, "bs5_tol1e-8": bs5}
+
+
 def cpu_baseline(n, nu, budget_s, padded=False):
     """Oracle RHS/s on the host: repeat the FP64 NumPy right-hand side (2/3
     rule, or padded: 3/2 rule) until the time budget is used (at least one
-    evaluation)."""
-    import numpy as np
+    evaluation); and the oracle's time to solution of the 32^3 Taylor-Green
+    runs (RK4 at dt = 0.01 and adaptive BS5 at 1e-8, to T = 1)."""
     from oracle import spectral
     from paper_1810_10197_amd import inputs
     u = inputs.tgv3d(n)
@@ -109,8 +178,10 @@ def cpu_baseline(n, nu, budget_s, padded=False):
     dt = time.perf_counter() - t0
     return {"value": count / dt, "unit": "RHS evals/s", "cores": 1, "kind": "oracle",
             "sample": "%d FP64 NumPy right-hand sides (%s rule) of the %d^3 Taylor-Green field "
-                      "(%.1f s; numpy.fft is single-threaded)"
-                      % (count, "3/2" if padded else "2/3", n, dt)}
+                      "(%.1f s; numpy.fft is single-threaded, so one core)"
+                      % (count, "3/2" if padded else "2/3", n, dt),
+            "host": host_cpu(),
+            "c1_time_to_solution": c1_oracle_time_to_solution()}
 
 
 def quadratic_interpolant(tref, yref):
@@ -536,6 +607,110 @@ def study_problem(args):
     print(json.dumps(out))
 
 
+def rel_l2_fields(u, uref):
+    """Per-component relative L2 error of a device state (torch) against a
+    device reference."""
+    import torch
+    out = []
+    for c in range(u.shape[1]):
+        d = torch.linalg.vector_norm(u[:, c] - uref[:, c]).item()
+        r = torch.linalg.vector_norm(uref[:, c]).item()
+        out.append(d / max(r, 1e-300))
+    return out
+
+
+def time_to_solution(ns, inputs, n=256, T=10.0, target=1e-6):
+    """Metric 2 of the workload: wall time to a relative energy error of
+    `target` at T on the Taylor-Green vortex (nu = 1/1600).  Reference: FP64
+    RK4 at dt = 1e-3 (E_ref and the state).  Arms: FP64 RK4 at dt = 0.01 and
+    0.008; BS5 with an FP32 right-hand side (FP64 state) at tol 1e-10 with
+    the Sec. 2.2.1 controller and with the trained proposer; and the BS5 FP32
+    tolerance sweep 1e-4, 1e-6, 1e-8 with per-field errors against the FP64
+    reference.  Each run is timed from set-state to the final diagnostics."""
+    import numpy as np
+    import torch
+    nu = 1.0 / 1600
+    u0 = inputs.tgv3d(n)[None]
+    out = {"workload": "3D Taylor-Green vortex %d^3, nu=1/1600, T=%g" % (n, T), "target": target}
+
+    def rk4(dt, prec, keep=False):
+        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision=prec)
+        s.set_state(u0)
+        steps = max(1, int(math.ceil(T / dt - 1e-9)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s.step_rk4(dt if i < steps - 1 else T - (steps - 1) * dt)
+        e, _, _ = s.diagnostics()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        u = s.get_state() if keep else None
+        s.close()
+        return float(e[0]), wall, 4 * steps, u
+
+    t0 = time.perf_counter()
+    eref, wref, _, uref = rk4(1e-3, "fp64", keep=True)
+    out["E_ref"] = eref
+    out["reference"] = "FP64 RK4 dt=1e-3 (%.1f s)" % wref
+    log("tts: E_ref(T=%g) = %.15e (%.1f s)" % (T, eref, wref))
+    for dt in (0.01, 0.008):
+        e, wall, nr, _ = rk4(dt, "fp64")
+        out["rk4_fp64_dt%g" % dt] = {"rel_energy_err": abs(e - eref) / eref, "wall_s": wall, "n_rhs": nr}
+        log("tts: rk4 fp64 dt=%g err %.2e wall %.2f s" % (dt, abs(e - eref) / eref, wall))
+    w, info = train_proposer(ns, inputs, iters=3000, members=128,
+                             target=((64, 128), nu, T, (1e-7, 1e-8, 1e-9, 1e-10)))
+    out["proposer_training"] = {k: info[k] for k in ("rows", "train_iters", "train_s", "loss_first",
+                                                      "loss_last")}
+
+    def bs5(tol, ctl, budget_s=60.0, chunk=0.5):
+        # chunks of `chunk` time units, each continuing the controller of the
+        # previous one (a progress line between); a run whose steps collapse
+        # (the unstable loose tolerances of an FP32 right-hand side) is
+        # abandoned after budget_s and reported as such
+        s = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp32")
+        s.mlp_set_weights(w)
+        s.set_state(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, tot, ok = 1e-3, {"n_rhs": 0, "n_accept": 0, "n_reject": 0}, True
+        t_now = 0.0
+        try:
+            for c in range(int(math.ceil(T / chunk - 1e-12))):
+                st = s.integrate(min(T, (c + 1) * chunk), h, tol, tol, controller=ctl, resume=c > 0)[0]
+                h, t_now = st["h_next"], st["t"]
+                for k in tot:
+                    tot[k] += st[k]
+                log("tts: bs5 %s tol=%g t=%g rhs %d rej %d" % (ctl, tol, t_now, tot["n_rhs"], tot["n_reject"]))
+                if time.perf_counter() - t0 > budget_s and t_now < T:
+                    ok = False
+                    tot["abandoned"] = "after %.0f s at t = %g (step %.2e)" % (time.perf_counter() - t0, t_now, h)
+                    break
+        except ns.NsError as e:
+            ok = False
+            tot["failed"] = str(e)
+        e, _, _ = s.diagnostics()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        r = {"tol": tol, "wall_s": wall, **tot}
+        if ok:
+            r["rel_energy_err"] = abs(float(e[0]) - eref) / eref
+            r["per_field_rel_l2"] = rel_l2_fields(s.get_state(), uref)
+        s.close()
+        log("tts: bs5 %s tol=%g %s" % (ctl, tol, r))
+        return r
+
+    out["bs5_pi_fp32"] = bs5(1e-10, "pi")
+    out["bs5_mlp_fp32"] = bs5(1e-10, "mlp")
+    out["bs5_pi_fp32_rtol_sweep"] = [bs5(tol, "pi", budget_s=15.0) for tol in (1e-4, 1e-6, 1e-8)]
+    fp64 = out["rk4_fp64_dt0.008"]
+    best = out["bs5_mlp_fp32"]
+    if best.get("rel_energy_err", 1.0) <= target and fp64["rel_energy_err"] <= target:
+        out["speedup_bs5_mlp_over_rk4_fp64"] = fp64["wall_s"] / best["wall_s"]
+    out["total_s"] = time.perf_counter() - t0
+    del uref
+    return out
+
+
 def study_tts(args):
     """Wall time to a fixed relative energy error at T on the Taylor-Green
     vortex (nu = 1/1600): plain FP64 RK4 at fixed steps (the last one clipped
@@ -631,6 +806,8 @@ def main():
     ap.add_argument("--dt", type=float, default=0.005)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tts", action="store_true",
+                    help="skip the time-to-solution runs of the default workload (about a minute)")
     ap.add_argument("--variants", default=None,
                     help="comma-separated launch variants of the 5 passes and the slab (skips the autotuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -760,8 +937,8 @@ def bench_throughput(args):
         rejected += int(st == ns.NS_STEP_REJECTED)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # the same steps again with HIP events around every launch: per-kernel
-    # durations for the roofline
+    # the same steps again with HIP events around every launch (the y/x/y
+    # slab phase as one unit): per-pass durations for the right-hand side
     torch.cuda.synchronize()
     s.profile_start()
     t1 = time.perf_counter()
@@ -770,6 +947,17 @@ def bench_throughput(args):
     torch.cuda.synchronize()
     elapsed_ev = time.perf_counter() - t1
     prof = s.profile_stop()
+    # and once more with every y/x/y launch bracketed on its own stream: the
+    # duration of each kernel, for the dominant kernel's roofline
+    prof_fine = None
+    if dim == 3:
+        s.profile_mode(1)
+        s.profile_start()
+        for _ in range(args.steps):
+            s.step_bs5(h, atol, rtol)
+        torch.cuda.synchronize()
+        prof_fine = s.profile_stop()
+        s.profile_mode(0)
     s.close()
 
     rhs_evals = 7 * args.steps * batch
@@ -793,19 +981,28 @@ def bench_throughput(args):
     rhs_passes = [k for k in ["zinv", "yinv", "xpass", "yfwd", "zfwd"] if k in pb]
     if dim == 3:
         # wall time per evaluation: z passes plus the y/x/y slab phase (its
-        # passes may overlap on two streams, so the phase is timed as a unit
-        # and is the roofline's unit when it dominates)
+        # passes may overlap on two streams, so the phase is timed as a unit)
         slab_ms, slab_cnt = prof["slab"]
         slab_us = 1000.0 * slab_ms / max(slab_cnt, 1)
         ph_bytes = pb["yinv"] + pb["xpass"] + pb["yfwd"]
         per_kernel["yxy_phase"] = {"us_per_rhs": slab_us, "bytes_per_rhs": ph_bytes,
                                    "gbs": ph_bytes / (slab_us * 1e-6) / 1e9}
         rhs_ms = (per_kernel["zinv"]["us_per_rhs"] + slab_us + per_kernel["zfwd"]["us_per_rhs"]) / 1000.0
-        units = ["zinv", "yxy_phase", "zfwd"]
+        # single kernels from the run with every launch bracketed
+        for name in ["yinv", "xpass", "yfwd"]:
+            ms, cnt = prof_fine[name]
+            nr = prof_fine["zinv"][1]
+            if cnt and nr:
+                bpl = pb[name] * nr / cnt
+                per_kernel[name] = {"avg_us": 1000.0 * ms / cnt, "launches": cnt,
+                                    "us_per_rhs": 1000.0 * ms / nr, "bytes_per_launch": bpl,
+                                    "gbs": bpl / (ms / cnt * 1e-3) / 1e9,
+                                    "timing": "every launch bracketed on its stream"}
+        units = ["zinv", "yinv", "xpass", "yfwd", "zfwd"]
     else:
         rhs_ms = sum(per_kernel[k]["us_per_rhs"] for k in rhs_passes) / 1000.0
         units = rhs_passes
-    dom = max(units, key=lambda k: per_kernel[k]["us_per_rhs"])
+    dom = max([k for k in units if k in per_kernel], key=lambda k: per_kernel[k]["us_per_rhs"])
     achieved = per_kernel[dom]["gbs"]
     model_bytes = sum(pb.values())
     unit = "RHS evals/s" if batch == 1 else "member RHS evals/s"
@@ -844,6 +1041,9 @@ def bench_throughput(args):
     }
     if not args.no_cpu and wl == "tgv":
         out["cpu_baseline"] = cpu_baseline(n, nu, args.cpu_budget, padded)
+        out["c1_gpu_time_to_solution"] = c1_gpu_time_to_solution(ns, inputs)
+    if not args.no_tts and wl == "tgv" and n == 256 and not padded and not fp64:
+        out["time_to_solution"] = time_to_solution(ns, inputs)
     print(json.dumps(out))
 
 

@@ -292,6 +292,11 @@ typedef struct ns_kernel_times {
 } ns_kernel_times;
 int ns_profile_start(ns_solver* s);
 int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
+/* every_launch != 0: while profiling, also bracket each y-inverse, x-pass and
+ * y-forward launch on its own stream (indices 1..3; with the two-stream slab
+ * schedule a launch's time then includes what overlaps it on the other
+ * stream); 0 (the default): the y/x/y phase only (index 8). */
+int ns_profile_mode(ns_solver* s, int every_launch);
 
 /* Autotuner of the right-hand side.  3D: parameters 0-4 are launch variants of
  * the five passes (z-inverse, y-inverse, x-pass, y-forward, z-forward): radix

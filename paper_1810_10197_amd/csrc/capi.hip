@@ -1274,6 +1274,16 @@ int ns_profile_start(ns_solver* s) {
   return NS_OK;
 }
 
+int ns_profile_mode(ns_solver* s, int every_launch) {
+  if (!s) return NS_ERR_ARG;
+  s->rb.fine = every_launch ? 1 : 0;
+  if (s->gexec) {                              // captured without (or with) the extra events
+    (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+  }
+  return NS_OK;
+}
+
 int ns_profile_stop(ns_solver* s, ns_kernel_times* out) {
   if (!s || !out) return NS_ERR_ARG;
   s->prof_on = false;

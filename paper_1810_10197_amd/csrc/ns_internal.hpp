@@ -45,6 +45,7 @@ struct RhsBufs {
   int variant[6];     // launch variant of each 3D pass, then the slab schedule (the autotuner's choice)
   hipStream_t side;   // second stream of the two-stream slab schedule (default priority)
   hipEvent_t fork, join;   // order `side` after / before the solver's stream
+  int fine = 0;       // timing hook also around every y/x/y launch (on its own stream)
 };
 constexpr int NVARIANT_COL = 5, NVARIANT_ROW = 2, NVARIANT_SLAB = 13;
 // 3D slab schedule of the y/x/y passes, variant v: v < 5 one stream with

@@ -608,7 +608,8 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
   }
   NSK_MARK(PROF_P1, 1, st);
   // the slab phase is timed as a whole: its launches may overlap on two
-  // streams, and events between them would perturb it
+  // streams, and events between them would perturb it (with bufs.fine every
+  // launch is also bracketed, on its own stream)
   NSK_MARK(PROF_SLAB, 0, st);
   if (two) {
     hipError_t e = hipEventRecord(bufs.fork, st);
@@ -622,6 +623,7 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
     hipStream_t ss = b ? bufs.side : st;
     V* A2s = (V*)(base + sc.a2s[b]);
     V* A3s = (V*)(base + sc.a3s[b]);
+    if (bufs.fine) NSK_MARK(PROF_P2, 0, ss);
     switch (tv[1]) {
       case 1: launch_yinv<N, T, 1>(g, A1, A2s, z0, nz, tw, act, ss); break;
       case 2: launch_yinv<N, T, 2>(g, A1, A2s, z0, nz, tw, act, ss); break;
@@ -629,8 +631,16 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
       case 4: launch_yinv<N, T, 4>(g, A1, A2s, z0, nz, tw, act, ss); break;
       default: launch_yinv<N, T, 0>(g, A1, A2s, z0, nz, tw, act, ss);
     }
+    if (bufs.fine) {
+      NSK_MARK(PROF_P2, 1, ss);
+      NSK_MARK(PROF_P3, 0, ss);
+    }
     if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2s, A3s, nz, tw, act, ss);
     else launch_xpass<N, T, 0>(g, A2s, A3s, nz, tw, act, ss);
+    if (bufs.fine) {
+      NSK_MARK(PROF_P3, 1, ss);
+      NSK_MARK(PROF_P4, 0, ss);
+    }
     switch (tv[3]) {
       case 1: launch_yfwd<N, T, 1>(g, A3s, A4, z0, nz, tw, act, ss); break;
       case 2: launch_yfwd<N, T, 2>(g, A3s, A4, z0, nz, tw, act, ss); break;
@@ -638,6 +648,7 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
       case 4: launch_yfwd<N, T, 4>(g, A3s, A4, z0, nz, tw, act, ss); break;
       default: launch_yfwd<N, T, 0>(g, A3s, A4, z0, nz, tw, act, ss);
     }
+    if (bufs.fine) NSK_MARK(PROF_P4, 1, ss);
   }
   if (two) {
     hipError_t e = hipEventRecord(bufs.join, bufs.side);

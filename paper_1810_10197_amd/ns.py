@@ -48,7 +48,7 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
            "ns_mlp_fit_stats", "ns_checkpoint_bytes", "ns_checkpoint_save", "ns_checkpoint_load",
            "ns_save", "ns_load",
            "ns_mlp_train", "ns_autotune", "ns_tune_get", "ns_tune_set", "ns_profile_start",
-           "ns_profile_stop", "ns_strerror", "ns_free", "ns_rhs_static", "ns_rhs_static_bytes"]
+           "ns_profile_stop", "ns_strerror", "ns_free", "ns_rhs_static", "ns_rhs_static_bytes", "ns_profile_mode"]
 NS_NTUNE = 6
 NS_TUNE_MAXV = 13
 NS_DEALIAS = {"2/3": 0, "3/2": 1}
@@ -128,6 +128,7 @@ _sig = {
     "ns_free": (None, [_P]),
     "ns_rhs_static": (_I, [ctypes.POINTER(NsConfig), _DP, _P, _P, _P]),
     "ns_rhs_static_bytes": (ctypes.c_size_t, [ctypes.POINTER(NsConfig)]),
+    "ns_profile_mode": (_I, [_P, _I]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -300,6 +301,10 @@ def ns_tune_set(h, variants):
 
 def ns_profile_start(h):
     return _check(_lib.ns_profile_start(h), "ns_profile_start")
+
+
+def ns_profile_mode(h, every_launch):
+    return _check(_lib.ns_profile_mode(h, int(every_launch)), "ns_profile_mode")
 
 
 def ns_profile_stop(h, out):
@@ -516,6 +521,9 @@ class Solver:
 
     def profile_start(self):
         ns_profile_start(self.handle)
+
+    def profile_mode(self, every_launch):
+        ns_profile_mode(self.handle, every_launch)
 
     def profile_stop(self):
         """{kernel name: (total ms, launches)} since profile_start."""
