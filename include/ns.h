@@ -317,9 +317,12 @@ int ns_profile_mode(ns_solver* s, int every_launch);
  * parameter 0 is the y-inverse's and parameter 4 the y-forward's variant
  * (radix plan and column tile, 0-4; with the Boussinesq scalar, y-forward
  * variants 2 and 4 split the four fields over two blocks), timed per launch;
- * parameter 2 the layout the x-pass hands to the y-forward (0 row-major, 1
- * column-major), timed over the whole right-hand side; the other parameters
- * are accepted and ignored, as are all of them below 256 points. */
+ * parameter 2 the x-pass: bit 0 the layout it hands to the y-forward (0
+ * row-major, 1 column-major), 2 and 3 the same layouts with one row per
+ * block and one wavefront per transform (at 512, 1024 and the padded 1536
+ * points; elsewhere as 0 and 1), timed over the whole right-hand side; the
+ * other parameters are accepted and ignored, as are all of them below 256
+ * points. */
 #define NS_NTUNE 6
 #define NS_TUNE_MAXV 13
 int ns_autotune(ns_solver* s, int reps, double* ms_host);

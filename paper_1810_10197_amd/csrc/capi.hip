@@ -1166,14 +1166,15 @@ int ns_tune_get(ns_solver* s, int* v) {
   return NS_OK;
 }
 
-static int tune_nvariants(int p) {
-  return p == 2 ? nsk::NVARIANT_ROW : (p == 5 ? nsk::NVARIANT_SLAB : nsk::NVARIANT_COL);
+static int tune_nvariants(const ns_solver* s, int p) {
+  if (p == 2) return s->g.dim == 2 ? nsk::NVARIANT_ROW2D : nsk::NVARIANT_ROW;
+  return p == 5 ? nsk::NVARIANT_SLAB : nsk::NVARIANT_COL;
 }
 
 int ns_tune_set(ns_solver* s, const int* v) {
   if (!s || !v) return NS_ERR_ARG;
   for (int i = 0; i < NS_NTUNE; ++i)
-    if (v[i] < 0 || v[i] >= tune_nvariants(i)) return NS_ERR_ARG;
+    if (v[i] < 0 || v[i] >= tune_nvariants(s, i)) return NS_ERR_ARG;
   for (int i = 0; i < NS_NTUNE; ++i) s->rb.variant[i] = v[i];
   if (s->gexec) {                              // captured with the old launches
     (void)hipGraphExecDestroy(s->gexec);
@@ -1218,7 +1219,7 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
   const int nq = d3 ? NS_NTUNE : (s->g.n >= 256 ? 3 : 0);
   for (int q = 0; q < nq && !rc; ++q) {
     const int p = d3 ? order3[q] : order2[q];
-    const int nv = tune_nvariants(p);
+    const int nv = tune_nvariants(s, p);
     double best = 1e300;
     int best_v = s->rb.variant[p];
     for (int v = 0; v < nv && !rc; ++v) {

@@ -48,6 +48,7 @@ struct RhsBufs {
   int fine = 0;       // timing hook also around every y/x/y launch (on its own stream)
 };
 constexpr int NVARIANT_COL = 5, NVARIANT_ROW = 2, NVARIANT_SLAB = 13;
+constexpr int NVARIANT_ROW2D = 4;   // 2D x-pass slot: B2 layout x (row per wavefront | row split)
 // 3D slab schedule of the y/x/y passes, variant v: v < 5 one stream with
 // slabs of n >> v planes; 5 <= v < 9 slabs of n >> (v - 4) planes alternating
 // between two streams and two slab buffers, so that the passes of one slab

@@ -203,6 +203,100 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k2_xpass(const cplx<T>* _
   }
 }
 
+// Q2 with one row per block and one wavefront per transform: the inverse
+// transforms of (u + iv), omega and (Boussinesq) rho run side by side in NZ
+// wavefronts, the fields meet in LDS for the products, and the forward
+// transforms of (v omega - i u omega) and (rho u + i rho v) run side by side
+// in the first two.  A large single grid has too few rows to fill the GPU
+// with one wavefront per row; this gives NZ times the wavefronts.  Same
+// arithmetic per point as k2_xpass.
+template <class PL, typename T, bool SCALAR, bool COLB2>
+__global__ __launch_bounds__((SCALAR ? 3 : 2) * (PL::N / PL::E)) void k2_xpass_split(
+    const cplx<T>* __restrict__ B1, cplx<T>* __restrict__ B2, Geom g, long long nrows,
+    const cplx<T>* __restrict__ tw) {
+  constexpr int N = PL::N, E = PL::E, TT = N / E;
+  constexpr int NZ = SCALAR ? 3 : 2;
+  constexpr int LD = LdsLen<N, true>::value;
+  static_assert(TT == 64, "one wavefront per transform");
+  using V = cplx<T>;
+  __shared__ V lds[NZ * LD];
+  const int grp = threadIdx.x / TT, t = threadIdx.x - grp * TT;   // grp: wavefront = transform
+  const long long row = blockIdx.x;                                // uniform per block
+  if (row >= nrows) return;
+  const long long m = row / N, y = row - m * N;
+  const int K = g.K, Kx = g.Kx;
+  const T zero = (T)0;
+  const long long fs = (long long)N * Kx;
+  const V* base = B1 + (m * 4 * N + y) * Kx;
+  V* buf = lds + grp * LD;
+  // wavefront grp loads and inverts field pair 0 (u + iv), 1 (omega), 2 (rho)
+  V z[E];
+  {
+    const V* pa = base + (grp == 0 ? 0 : grp + 1) * fs;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int pos = in_pos<PL>(t, i);
+      const bool lo = pos <= K, hi = pos >= N - K;
+      const int k0 = lo ? pos : N - pos;
+      const int kk = k0 <= K ? k0 : K;
+      const T sg = lo ? (T)1 : (T)-1;
+      const V a = pa[kk];
+      const V b = grp == 0 ? pa[fs + kk] : mk<V>(zero, zero);
+      const T ay = kk == 0 ? zero : a.y, by = kk == 0 ? zero : b.y;
+      const V r = mk<V>(a.x - sg * by, sg * ay + b.x);
+      z[i] = (lo || hi) ? r : mk<V>(zero, zero);
+    }
+  }
+  fft_regs<PL, +1, V, true, true>(z, t, buf, tw);
+  // physical values by point: omega and rho (real parts) in buffer 1 as two
+  // arrays of N reals, (u, v) in buffer NZ - 1 (SCALAR) or 0
+  __syncthreads();
+  T* wr = reinterpret_cast<T*>(lds + LD);          // omega [N], rho [N]
+  V* uv = lds + (SCALAR ? 2 : 0) * LD;
+  static_assert(2 * N <= 2 * LD, "two real arrays fit one buffer");
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int pos = out_pos<PL>(t, i);
+    if (grp == 0) uv[pos] = z[i];
+    else if (grp == 1) wr[pos] = z[i].x;
+    else wr[N + pos] = z[i].x;
+  }
+  __syncthreads();
+  V pr[E];                                          // group 0: n, group 1: q (in_pos order)
+  if (grp < 2) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int pos = out_pos<PL>(t, i);
+      const V w2 = uv[pos];
+      const T u = w2.x, v = w2.y;
+      if (grp == 0) {
+        const T w = wr[pos];
+        pr[out_to_in<PL>(i)] = mk<V>(v * w, -(u * w));
+      } else {
+        const T r = SCALAR ? wr[N + pos] : zero;
+        pr[out_to_in<PL>(i)] = mk<V>(r * u, r * v);
+      }
+    }
+  }
+  __syncthreads();                                  // the exchange buffers are free again
+  if (grp >= (SCALAR ? 2 : 1)) return;              // uniform per wavefront; no block barrier follows
+  fft_regs<PL, -1, V, true, true>(pr, t, lds + grp * LD, tw);
+  const int partner = (TT - t) & (TT - 1);
+  V* out = COLB2 ? B2 + m * 4 * fs + y : B2 + (m * 4 * N + y) * Kx;
+  const long long ks = COLB2 ? N : 1;
+  V* o0 = out + (grp == 0 ? 0 : 2) * fs;            // (n_x, n_y) or (q_x, q_y)
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    V a, b;
+    split_pair<PL, V, T>(pr, i, t, partner, a, b);
+    const int pos = out_pos<PL>(t, i);
+    if (pos <= K) {
+      o0[pos * ks] = a;
+      o0[fs + pos * ks] = b;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- Q3
 // One block per tile of C columns kx; the NF transformed fields of a column
 // are transformed side by side by NF thread groups (so that a 1024-point
@@ -322,9 +416,10 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::
 // plan default tile, 4 narrow plan two columns; Q3 (slot 4) 0 up to eight
 // columns, 1 two, 2 one (Boussinesq: the fields split over two blocks, up to
 // eight columns), 3 narrow plan up to eight, 4 narrow plan one (Boussinesq:
-// split, up to eight); the layout of B2 (slot 2) 0 row-major, 1
-// column-major.  The x-pass keeps the wide plan (a row stays inside one
-// wavefront).
+// split, up to eight); slot 2: the layout of B2 (bit 0: 0 row-major, 1
+// column-major) and, from 2 on, the row-split x-pass (one wavefront per
+// transform; where a row's transform is one wavefront).  The x-pass keeps
+// the wide plan (a row stays inside one wavefront).
 template <int N, int V> struct Q1Var {
   using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
   static constexpr int CW = N < 256 ? 0 : (V == 1 ? 4 : (V == 2 || V == 4 ? 2 : 0));
@@ -378,7 +473,10 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   const int nfield = SCALAR ? 4 : 3;
   // variants only matter (and are only built) from 256 points on
   const int v1 = N >= 256 ? bufs.variant[0] : 0, v3 = N >= 256 ? bufs.variant[4] : 0;
-  const bool colb2 = N >= 256 && bufs.variant[2] == 1;
+  const bool colb2 = N >= 256 && (bufs.variant[2] & 1);
+  // the row-split x-pass (one wavefront per transform) where a row is one wavefront
+  constexpr bool can_split = N >= 256 && PL::N / PL::E == 64;
+  const bool split = can_split && bufs.variant[2] >= 2;
 #define NSK_MARK(id, ph) \
   if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, st)
   NSK_MARK(PROF_P1, 0);
@@ -392,12 +490,25 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   NSK_MARK(PROF_P1, 1);
   const long long rows = (long long)g.batch * N;
   NSK_MARK(PROF_P3, 0);
-  if (colb2)
-    hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR, N >= 256>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
-                       dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
-  else
-    hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR, false>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
-                       dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
+  if constexpr (can_split) {
+    if (split) {
+      constexpr int NT = (SCALAR ? 3 : 2) * 64;
+      if (colb2)
+        hipLaunchKernelGGL((k2_xpass_split<PL, T, SCALAR, true>), dim3((unsigned)rows), dim3(NT), 0, st, B1, B2, g,
+                           rows, tw);
+      else
+        hipLaunchKernelGGL((k2_xpass_split<PL, T, SCALAR, false>), dim3((unsigned)rows), dim3(NT), 0, st, B1, B2,
+                           g, rows, tw);
+    }
+  }
+  if (!split) {
+    if (colb2)
+      hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR, N >= 256>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
+                         dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
+    else
+      hipLaunchKernelGGL((k2_xpass<PL, T, SCALAR, false>), dim3((unsigned)((rows + RC::RPB - 1) / RC::RPB)),
+                         dim3(RC::NT), 0, st, B1, B2, g, rows, tw);
+  }
   NSK_MARK(PROF_P3, 1);
   NSK_MARK(PROF_P5, 0);
   if (colb2) launch_q3v<N, T, SCALAR, N >= 256>(v3, g, B2, U, K, p, tw, st);

@@ -66,7 +66,7 @@ def test_padded_rhs2d_every_launch_variant(ns, n, prec):
     st = band_field(n, 11 * n, 3)
     ref = spectral.rhs_ns2d_padded(st, nu, kappa, ri)
     s = solver(ns, n, prec, 1, nu, kappa, ri)
-    for v in range(10):
+    for v in range(20):                         # x-pass slot: layout bit, row split from 2 on
         s.tune([v % 5, 0, v // 5, 0, 4 - v % 5, 0])
         got = s.rhs(st[None]).cpu().numpy()[0]
         err = max(per_field_rel_l2(got, ref))
