@@ -164,19 +164,15 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
 // tile), remapped so that each XCD takes a contiguous range: neighbouring
 // tiles, whose output rows share cache lines at the tile edges, then write
 // through the same L2 (about 1% faster than the plain 2D grid at 256^3).
+// One block's work (logical block id L, LDS of C * (N + 1) values).
 template <class PL, typename T, int CW>
-__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
-                                                             cplx<T>* __restrict__ A2s, int z0, int zs,
-                                                             long long nblocks,
-                                                             const cplx<T>* __restrict__ tw,
-                                                             const int* __restrict__ active) {
+__device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<T>* __restrict__ A2s, int z0,
+                                           int zs, long long L, cplx<T>* lds, const cplx<T>* __restrict__ tw,
+                                           const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
-  __shared__ V lds[C * CF::LD];
-  const long long L = xcd_logical(blockIdx.x, gridDim.x);
-  if (L >= nblocks) return;                       // uniform per block
   const int ntx = (zs * KX + C - 1) / C;
   const long long bf = L / ntx;                   // member * 6 + field
   const int bx = (int)(L - bf * ntx);
@@ -219,6 +215,19 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
   }
 }
 
+template <class PL, typename T, int CW>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>* __restrict__ A1,
+                                                             cplx<T>* __restrict__ A2s, int z0, int zs,
+                                                             long long nblocks,
+                                                             const cplx<T>* __restrict__ tw,
+                                                             const int* __restrict__ active) {
+  using CF = ColCfg<PL, T, CW>;
+  __shared__ cplx<T> lds[CF::C * CF::LD];
+  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;                       // uniform per block
+  yinv_block<PL, T, CW>(A1, A2s, z0, zs, L, lds, tw, active);
+}
+
 // ---------------------------------------------------------------- P3
 // One group of N/E threads per (member, z, y) row, everything in registers:
 //  1. the three paired half spectra (u_x + i u_y), (u_z + i w_x), (w_y + i w_z)
@@ -231,21 +240,20 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yinv(const cplx<T>*
 //     forward pass's input positions);
 //  4. n_x, n_y are split from Z(k) and conj(Z(N-k)), the mirror value coming
 //     from the partner thread through a cross-lane shuffle; keep kx <= K.
-template <class PL, typename T>
-__global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2s,
-                                                              cplx<T>* __restrict__ A3s, int zs,
-                                                              const cplx<T>* __restrict__ tw,
-                                                              const int* __restrict__ active) {
+// One block's rows rb * RPB .. rb * RPB + RPB - 1 of member m (LDS of RPB
+// padded rows).
+template <class PL, typename T, int RPB>
+__device__ __forceinline__ void xpass_block(const cplx<T>* __restrict__ A2s, cplx<T>* __restrict__ A3s, int zs,
+                                            long long rb, long long m, cplx<T>* lds,
+                                            const cplx<T>* __restrict__ tw, const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KX = K + 1;
   using V = cplx<T>;
   using RC = RowCfg<PL, T>;
   constexpr int E = RC::E, TT = RC::TT;
-  __shared__ V lds[RC::RPB * RC::LD];
   const int grp = threadIdx.x / TT, t = threadIdx.x % TT;
   const long long RPM = (long long)zs * N;        // rows (zl, y) per member in the slab
-  const long long m = blockIdx.y;
   if (active && !active[m]) return;
-  const long long row = (long long)blockIdx.x * RC::RPB + grp;
+  const long long row = rb * RPB + grp;
   const bool valid = row < RPM;
   const long long rr = valid ? row : 0;
   const T zero = (T)0;
@@ -344,24 +352,29 @@ __global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __
   }
 }
 
+template <class PL, typename T>
+__global__ __launch_bounds__((RowCfg<PL, T>::NT)) void k_xpass(const cplx<T>* __restrict__ A2s,
+                                                              cplx<T>* __restrict__ A3s, int zs,
+                                                              const cplx<T>* __restrict__ tw,
+                                                              const int* __restrict__ active) {
+  using RC = RowCfg<PL, T>;
+  __shared__ cplx<T> lds[RC::RPB * RC::LD];
+  xpass_block<PL, T, RC::RPB>(A2s, A3s, zs, blockIdx.x, blockIdx.y, lds, tw, active);
+}
+
 // ---------------------------------------------------------------- P4
 // Columns (zl, kx) of one (member, component) in the slab: N values of y ->
 // 2K+1 retained ky, written to plane z0 + zl of A4 (blocks XCD-grouped as in
 // P2).
 template <class PL, typename T, int CW>
-__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3s,
-                                                             cplx<T>* __restrict__ A4, int z0, int zs,
-                                                             long long nblocks,
-                                                             const cplx<T>* __restrict__ tw,
-                                                             const int* __restrict__ active) {
+__device__ __forceinline__ void yfwd_block(const cplx<T>* __restrict__ A3s, cplx<T>* __restrict__ A4, int z0,
+                                           int zs, long long L, cplx<T>* lds, const cplx<T>* __restrict__ tw,
+                                           const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
-  __shared__ V lds[C * CF::LD];
   const int nkxs = zs * KX;                       // row length of the slab buffer
-  const long long L = xcd_logical(blockIdx.x, gridDim.x);
-  if (L >= nblocks) return;                       // uniform per block
   const int ntx = (nkxs + C - 1) / C;
   const long long bc = L / ntx;                   // member * 3 + component
   const int bx = (int)(L - bc * ntx);
@@ -399,6 +412,19 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>*
       }
     }
   }
+}
+
+template <class PL, typename T, int CW>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_yfwd(const cplx<T>* __restrict__ A3s,
+                                                             cplx<T>* __restrict__ A4, int z0, int zs,
+                                                             long long nblocks,
+                                                             const cplx<T>* __restrict__ tw,
+                                                             const int* __restrict__ active) {
+  using CF = ColCfg<PL, T, CW>;
+  __shared__ cplx<T> lds[CF::C * CF::LD];
+  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;                       // uniform per block
+  yfwd_block<PL, T, CW>(A3s, A4, z0, zs, L, lds, tw, active);
 }
 
 // ---------------------------------------------------------------- P5
