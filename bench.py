@@ -39,10 +39,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rhs256_fp32_hbm_traffic.txt")
 TRAFFIC_SOURCES = ["fft_core.hpp", "pass_common.hpp", "rhs3d_kernels.hpp", "rhs3d.hip"]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, launches_per_rhs=1.0):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE summary (copy-calibrated), or None when the kernel sources have
-    changed since the counters were taken."""
+    WRITE_SIZE summary (copy-calibrated bytes per right-hand side, divided by
+    this run's launches per right-hand side), or None when the kernel sources
+    have changed since the counters were taken."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -55,8 +56,8 @@ def measured_traffic(kernel):
         return None
     for l in text:
         parts = l.split()
-        if len(parts) == 3 and parts[0] == "traffic_bytes" and parts[1] == kernel:
-            return float(parts[2])
+        if len(parts) == 3 and parts[0] == "traffic_per_rhs" and parts[1] == kernel:
+            return float(parts[2]) / launches_per_rhs
     return None
 
 
@@ -1025,8 +1026,8 @@ def bench_throughput(args):
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom) if (wl == "tgv" and n == 256 and not fp64
-                                                          and not padded) else None,
+                     "traffic": measured_traffic(dom, per_kernel[dom].get("launches", n_rhs) / n_rhs)
+                     if (wl == "tgv" and n == 256 and not fp64 and not padded) else None,
                      "kernel": dom},
         "rhs_model_gb": model_bytes / 1e9,
         "rhs_passes_ms": rhs_ms,
