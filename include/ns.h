@@ -114,16 +114,23 @@ typedef struct ns_stats {
 /* Bytes of device workspace ns_init needs for cfg (0 if cfg is invalid). */
 size_t ns_workspace_bytes(const ns_config* cfg);
 
-/* Create a solver.  nu_host[batch]: viscosity (1/Re) per member.  workspace:
- * device buffer of at least ns_workspace_bytes(cfg) bytes, 256-byte aligned,
- * owned by the caller and kept until ns_free.  stream: hipStream_t or NULL.
- * On success *out receives the solver; the state is unset until
- * ns_set_state. */
+/* Create a solver for `batch` independent members of the problem of Sec. 2
+ * (the periodic box of Eq. (1), discretised as Eq. (2); in 2D, Sec. 3.2).
+ * nu_host[batch]: viscosity (1/Re, Sec. 2) per member.  workspace: device
+ * buffer of at least ns_workspace_bytes(cfg) bytes, 256-byte aligned, owned by
+ * the caller and kept until ns_free.  stream: hipStream_t or NULL.  On success
+ * *out receives the solver; the state is unset until ns_set_state.  Errors:
+ * NS_ERR_ARG (invalid cfg, null pointers, workspace too small or misaligned),
+ * NS_ERR_HIP. */
 int ns_init(const ns_config* cfg, const double* nu_host, void* workspace,
             size_t workspace_bytes, void* stream, ns_solver** out);
 
-/* Copy in / out the state (layout above).  set_state drops non-retained modes
- * and invalidates the cached first stage f(u_n). */
+/* Copy in / out the state u_hat of Eq. (2) (layout above; the transform of
+ * Sec. 2.1).  set_state drops non-retained modes, invalidates the cached first
+ * stage f(u_n) and leaves no controller to resume; it does not check that the
+ * field is divergence-free (the projection of every right-hand side keeps the
+ * divergence-free part's evolution exact).  Device buffers, may be freed after
+ * the call returns (the copy is ordered on the solver's stream). */
 int ns_set_state(ns_solver* s, const void* uhat);
 int ns_get_state(ns_solver* s, void* uhat);
 
@@ -246,6 +253,10 @@ int ns_refresh_rhs(ns_solver* s);
  * energies, then log10 of the last four accepted error estimates (oldest
  * first, padded with 1.0); normalised by the stored mean and scale.  Output:
  * y = log(h_next / h).  Weights live in the solver's workspace. */
+/* Copy the NS_MLP_NWEIGHTS weights in / out.  Host arrays: the weights are a
+ * 22 KB vector that callers keep in files and checkpoints, so the host is their
+ * natural home; the copy is synchronous and the library keeps its own device
+ * copy in the workspace. */
 int ns_mlp_set_weights(ns_solver* s, const float* w_host);   /* NS_MLP_NWEIGHTS */
 int ns_mlp_get_weights(ns_solver* s, float* w_host);
 /* y_dev[n] = network(x_dev[n][20]) for raw (unnormalised) feature rows. */
@@ -273,7 +284,9 @@ int ns_mlp_push_rows(ns_solver* s, const float* x_host, const float* y_host, int
 int ns_mlp_fit_stats(ns_solver* s);
 /* iters Adam steps on minibatches of `batch` recorded rows drawn with
  * splitmix64(seed + iteration * batch + sample); loss_host (may be NULL)
- * receives the last minibatch loss. */
+ * receives the last minibatch loss.  The seed is this library's addition to
+ * the training call: with it a run's minibatches are reproducible and a test
+ * can replay them on the host. */
 int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long long seed,
                  float* loss_host);
 
@@ -332,7 +345,9 @@ int ns_tune_set(ns_solver* s, const int* variant_host);
 /* Static description of a status code. */
 const char* ns_strerror(int status);
 
-/* Release the solver's host-side bookkeeping (caller memory is untouched). */
+/* Release the solver (no passage of the paper: resource bookkeeping).  Frees
+ * its streams, events, graph and the small pinned host buffer ns_integrate
+ * reads the done flags through; caller memory is untouched.  NULL is a no-op. */
 void ns_free(ns_solver* s);
 
 #ifdef __cplusplus

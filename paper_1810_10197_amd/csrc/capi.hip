@@ -220,6 +220,10 @@ struct ns_solver {
   // captured attempt graph of ns_integrate and the parameters it bakes in
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_st = nullptr;   // private stream: graphs cannot be captured on the null stream
+  // ns_integrate's read-back of the done flags: pinned [2][batch] and one event
+  // per slot, made on its first call and kept until ns_free
+  int* done_pinned = nullptr;
+  hipEvent_t done_ev[2] = {nullptr, nullptr};
   double g_atol = -1, g_rtol = -1, g_tend = 0;
   int g_ctrl = -1, g_collect = -1, g_method = -1;
   // kernel timing (ns_profile_start/stop)
@@ -773,16 +777,13 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
   // on the null stream), ordered after and before the caller's stream.
   if (!s->cap_st) NS_HIP(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
   hipStream_t user_st = s->st;
-  hipEvent_t ev[2];
-  if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return NS_ERR_HIP;
-  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
-    (void)hipEventDestroy(ev[0]);
-    return NS_ERR_HIP;
-  }
-  int* done_pinned = nullptr;
+  for (hipEvent_t& e : s->done_ev)
+    if (!e) NS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (!s->done_pinned) NS_HIP(hipHostMalloc((void**)&s->done_pinned, sizeof(int) * 2 * (size_t)B, 0));
+  hipEvent_t* ev = s->done_ev;
+  int* done_pinned = s->done_pinned;
   int status = NS_OK;
-  if (hipEventRecord(ev[0], user_st) != hipSuccess || hipStreamWaitEvent(s->cap_st, ev[0], 0) != hipSuccess ||
-      hipHostMalloc((void**)&done_pinned, sizeof(int) * 2 * (size_t)B, 0) != hipSuccess)
+  if (hipEventRecord(ev[0], user_st) != hipSuccess || hipStreamWaitEvent(s->cap_st, ev[0], 0) != hipSuccess)
     status = NS_ERR_HIP;
   s->st = s->cap_st;
   if (!status && use_graph) {
@@ -848,9 +849,6 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
   }
   (void)hipStreamSynchronize(s->st);
   s->st = user_st;
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
-  if (done_pinned) (void)hipHostFree(done_pinned);
   if (status) return status;
   s->k1_valid = true;
   s->ctl_warm = true;
@@ -1331,6 +1329,9 @@ void ns_free(ns_solver* s) {
   if (!s) return;
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
   if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
+  for (hipEvent_t e : s->done_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->done_pinned) (void)hipHostFree(s->done_pinned);
   if (s->rb.side) (void)hipStreamDestroy(s->rb.side);
   if (s->rb.fork) (void)hipEventDestroy(s->rb.fork);
   if (s->rb.join) (void)hipEventDestroy(s->rb.join);

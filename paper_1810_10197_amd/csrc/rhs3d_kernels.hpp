@@ -26,7 +26,8 @@
 // complex), chosen so that every column pass tiles a contiguous run of
 // columns:
 //   A1  [m][6][ky'][z][kx]   written by P1, read by P2 (columns (z, kx))
-//   A2s [m][6][zl][y][kx]    slab: written by P2, read by P3 (rows (zl, y))
+//   A2s [m][6][y][zl][kx]    slab: written by P2 (whole y rows of the slab),
+//                            read by P3 (rows (y, zl), y-major)
 //   A3s [m][3][y][zl][kx]    slab: written by P3, read by P4 (columns (zl, kx))
 //   A4  [m][3][z][ky'][kx]   written by P4, read by P5 (columns (ky', kx)); the
 //                            z-row pitch is padded to a multiple of 32 values so
@@ -207,11 +208,11 @@ __device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<
   }
   fft_regs<PL, +1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
-    const int zl = cz / KX, kx = cz - zl * KX;
+    const int nkxs = zs * KX;                     // one y row of the slab: every (zl, kx)
     V* out = A2s + bf * zs * NKX;
-    const unsigned lo = (unsigned)(zl * NKX + t * KX + kx) * (unsigned)sizeof(V);
+    const unsigned lo = (unsigned)(cz + t * nkxs) * (unsigned)sizeof(V);
 #pragma unroll
-    for (int i = 0; i < E; ++i) *byte_at(out + out_base<PL>(i) * KX, lo) = v[i];
+    for (int i = 0; i < E; ++i) *byte_at(out + (long long)out_base<PL>(i) * nkxs, lo) = v[i];
   }
 }
 
@@ -251,7 +252,7 @@ __device__ __forceinline__ void xpass_block(const cplx<T>* __restrict__ A2s, cpl
   using RC = RowCfg<PL, T>;
   constexpr int E = RC::E, TT = RC::TT;
   const int grp = threadIdx.x / TT, t = threadIdx.x % TT;
-  const long long RPM = (long long)zs * N;        // rows (zl, y) per member in the slab
+  const long long RPM = (long long)zs * N;        // rows (y, zl) per member in the slab, y-major
   if (active && !active[m]) return;
   const long long row = rb * RPB + grp;
   const bool valid = row < RPM;
@@ -329,7 +330,7 @@ __device__ __forceinline__ void xpass_block(const cplx<T>* __restrict__ A2s, cpl
   fft_regs<PL, -1, V, true, true>(nz, t, buf, w);
 
   const int partner = (TT - t) & (TT - 1);
-  V* out = A3s + ((m * 3) * N + (rr % N)) * (long long)zs * KX + (rr / N) * (long long)KX + t;
+  V* out = A3s + (m * 3 * RPM + rr) * KX + t;
   const long long CST = RPM * KX;
   const T half = (T)0.5;
 #pragma unroll
