@@ -15,6 +15,19 @@ constexpr int floor_pow2(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p
 // default of >= 16 columns and >= 256 threads), N/E threads per column.  A
 // request of 64 columns may use up to 160 KB of LDS (one block per CU): the
 // longer contiguous runs per row can outweigh the lower block count.
+// LDS stride of one column's transform buffer in a column pass.  A wavefront
+// holds C columns (lane % C) of 64 / C transform threads each (lane / C), and
+// the transforms' exchanges step through a buffer in units of one element per
+// thread.  With 16 or more columns the columns alone fill the 16 lanes that
+// share an LDS cycle, and a stride of N + 1 spreads them over the banks.  With
+// fewer columns, a group of 16 lanes spans 16 / C consecutive threads of each
+// column: a stride congruent to 16 / C modulo 32 elements puts the columns
+// 16 / C elements apart, so that the threads' unit offsets fill the gaps
+// instead of landing on the next column's banks.
+__host__ __device__ constexpr int col_ld(int n, int c) {
+  return c >= 16 ? n + 1 : n + ((16 / c - n) % 32 + 32) % 32;
+}
+
 template <class PL, typename T, int CW = 0> struct ColCfg {
   using V = cplx<T>;
   static constexpr int N = PL::N;
@@ -24,7 +37,7 @@ template <class PL, typename T, int CW = 0> struct ColCfg {
   static constexpr int C = floor_pow2(cmin(CW > 0 ? CW : cmax(256 / TT, 16),
                                            cmin(1024 / TT, LDS_BUDGET / ((N + 1) * (int)sizeof(V)))));
   static constexpr int NT = C * TT;
-  static constexpr int LD = N + 1;      // padded LDS stride per column
+  static constexpr int LD = col_ld(N, C);
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD

@@ -306,16 +306,16 @@ __global__ __launch_bounds__((SCALAR ? 3 : 2) * (PL::N / PL::E)) void k2_xpass_s
 template <class PL, typename T, int NF, int CMAX = 8> struct Q3Cfg {
   static constexpr int N = PL::N;
   static constexpr int TT = N / PL::E;
-  static constexpr int LD = N + 1;
   static constexpr int LDS_BUDGET = 160 * 1024;
-  static constexpr int C =
-      cmax(1, cmin(cmin(1024 / (TT * NF), CMAX), floor_pow2(LDS_BUDGET / (NF * LD * (int)sizeof(cplx<T>)))));
+  static constexpr int C = cmax(
+      1, cmin(cmin(1024 / (TT * NF), CMAX), floor_pow2(LDS_BUDGET / (NF * (N + 32) * (int)sizeof(cplx<T>)))));
+  static constexpr int LD = col_ld(N, C);
   static constexpr int NT = C * TT * NF;
 };
 
 // With SPLIT (Boussinesq only) a block takes two of the four fields: group 0
 // the velocity pair (n_x, n_y) and its projection, group 1 the density flux
-// (q_x, q_y) and its divergence; blockIdx.y = 2 member + group.  Half the
+// (q_x, q_y) and its divergence; the logical block row is 2 member + group.  Half the
 // fields per block leaves room for twice the columns per tile.
 template <bool SCALAR, bool SPLIT> struct Q3Fields {
   static constexpr int NF = SCALAR ? 4 : 2;
@@ -325,7 +325,7 @@ template <bool SCALAR, bool SPLIT> struct Q3Fields {
 template <class PL, typename T, bool SCALAR, int CMAX, bool COLB2, bool SPLIT>
 __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::NT)) void k2_yfwd(
     const cplx<T>* __restrict__ B2, const double2* __restrict__ U, double2* __restrict__ Kout, Geom g,
-    const double* __restrict__ nu, double ri, double kappa, const cplx<T>* __restrict__ tw) {
+    const double* __restrict__ nu, double ri, double kappa, const cplx<T>* __restrict__ tw, long long nblocks) {
   constexpr int N = PL::N;
   constexpr int NFB = Q3Fields<SCALAR, SPLIT>::NFB;
   constexpr bool SP = SCALAR && SPLIT;
@@ -333,16 +333,23 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::
   using QC = Q3Cfg<PL, T, NFB, CMAX>;
   constexpr int E = PL::E, C = QC::C, TT = QC::TT, LD = QC::LD;
   __shared__ V lds[NFB * C * LD];
+  // logical block: tile + ntiles * (member, group); XCD-grouped so that the
+  // neighbouring tiles, which share cache lines of B2 and of the state, run on
+  // one XCD (one L2)
+  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;                      // uniform per block
+  const int ntiles = (g.Kx + C - 1) / C;
+  const int bxt = (int)(L % ntiles), byt = (int)(L / ntiles);
   const int f = threadIdx.x / (C * TT);
   const int rem = threadIdx.x - f * (C * TT);
   // transform phase: lanes along the column when it is contiguous (COLB2),
   // else across the tile's columns
   const int lc = COLB2 ? rem / TT : rem % C, t = COLB2 ? rem % TT : rem / C;
-  const int grp = SP ? (int)(blockIdx.y & 1) : 0;
-  const int m = SP ? (int)(blockIdx.y >> 1) : (int)blockIdx.y;
+  const int grp = SP ? (byt & 1) : 0;
+  const int m = SP ? (byt >> 1) : byt;
   const int fg = grp * 2 + f;                    // field of B2 this thread group transforms
   {
-    const int kxt = blockIdx.x * C + lc;
+    const int kxt = bxt * C + lc;
     const bool vt = kxt < g.Kx;
     V* buf = lds + (f * C + lc) * LD;
     V o[E];
@@ -359,7 +366,7 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::
   }
   // epilogue: lanes across the tile's columns (adjacent kx of the state)
   const int elc = rem % C, et = rem / C;
-  const int kx = blockIdx.x * C + elc;
+  const int kx = bxt * C + elc;
   if (kx >= g.Kx) return;
   const double scale = 1.0 / ((double)N * (double)N);
   const double num = nu[m];
@@ -445,9 +452,10 @@ static void launch_q3(const Geom& g, const cplx<T>* B2, const double2* U, double
                       const cplx<T>* tw, hipStream_t st) {
   using QV = Q3Var<N, VAR, SCALAR>;
   using QC = Q3Cfg<typename QV::PL, T, Q3Fields<SCALAR, QV::SPLIT>::NFB, QV::CMAX>;
-  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX, COLB2, QV::SPLIT>),
-                     dim3((g.Kx + QC::C - 1) / QC::C, g.batch * (QV::SPLIT ? 2 : 1)), dim3(QC::NT), 0, st, B2,
-                     U, K, g, p.nu, p.ri, p.kappa, tw);
+  const long long nb = (long long)((g.Kx + QC::C - 1) / QC::C) * g.batch * (QV::SPLIT ? 2 : 1);
+  const long long nbp = (nb + 7) / 8 * 8;
+  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX, COLB2, QV::SPLIT>), dim3((unsigned)nbp),
+                     dim3(QC::NT), 0, st, B2, U, K, g, p.nu, p.ri, p.kappa, tw, nb);
 }
 template <int N, typename T, bool SCALAR, bool COLB2>
 static void launch_q3v(int v3, const Geom& g, const cplx<T>* B2, const double2* U, double2* K,
