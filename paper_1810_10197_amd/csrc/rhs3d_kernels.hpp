@@ -436,7 +436,8 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
                                                            float2* __restrict__ K32,
                                                            const double* __restrict__ nu,
                                                            const cplx<T>* __restrict__ tw,
-                                                           const int* __restrict__ active) {
+                                                           const int* __restrict__ active,
+                                                           long long nblocks) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
   constexpr int NCOLP = (NCOL + 31) / 32 * 32;      // line-aligned z-row pitch of A4
   constexpr long long MR = (long long)NCOL * KF;
@@ -444,9 +445,14 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
+  // logical block = (member, column tile), XCD-grouped: neighbouring tiles
+  // share the cache lines at their edges in the compact u_hat and f rows
+  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L >= nblocks) return;                     // uniform per block
+  constexpr int ntiles = (NCOL + C - 1) / C;
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int col = blockIdx.x * C + lc;
-  const int m = blockIdx.y;
+  const int col = (int)(L % ntiles) * C + lc;
+  const int m = (int)(L / ntiles);
   if (active && !active[m]) return;
   const bool valid = col < NCOL;
   const int colc = valid ? col : 0;
@@ -585,8 +591,10 @@ static void launch_zfwd(const Geom& g, const cplx<T>* A4, const UT* U, double2* 
   using CV = ColVar<N, V == 4 ? 1 : V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
   const int ncol = g.Kf * g.Kx;
-  hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW, UT>), dim3((ncol + CF::C - 1) / CF::C, g.batch),
-                     dim3(CF::NT), 0, st, A4, U, K, K32, nu, tw, act);
+  const long long nb = (long long)((ncol + CF::C - 1) / CF::C) * g.batch;
+  const long long nbp = (nb + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_zfwd<typename CV::PL, T, CV::CW, UT>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, A4, U,
+                     K, K32, nu, tw, act, nb);
 }
 
 // Scratch regions of one evaluation (T complex), each 256-byte aligned: A1,
