@@ -212,7 +212,7 @@ __device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<
     V* out = A2s + bf * zs * NKX;
     const unsigned lo = (unsigned)(cz + t * nkxs) * (unsigned)sizeof(V);
 #pragma unroll
-    for (int i = 0; i < E; ++i) *byte_at(out + (long long)out_base<PL>(i) * nkxs, lo) = v[i];
+    for (int i = 0; i < E; ++i) st_out<N>(byte_at(out + (long long)out_base<PL>(i) * nkxs, lo), v[i]);
   }
 }
 
@@ -512,9 +512,9 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
       f1 = make_double2(n1x - ky * px - vk * u1.x, n1y - ky * py - vk * u1.y);
       f2 = make_double2(n2x - kz * px - vk * u2.x, n2y - kz * py - vk * u2.y);
     }
-    *byte_at(kp, off) = f0;
-    *byte_at(kp + MR, off) = f1;
-    *byte_at(kp + 2 * MR, off) = f2;
+    st_out<N>(byte_at(kp, off), f0);
+    st_out<N>(byte_at(kp + MR, off), f1);
+    st_out<N>(byte_at(kp + 2 * MR, off), f2);
     if (K32m) {
       float2* kq = K32m + rowb * NCOL;
       *byte_at(kq, off / 2u) = make_float2((float)f0.x, (float)f0.y);
