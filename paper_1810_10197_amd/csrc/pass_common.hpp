@@ -105,6 +105,21 @@ template <int N, typename V> __device__ __forceinline__ void st_out(V* p, V v) {
   else *p = v;
 }
 
+// Load with the nontemporal hint, for the y-inverse's input (the z-inverse's
+// output, read exactly once): y/x/y phase 1-3% faster at 256^3, 5% at 512^3.
+// On the x-pass's, the y-forward's and the z-forward's inputs it made the
+// phase slower or left it as it was.
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v x = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(x.x, x.y);
+}
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const d2v x = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return make_double2(x.x, x.y);
+}
+
 // Pointer plus a 32-bit byte offset: with a block-uniform base this maps to
 // loads and stores that take the base in scalar registers and only the
 // offset per lane.

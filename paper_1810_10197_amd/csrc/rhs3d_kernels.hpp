@@ -195,14 +195,14 @@ __device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<
     if (bd == BAND_GAP) {
       v[i] = zero;
     } else if (bd == BAND_LO) {
-      v[i] = *byte_at(in + (long long)c * NKX, lane);
+      v[i] = ld_nt(byte_at(in + (long long)c * NKX, lane));
     } else if (bd == BAND_HI) {
-      v[i] = *byte_at(in + (long long)(c - N + KF) * NKX, lane);
+      v[i] = ld_nt(byte_at(in + (long long)(c - N + KF) * NKX, lane));
     } else {
       const int e = c + t;
       const bool ret = (e <= K) || (e >= N - K);
       const int kyp = e <= K ? e : (ret ? e - N + KF : 0);
-      const V x = *byte_at(in, (unsigned)(czc + kyp * NKX) * (unsigned)sizeof(V));
+      const V x = ld_nt(byte_at(in, (unsigned)(czc + kyp * NKX) * (unsigned)sizeof(V)));
       v[i] = ret ? x : zero;
     }
   }
