@@ -296,20 +296,25 @@ int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long lon
  * y-inverse, x-pass, y-forward, z-forward; in 3D the y/x/y launches are not
  * timed one by one), 5 stage combinations, 6 reductions, 7 other, 8 the
  * whole y/x/y slab phase of a 3D evaluation (wall time on the solver's
- * stream; its launches may overlap on two streams).  stop synchronises and fills total milliseconds and launch counts
- * per index. */
-#define NS_NPROF 9
+ * stream; its launches may overlap on two streams), 9 whole right-hand-side
+ * evaluations (mode 2 only).  stop synchronises and fills total milliseconds
+ * and launch counts per index. */
+#define NS_NPROF 10
 typedef struct ns_kernel_times {
   double ms[NS_NPROF];
   long long count[NS_NPROF];
 } ns_kernel_times;
 int ns_profile_start(ns_solver* s);
 int ns_profile_stop(ns_solver* s, ns_kernel_times* out_host);
-/* every_launch != 0: while profiling, also bracket each y-inverse, x-pass and
- * y-forward launch on its own stream (indices 1..3; with the two-stream slab
+/* What profiling brackets.  mode 0 (the default): the passes, with the 3D
+ * y/x/y phase as one unit (index 8).  1: also each y-inverse, x-pass and
+ * y-forward launch, on its own stream (indices 1..3; with the two-stream slab
  * schedule a launch's time then includes what overlaps it on the other
- * stream); 0 (the default): the y/x/y phase only (index 8). */
-int ns_profile_mode(ns_solver* s, int every_launch);
+ * stream).  2: only each whole right-hand-side evaluation, first pass start to
+ * last pass end (index 9), so that the evaluation runs with two events instead
+ * of one pair per pass; combinations and reductions keep their brackets.
+ * Other values: NS_ERR_ARG. */
+int ns_profile_mode(ns_solver* s, int mode);
 
 /* Autotuner of the right-hand side.  3D: parameters 0-4 are launch variants of
  * the five passes (z-inverse, y-inverse, x-pass, y-forward, z-forward): radix

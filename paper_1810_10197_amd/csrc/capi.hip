@@ -1207,6 +1207,8 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
     NS_HIP(nsk::fill(s->h_d, 0.0, s->g.batch, s->st));
     NS_HIP(nsk::combine2(s->g, s->u, c, s->h_d, nullptr, s->U32, nullptr, s->st));
   }
+  const int was_mode = s->rb.fine;
+  s->rb.fine = 0;                              // the trials are timed by pass
   // 3D: the slab first (it changes what the passes read from), then every
   // pass; 2D: the layout between the x-pass and Q3 (slot 2, timed over the
   // whole right-hand side), then the two column passes (Q1 in slot 0, Q3 in
@@ -1251,6 +1253,7 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
     }
     s->rb.variant[p] = best_v;
   }
+  s->rb.fine = was_mode;
   if (was_on) (void)ns_profile_start(s);
   if (s->gexec) {
     (void)hipGraphExecDestroy(s->gexec);
@@ -1273,15 +1276,17 @@ int ns_profile_start(ns_solver* s) {
   return NS_OK;
 }
 
-int ns_profile_mode(ns_solver* s, int every_launch) {
-  if (!s) return NS_ERR_ARG;
-  s->rb.fine = every_launch ? 1 : 0;
+int ns_profile_mode(ns_solver* s, int mode) {
+  if (!s || mode < 0 || mode > 2) return NS_ERR_ARG;
+  s->rb.fine = mode;
   if (s->gexec) {                              // captured without (or with) the extra events
     (void)hipGraphExecDestroy(s->gexec);
     s->gexec = nullptr;
   }
   return NS_OK;
 }
+
+static_assert(nsk::NPROF == NS_NPROF, "timing indices of the C ABI and of the kernels");
 
 int ns_profile_stop(ns_solver* s, ns_kernel_times* out) {
   if (!s || !out) return NS_ERR_ARG;

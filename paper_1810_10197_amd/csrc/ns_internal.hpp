@@ -34,7 +34,7 @@ struct RhsParams {
 // 1 after, on the stream of the launch; id is one of the PROF_* values
 // (PROF_SLAB brackets the whole y/x/y slab phase on the solver's stream).
 typedef void (*HookFn)(void* ctx, int id, int phase, hipStream_t st);
-enum { PROF_P1 = 0, PROF_P2, PROF_P3, PROF_P4, PROF_P5, PROF_COMBINE, PROF_REDUCE, PROF_OTHER, PROF_SLAB, NPROF };
+enum { PROF_P1 = 0, PROF_P2, PROF_P3, PROF_P4, PROF_P5, PROF_COMBINE, PROF_REDUCE, PROF_OTHER, PROF_SLAB, PROF_RHS, NPROF };
 
 // Scratch for one RHS evaluation (rhs precision T).
 struct RhsBufs {
@@ -45,7 +45,8 @@ struct RhsBufs {
   int variant[6];     // launch variant of each 3D pass, then the slab schedule (the autotuner's choice)
   hipStream_t side;   // second stream of the two-stream slab schedule (default priority)
   hipEvent_t fork, join;   // order `side` after / before the solver's stream
-  int fine = 0;       // timing hook also around every y/x/y launch (on its own stream)
+  int fine = 0;       // timing brackets: 0 passes, 1 also every y/x/y launch (on its
+                      // own stream), 2 whole evaluations only (PROF_RHS)
 };
 constexpr int NVARIANT_COL = 5, NVARIANT_ROW = 2, NVARIANT_SLAB = 13;
 constexpr int NVARIANT_ROW2D = 4;   // 2D x-pass slot: B2 layout x (row per wavefront | row split)

@@ -486,7 +486,8 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   constexpr bool can_split = N >= 256 && PL::N / PL::E == 64;
   const bool split = can_split && bufs.variant[2] >= 2;
 #define NSK_MARK(id, ph) \
-  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, st)
+  if (bufs.hook && bufs.fine != 2) bufs.hook(bufs.hook_ctx, id, ph, st)
+  if (bufs.hook && bufs.fine == 2) bufs.hook(bufs.hook_ctx, PROF_RHS, 0, st);
   NSK_MARK(PROF_P1, 0);
   switch (v1) {
     case 1: launch_q1<N, T, N >= 256 ? 1 : 0>(g, U, B1, nfield, tw, st); break;
@@ -522,6 +523,7 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   if (colb2) launch_q3v<N, T, SCALAR, N >= 256>(v3, g, B2, U, K, p, tw, st);
   else launch_q3v<N, T, SCALAR, false>(v3, g, B2, U, K, p, tw, st);
   NSK_MARK(PROF_P5, 1);
+  if (bufs.hook && bufs.fine == 2) bufs.hook(bufs.hook_ctx, PROF_RHS, 1, st);
 #undef NSK_MARK
   return hipGetLastError();
 }

@@ -536,7 +536,9 @@ template <int N, int V> struct ColVar {
 };
 
 #define NSK_MARK(id, ph, stream) \
-  if (bufs.hook) bufs.hook(bufs.hook_ctx, id, ph, stream)
+  if (bufs.hook && bufs.fine != 2) bufs.hook(bufs.hook_ctx, id, ph, stream)
+#define NSK_MARK_RHS(ph) \
+  if (bufs.hook && bufs.fine == 2) bufs.hook(bufs.hook_ctx, PROF_RHS, ph, st)
 
 template <int N, typename T, int V, typename UT>
 static void launch_zinv(const Geom& g, const UT* U, cplx<T>* A1, const cplx<T>* tw, const int* act,
@@ -633,6 +635,7 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
   const int* act = p.active;                       // members to evaluate (null: all)
   const bool two = slab_two_streams(tv[5]) && bufs.side && N >= 2;
   const int zs = slab_planes(g, tv[5]);
+  NSK_MARK_RHS(0);
   NSK_MARK(PROF_P1, 0, st);
   switch (tv[0]) {
     case 1: launch_zinv<N, T, 1, UT>(g, U, A1, tw, act, st); break;
@@ -658,7 +661,7 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
     hipStream_t ss = b ? bufs.side : st;
     V* A2s = (V*)(base + sc.a2s[b]);
     V* A3s = (V*)(base + sc.a3s[b]);
-    if (bufs.fine) NSK_MARK(PROF_P2, 0, ss);
+    if (bufs.fine == 1) NSK_MARK(PROF_P2, 0, ss);
     switch (tv[1]) {
       case 1: launch_yinv<N, T, 1>(g, A1, A2s, z0, nz, tw, act, ss); break;
       case 2: launch_yinv<N, T, 2>(g, A1, A2s, z0, nz, tw, act, ss); break;
@@ -666,13 +669,13 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
       case 4: launch_yinv<N, T, 4>(g, A1, A2s, z0, nz, tw, act, ss); break;
       default: launch_yinv<N, T, 0>(g, A1, A2s, z0, nz, tw, act, ss);
     }
-    if (bufs.fine) {
+    if (bufs.fine == 1) {
       NSK_MARK(PROF_P2, 1, ss);
       NSK_MARK(PROF_P3, 0, ss);
     }
     if (tv[2] == 1) launch_xpass<N, T, 1>(g, A2s, A3s, nz, tw, act, ss);
     else launch_xpass<N, T, 0>(g, A2s, A3s, nz, tw, act, ss);
-    if (bufs.fine) {
+    if (bufs.fine == 1) {
       NSK_MARK(PROF_P3, 1, ss);
       NSK_MARK(PROF_P4, 0, ss);
     }
@@ -683,7 +686,7 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
       case 4: launch_yfwd<N, T, 4>(g, A3s, A4, z0, nz, tw, act, ss); break;
       default: launch_yfwd<N, T, 0>(g, A3s, A4, z0, nz, tw, act, ss);
     }
-    if (bufs.fine) NSK_MARK(PROF_P4, 1, ss);
+    if (bufs.fine == 1) NSK_MARK(PROF_P4, 1, ss);
   }
   if (two) {
     hipError_t e = hipEventRecord(bufs.join, bufs.side);
@@ -701,8 +704,10 @@ static hipError_t run3d(const Geom& g, const UT* U, double2* K, const RhsParams&
     default: launch_zfwd<N, T, 0, UT>(g, A4, U, K, k32, p.nu, tw, act, st);
   }
   NSK_MARK(PROF_P5, 1, st);
+  NSK_MARK_RHS(1);
   return hipGetLastError();
 }
 #undef NSK_MARK
+#undef NSK_MARK_RHS
 
 }  // namespace nsk

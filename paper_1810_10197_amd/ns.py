@@ -52,7 +52,7 @@ EXPORTS = ["ns_workspace_bytes", "ns_init", "ns_set_state", "ns_get_state", "ns_
 NS_NTUNE = 6
 NS_TUNE_MAXV = 13
 NS_DEALIAS = {"2/3": 0, "3/2": 1}
-PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other", "slab"]
+PROF_NAMES = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "combine", "reduce", "other", "slab", "rhs"]
 
 
 class NsConfig(ctypes.Structure):
@@ -72,7 +72,7 @@ class NsStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-NS_NPROF = 9
+NS_NPROF = 10
 
 
 class NsKernelTimes(ctypes.Structure):
@@ -303,8 +303,8 @@ def ns_profile_start(h):
     return _check(_lib.ns_profile_start(h), "ns_profile_start")
 
 
-def ns_profile_mode(h, every_launch):
-    return _check(_lib.ns_profile_mode(h, int(every_launch)), "ns_profile_mode")
+def ns_profile_mode(h, mode):
+    return _check(_lib.ns_profile_mode(h, int(mode)), "ns_profile_mode")
 
 
 def ns_profile_stop(h, out):
@@ -522,8 +522,9 @@ class Solver:
     def profile_start(self):
         ns_profile_start(self.handle)
 
-    def profile_mode(self, every_launch):
-        ns_profile_mode(self.handle, every_launch)
+    def profile_mode(self, mode):
+        """0 passes, 1 also every y/x/y launch, 2 whole evaluations only."""
+        ns_profile_mode(self.handle, mode)
 
     def profile_stop(self):
         """{kernel name: (total ms, launches)} since profile_start."""
