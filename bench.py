@@ -61,6 +61,10 @@ def measured_traffic(kernel, launches_per_rhs=1.0):
     return None
 
 
+# slab schedule variants that alternate two streams -> the same slab size on one stream
+ONE_STREAM_SLAB = {5: 1, 6: 2, 7: 3, 8: 4, 11: 9, 12: 10}
+
+
 def pass_bytes(n, fp64=False, stage32=False):
     """Algorithmic HBM bytes of each right-hand-side pass per evaluation (one
     member): reads + writes of the retained-mode pencil model.  cb = bytes per
@@ -950,8 +954,14 @@ def bench_throughput(args):
     prof = s.profile_stop()
     # and once more with every y/x/y launch bracketed on its own stream: the
     # duration of each kernel, for the dominant kernel's roofline
+    # (with a two-stream slab schedule the launches of one stream overlap those
+    # of the other and their brackets would hold both; this run then takes the
+    # same slab size on one stream, which runs the same kernels one at a time)
     prof_fine = None
+    fine_variants = list(tune_variants)
     if dim == 3:
+        fine_variants[5] = ONE_STREAM_SLAB.get(fine_variants[5], fine_variants[5])
+        s.tune(fine_variants)
         s.profile_mode(1)
         s.profile_start()
         for _ in range(args.steps):
@@ -959,6 +969,7 @@ def bench_throughput(args):
         torch.cuda.synchronize()
         prof_fine = s.profile_stop()
         s.profile_mode(0)
+        s.tune(list(tune_variants))
     # and once more with one event pair around each whole right-hand side (no
     # events between its passes): the evaluation's wall time
     s.profile_mode(2)
@@ -1007,7 +1018,10 @@ def bench_throughput(args):
                 per_kernel[name] = {"avg_us": 1000.0 * ms / cnt, "launches": cnt,
                                     "us_per_rhs": 1000.0 * ms / nr, "bytes_per_launch": bpl,
                                     "gbs": bpl / (ms / cnt * 1e-3) / 1e9,
-                                    "timing": "every launch bracketed on its stream"}
+                                    "timing": "every launch bracketed on its stream"
+                                    + ("" if fine_variants == list(tune_variants) else
+                                       ", the slab schedule's launches on one stream (variants %s)"
+                                       % ",".join(map(str, fine_variants)))}
         units = ["zinv", "yinv", "xpass", "yfwd", "zfwd"]
     else:
         phase_sum_ms = sum(per_kernel[k]["us_per_rhs"] for k in rhs_passes) / 1000.0

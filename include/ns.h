@@ -328,9 +328,13 @@ int ns_profile_mode(ns_solver* s, int mode);
  * the finer slabs n >> 5 and n >> 6.  ns_autotune times every variant of every
  * parameter on the current state (reps evaluations each, HIP events: the z
  * passes per launch, the y/x/y passes and the slab schedule by the wall time
- * of the y/x/y phase per evaluation) and keeps the fastest; ms_host
- * (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL) receives the average
- * milliseconds (0 for variants a parameter lacks).  tune_get /
+ * of the y/x/y phase per evaluation) and keeps the fastest; then, for each
+ * parameter with several variants within 3% of its fastest, it times those on
+ * whole evaluations (2 x reps each, one event pair per evaluation) and keeps the
+ * fastest of them, since a pass's variant also changes what the caches hold
+ * for its neighbours.  ms_host (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL)
+ * receives the per-parameter averages of the first round in milliseconds (0
+ * for variants a parameter lacks).  tune_get /
  * tune_set read or restore the choice (e.g. from a cache).  2D (n >= 256):
  * parameter 0 is the y-inverse's and parameter 4 the y-forward's variant
  * (radix plan and column tile, 0-4; with the Boussinesq scalar, y-forward

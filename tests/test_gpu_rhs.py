@@ -199,7 +199,8 @@ def test_every_launch_variant_matches_oracle(ns, n):
         check_faces(got, ref, n, 10 * tol)
     s.set_state(u[None])
     variants, ms = s.autotune(reps=2)
-    assert all(ms[p][variants[p]] == min(x for x in ms[p] if x > 0) for p in range(6))
+    # per pass the fastest variant, or one within 3% of it that won on whole evaluations
+    assert all(ms[p][variants[p]] <= 1.03 * min(x for x in ms[p] if x > 0) for p in range(6))
     got = s.rhs(u[None]).cpu().numpy()[0]
     assert max(per_field_rel_l2(got, ref)) <= tol
     s.close()

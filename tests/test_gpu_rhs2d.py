@@ -130,9 +130,10 @@ def test_rhs2d_every_launch_variant(ns, n, scalar, prec):
         assert err <= tol, (v, err)
     s.set_state(u[None])
     variants, ms = s.autotune(reps=2)
-    assert ms[0][variants[0]] == min(x for x in ms[0][:5] if x > 0)
-    assert ms[2][variants[2]] == min(x for x in ms[2][:4] if x > 0)
-    assert ms[4][variants[4]] == min(x for x in ms[4][:5] if x > 0)
+    # per slot the fastest variant, or one within 3% of it that won on whole evaluations
+    assert ms[0][variants[0]] <= 1.03 * min(x for x in ms[0][:5] if x > 0)
+    assert ms[2][variants[2]] <= 1.03 * min(x for x in ms[2][:4] if x > 0)
+    assert ms[4][variants[4]] <= 1.03 * min(x for x in ms[4][:5] if x > 0)
     got = s.rhs(u[None]).cpu().numpy()[0]
     assert max(per_field_rel_l2(got, ref)) <= tol
     s.close()
