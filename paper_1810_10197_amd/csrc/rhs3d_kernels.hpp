@@ -445,9 +445,13 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zfwd(const cplx<T>*
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
   __shared__ V lds[C * CF::LD];
-  // logical block = (member, column tile), XCD-grouped: neighbouring tiles
-  // share the cache lines at their edges in the compact u_hat and f rows
-  const long long L = xcd_logical(blockIdx.x, gridDim.x);
+  // logical block = (member, column tile), XCD-grouped on the power-of-two
+  // grids: neighbouring tiles share the cache lines at their edges in the
+  // compact u_hat and f rows (256^3: u_hat reads 1.18x -> 1.01x of the model;
+  // 512^3: 821 -> 639 us).  On the zero-padded 3 * 2^k grids the grouping made
+  // the pass slower (384: 231 -> 300 us), and tiles keep the launch order.
+  constexpr bool GROUP = (N & (N - 1)) == 0;
+  const long long L = GROUP ? xcd_logical(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
   if (L >= nblocks) return;                     // uniform per block
   constexpr int ntiles = (NCOL + C - 1) / C;
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
