@@ -25,7 +25,8 @@
 // three passes instead of going to HBM and back.  Intermediate layouts (T
 // complex), chosen so that every column pass tiles a contiguous run of
 // columns:
-//   A1  [m][6][ky'][z][kx]   written by P1, read by P2 (columns (z, kx))
+//   A1  [m][6][ky'][z][kx]   written by P1, read by P2 (columns (z, kx)); rows of
+//                            a1_pitch(n) values (K + 1, padded from n = 512 on)
 //   A2s [m][6][y][zl][kx]    slab: written by P2 (whole y rows of the slab),
 //                            read by P3 (rows (y, zl), y-major)
 //   A3s [m][3][y][zl][kx]    slab: written by P3, read by P4 (columns (zl, kx))
@@ -46,6 +47,18 @@ static_assert(TWN == TWN_TABLE, "twiddle table length");
 // neither loaded nor stored, and those that always hold band elements need no
 // per-lane test.  Addresses are a block-uniform base plus a 32-bit per-lane
 // byte offset; what a register adds on top is uniform again.
+
+// Row pitch of A1 (values per (ky', z) row): K + 1, padded to a multiple of
+// 16 on the power-of-two grids from 512 on.  There A1 (1.4 GB at 512^3) is far
+// larger than the memory-side cache, and P1's column tiles write 128-byte
+// chunks into rows of 1,368 bytes: every chunk straddles two lines and the
+// writes ran at 2.6 TB/s; in rows of 176 values, with the pad columns written
+// as zeros, the same writes run at 5.4 TB/s.  Below 512 the rows stay K + 1
+// (at 256^3 A1 fits the cache and padding gained nothing there), and the
+// padded 3 * 2^k grids have K + 1 = 2^k already.
+__host__ __device__ constexpr int a1_pitch(int n) {
+  return (n >= 512 && (n & (n - 1)) == 0) ? ((n - 1) / 3 + 1 + 15) / 16 * 16 : (n - 1) / 3 + 1;
+}
 
 // ---------------------------------------------------------------- P1
 // Column loads of P1 from the compact FP64 state: component pa (and pb for
@@ -104,6 +117,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
                                                              const cplx<T>* __restrict__ tw,
                                                              const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NCOL = KF * KX;
+  constexpr int KXA = a1_pitch(N), NCOLA = KF * KXA;   // A1's columns (ky', kx), padded rows
   constexpr long long MR = (long long)NCOL * KF;
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
@@ -111,18 +125,20 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
   __shared__ V lds[C * CF::LD];
   const long long L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nblocks) return;                     // uniform per block
-  constexpr int ntiles = (NCOL + C - 1) / C;
+  constexpr int ntiles = (NCOLA + C - 1) / C;
   const int f = (int)(L % 6);
   const long long q = L / 6;
   const int tile = (int)(q % ntiles);
   const int m = (int)(q / ntiles);
   if (active && !active[m]) return;             // member not evaluated (uniform per block)
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int col = tile * C + lc;
-  const bool valid = col < NCOL;
+  const int col = tile * C + lc;                // column of A1: ky' * KXA + kx
+  const bool valid = col < NCOLA;
   const int colc = valid ? col : 0;
-  const int kyp = colc / KX;
-  const int kx = colc - kyp * KX;
+  const int kyp = colc / KXA;
+  const int kx = colc - kyp * KXA;
+  const bool real = kx < KX;                    // pad columns transform zeros and write them
+  const int colu = real ? kyp * KX + kx : 0;    // the column in the compact state
   const int ky = kyp <= K ? kyp : kyp - KF;
   Tw<PL, V> w;
   tw_load<PL>(w, t, tw);
@@ -130,11 +146,11 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
   const int ca = f < 3 ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
   const int cb = f == 3 ? 1 : (f == 4 ? 2 : 0);
   const UT* Um = U + (long long)m * 3 * MR;
-  const unsigned lane = (unsigned)(colc + t * NCOL) * (unsigned)sizeof(UT);
+  const unsigned lane = (unsigned)(colu + t * NCOL) * (unsigned)sizeof(UT);
   double2 a[E], b[E];
   int kzs[E];
-  if (f < 3) zinv_loads<PL, false, UT>(Um + ca * MR, Um, lane, colc, t, a, b, kzs);
-  else zinv_loads<PL, true, UT>(Um + ca * MR, Um + cb * MR, lane, colc, t, a, b, kzs);
+  if (f < 3) zinv_loads<PL, false, UT>(Um + ca * MR, Um, lane, colu, t, a, b, kzs);
+  else zinv_loads<PL, true, UT>(Um + ca * MR, Um + cb * MR, lane, colu, t, a, b, kzs);
   V v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -148,14 +164,14 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
       const double wr = ka * a[i].x - kb * b[i].x, wi = ka * a[i].y - kb * b[i].y;
       vx = -wi; vy = wr;
     }
-    v[i] = mk<V>((T)vx, (T)vy);
+    v[i] = real ? mk<V>((T)vx, (T)vy) : mk<V>((T)0, (T)0);
   }
   fft_regs<PL, +1>(v, t, lds + lc * CF::LD, w);
   if (valid) {
-    V* out = A1 + (long long)(m * 6 + f) * KF * N * KX;
-    const unsigned lo = (unsigned)((kyp * N + t) * KX + kx) * (unsigned)sizeof(V);
+    V* out = A1 + (long long)(m * 6 + f) * KF * N * KXA;
+    const unsigned lo = (unsigned)((kyp * N + t) * KXA + kx) * (unsigned)sizeof(V);
 #pragma unroll
-    for (int i = 0; i < E; ++i) *byte_at(out + out_base<PL>(i) * KX, lo) = v[i];
+    for (int i = 0; i < E; ++i) *byte_at(out + out_base<PL>(i) * KXA, lo) = v[i];
   }
 }
 
@@ -171,21 +187,24 @@ __device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<
                                            int zs, long long L, cplx<T>* lds, const cplx<T>* __restrict__ tw,
                                            const int* __restrict__ active) {
   constexpr int N = PL::N, K = (N - 1) / 3, KF = 2 * K + 1, KX = K + 1, NKX = N * KX;
+  constexpr int KXA = a1_pitch(N), NKXA = N * KXA;  // A1's padded rows
   using V = cplx<T>;
   using CF = ColCfg<PL, T, CW>;
   constexpr int E = CF::E, C = CF::C, TT = CF::TT;
-  const int ntx = (zs * KX + C - 1) / C;
+  const int ntx = (zs * KXA + C - 1) / C;
   const long long bf = L / ntx;                   // member * 6 + field
   const int bx = (int)(L - bf * ntx);
   if (active && !active[bf / 6]) return;
   const int lc = threadIdx.x % C, t = threadIdx.x / C;
-  const int cz = bx * C + lc;                     // slab column zl * KX + kx
-  const bool valid = cz < zs * KX;
-  const int czc = valid ? cz : 0;
+  const int cz = bx * C + lc;                     // slab column of A1: zl * KXA + kx
+  const bool inb = cz < zs * KXA;
+  const int czc = inb ? cz : 0;
+  const int zl = czc / KXA, kx = czc - zl * KXA;
+  const bool valid = inb && kx < KX;              // pad columns are read (zeros), not written
   Tw<PL, V> w;
   tw_load<PL>(w, t, tw);
-  const V* in = A1 + bf * KF * NKX + z0 * KX;
-  const unsigned lane = (unsigned)(czc + t * NKX) * (unsigned)sizeof(V);
+  const V* in = A1 + bf * KF * NKXA + z0 * KXA;
+  const unsigned lane = (unsigned)(czc + t * NKXA) * (unsigned)sizeof(V);
   V v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -195,14 +214,14 @@ __device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<
     if (bd == BAND_GAP) {
       v[i] = zero;
     } else if (bd == BAND_LO) {
-      v[i] = ld_nt(byte_at(in + (long long)c * NKX, lane));
+      v[i] = ld_nt(byte_at(in + (long long)c * NKXA, lane));
     } else if (bd == BAND_HI) {
-      v[i] = ld_nt(byte_at(in + (long long)(c - N + KF) * NKX, lane));
+      v[i] = ld_nt(byte_at(in + (long long)(c - N + KF) * NKXA, lane));
     } else {
       const int e = c + t;
       const bool ret = (e <= K) || (e >= N - K);
       const int kyp = e <= K ? e : (ret ? e - N + KF : 0);
-      const V x = ld_nt(byte_at(in, (unsigned)(czc + kyp * NKX) * (unsigned)sizeof(V)));
+      const V x = ld_nt(byte_at(in, (unsigned)(czc + kyp * NKXA) * (unsigned)sizeof(V)));
       v[i] = ret ? x : zero;
     }
   }
@@ -210,7 +229,7 @@ __device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<
   if (valid) {
     const int nkxs = zs * KX;                     // one y row of the slab: every (zl, kx)
     V* out = A2s + bf * zs * NKX;
-    const unsigned lo = (unsigned)(cz + t * nkxs) * (unsigned)sizeof(V);
+    const unsigned lo = (unsigned)(zl * KX + kx + t * nkxs) * (unsigned)sizeof(V);
 #pragma unroll
     for (int i = 0; i < E; ++i) st_out<N>(byte_at(out + (long long)out_base<PL>(i) * nkxs, lo), v[i]);
   }
@@ -549,7 +568,7 @@ static void launch_zinv(const Geom& g, const UT* U, cplx<T>* A1, const cplx<T>* 
                         hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
-  const int ncol = g.Kf * g.Kx;
+  const int ncol = g.Kf * a1_pitch(N);
   const long long nb = (long long)g.batch * 6 * ((ncol + CF::C - 1) / CF::C);
   const long long nbp = (nb + 7) / 8 * 8;
   hipLaunchKernelGGL((k_zinv<typename CV::PL, T, CV::CW, UT>), dim3((unsigned)nbp), dim3(CF::NT), 0, st, U, A1,
@@ -560,7 +579,7 @@ static void launch_yinv(const Geom& g, const cplx<T>* A1, cplx<T>* A2s, int z0, 
                         const int* act, hipStream_t st) {
   using CV = ColVar<N, V>;
   using CF = ColCfg<typename CV::PL, T, CV::CW>;
-  const int ncol = zs * g.Kx;
+  const int ncol = zs * a1_pitch(N);
   const int ntx = (ncol + CF::C - 1) / CF::C;
   const long long nb = (long long)ntx * g.batch * 6;
   const dim3 grid((unsigned)((nb + 7) / 8 * 8));
@@ -616,7 +635,7 @@ inline Scratch3d scratch3d(const Geom& g, int fp64) {
   const size_t p2 = B * 6 * n * g.Kx * cb, p3 = B * 3 * n * g.Kx * cb;   // per z plane
   Scratch3d s;
   s.a1 = 0;
-  s.a4 = al256(B * 6 * n * plane * cb);
+  s.a4 = al256(B * 6 * n * (size_t)g.Kf * a1_pitch(g.n) * cb);   // A1 with its padded rows
   const size_t planep = (plane + 31) / 32 * 32;       // A4's padded z-row pitch
   s.a2s[0] = s.a4 + al256(B * 3 * n * planep * cb);
   s.a3s[0] = s.a2s[0] + al256(p2 * n);
