@@ -137,7 +137,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k_zinv(const UT* __re
   const int colc = valid ? col : 0;
   const int kyp = colc / KXA;
   const int kx = colc - kyp * KXA;
-  const bool real = kx < KX;                    // pad columns transform zeros and write them
+  const bool real = KXA == KX || kx < KX;       // pad columns transform zeros and write them
   const int colu = real ? kyp * KX + kx : 0;    // the column in the compact state
   const int ky = kyp <= K ? kyp : kyp - KF;
   Tw<PL, V> w;
@@ -200,7 +200,7 @@ __device__ __forceinline__ void yinv_block(const cplx<T>* __restrict__ A1, cplx<
   const bool inb = cz < zs * KXA;
   const int czc = inb ? cz : 0;
   const int zl = czc / KXA, kx = czc - zl * KXA;
-  const bool valid = inb && kx < KX;              // pad columns are read (zeros), not written
+  const bool valid = inb && (KXA == KX || kx < KX);   // pad columns are read (zeros), not written
   Tw<PL, V> w;
   tw_load<PL>(w, t, tw);
   const V* in = A1 + bf * KF * NKXA + z0 * KXA;
