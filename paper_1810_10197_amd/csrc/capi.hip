@@ -114,7 +114,7 @@ struct Layout {
   size_t tw32, tw64, nu, h, red_out, mask, alpha, red_part, bandb;
   size_t ctl_d[6], ctl_i[7], ctl_l[3];
   size_t mw, mmom, mvel, mgrad, mloss, mx, my, pend_x, pend_h, pend_ok, ring_x, ring_y, ring_n, rows, act;
-  size_t fields[10], stage32, dpart, k32, a1, a2, total;
+  size_t fields[10], stage32, u32, dpart, k32, a1, a2, total;
 };
 
 Layout make_layout(const ns_config* c) {
@@ -152,10 +152,11 @@ Layout make_layout(const ns_config* c) {
   L.act = take(nsk::mlp_act_floats(TRAIN_MAX) * 4);
   for (int i = 0; i < 10; ++i) L.fields[i] = take((size_t)g.epm * B * 16);
   L.stage32 = take((size_t)g.epm * B * 8);   // FP32 stage input of an FP32 3D right-hand side
+  const bool s32 = c->dim == 3 && c->rhs_precision == NS_FP32;
+  L.u32 = take(s32 ? (size_t)g.epm * B * 8 : 0);   // FP32 rounding of the committed state
   L.dpart = take((size_t)g.epm * B * 16);    // sum_{j<S} (b_j - bh_j) k_j, from the last combination
   // FP32 copies of the stage derivatives (3D FP32 right-hand side): the
   // sources of the stage combinations whose result is an FP32 stage input
-  const bool s32 = c->dim == 3 && c->rhs_precision == NS_FP32;
   L.k32 = take(s32 ? (size_t)g.epm * B * 8 * 8 : 0);
   const int fp64 = c->rhs_precision == NS_FP64;
   const size_t scratch = c->dim == 3 ? nsk::rhs3d_scratch_bytes(g, fp64) : nsk::rhs2d_scratch_bytes(g, fp64);
@@ -187,6 +188,9 @@ struct ns_solver {
   double2* u;        // committed state u_n (compact)
   double2* U;        // stage / candidate state
   float2* U32;       // stage state rounded to FP32: the input of an FP32 3D right-hand side
+  float2* u32;       // u_n rounded to FP32 (3D FP32 right-hand side; else null): the base of
+                     // the stage combinations that are only FP32 inputs
+  bool u32_ok = false;   // u32 holds the rounding of the current u
   double2* dpart;    // embedded difference over all stages but the last (written with u_{n+1})
   double2* k[8];     // stage derivatives; k[0] = f(u_n) when k1_valid
   float2* k32[8];    // their FP32 copies (3D FP32 right-hand side; else null), kept in step with k
@@ -278,6 +282,19 @@ static int rhs(ns_solver* s, const double2* U, double2* K, bool want32 = false, 
 // where it is needed (the last stage of an FSAL pair is u_{n+1}).
 static bool stage32(const ns_solver* s) { return s->g.dim == 3 && !s->fp64; }
 
+// u32 = u rounded to FP32, where the FP32 stage combinations need it and it
+// is not current.  Kept current by the commits: the last stage of an attempt
+// writes the FP32 rounding of u_{n+1} as its stage input, which the commit
+// keeps (a pointer swap, or a masked copy inside a captured attempt).
+static int ensure_u32(ns_solver* s) {
+  if (!stage32(s) || s->u32_ok) return NS_OK;
+  Combo c0;
+  c0.nterms = 0;
+  NS_HIP(nsk::combine2(s->g, s->u, c0, s->h_d, nullptr, s->u32, nullptr, s->st));
+  s->u32_ok = true;
+  return NS_OK;
+}
+
 // U_i = u + h sum_j c_j k_j and k_i = f(U_i); keep64: also write U_i in FP64;
 // dpart (not null): also sum_j coef2_j k_j from the same loads.  A stage that
 // is only an FP32 input reads the FP32 copies of the k_j; want32: write the
@@ -291,7 +308,8 @@ static int stage(ns_solver* s, Combo c, const double* h, bool keep64, double2* K
     from32 = c.src32[j] != nullptr;
   }
   if (from32) {
-    NS_HIP(nsk::combine_s32(s->g, s->u, c, h, s->U32, s->st));
+    if (int rc = ensure_u32(s)) return rc;
+    NS_HIP(nsk::combine_s32(s->g, (const float2*)s->u32, c, h, s->U32, s->st));
   } else if (stage32(s)) {
     NS_HIP(nsk::combine2(s->g, s->u, c, h, keep64 ? s->U : nullptr, s->U32, dpart, s->st));
   } else if (dpart) {
@@ -416,6 +434,12 @@ static int apply_forcing(ns_solver* s, const int* mask_dev, bool have_reduction 
   NS_HIP(nsk::force_alpha(s->red_out, mask_dev, s->cfg.force_e0, s->alpha_d, s->g.batch, s->st));
   NS_HIP(nsk::scale_band(s->g, s->u, s->alpha_d, forcing_kf2(s), s->st));
   s->k1_valid = false;
+  if (stage32(s)) {                            // the rescaled band changes u's FP32 rounding
+    Combo c0;
+    c0.nterms = 0;
+    NS_HIP(nsk::combine2(s->g, s->u, c0, s->h_d, nullptr, s->u32, nullptr, s->st));
+    s->u32_ok = true;
+  }
   return NS_OK;
 }
 
@@ -443,6 +467,7 @@ static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
   NS_HIP(hipMemcpyAsync(s->mask_d, s->maskbuf.data(), sizeof(int) * s->g.batch, hipMemcpyHostToDevice, s->st));
   if (nacc == s->g.batch) {
     std::swap(s->u, s->U);
+    if (s->u32) std::swap(s->u32, s->U32);     // the last stage's input: u_{n+1} rounded to FP32
     std::swap(s->k[0], s->k[last]);
     std::swap(s->k32[0], s->k32[last]);
     if (s->gexec) {                            // the captured graph holds the old pointers
@@ -451,6 +476,7 @@ static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
     }
   } else if (nacc > 0) {
     NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->mask_d, s->st));
+    if (s->u32) NS_HIP(nsk::masked_copy32(s->g, s->U32, s->u32, s->mask_d, s->st));
     NS_HIP(nsk::masked_copy(s->g, s->k[last], s->k[0], s->mask_d, s->st));
     if (s->k32[0]) NS_HIP(nsk::masked_copy32(s->g, s->k32[last], s->k32[0], s->mask_d, s->st));
   }
@@ -481,6 +507,7 @@ static int integrate_attempt(ns_solver* s, const Pair& P, double atol, double rt
     NS_HIP(nsk::collect_rows(s->ctl, s->mx, s->pend_x, s->pend_h, s->pend_ok, s->ring_x, s->ring_y, s->ring_n,
                              RING_CAP, s->g.batch, s->st));
   NS_HIP(nsk::masked_copy(s->g, s->U, s->u, s->ctl.accept, s->st));
+  if (s->u32) NS_HIP(nsk::masked_copy32(s->g, s->U32, s->u32, s->ctl.accept, s->st));
   NS_HIP(nsk::masked_copy(s->g, s->k[P.stages - 1], s->k[0], s->ctl.accept, s->st));
   if (s->k32[0]) NS_HIP(nsk::masked_copy32(s->g, s->k32[P.stages - 1], s->k32[0], s->ctl.accept, s->st));
   if (forced) {
@@ -531,6 +558,7 @@ int ns_init(const ns_config* cfg, const double* nu_host, void* workspace, size_t
   s->u = (double2*)(w + L.fields[0]);
   s->U = (double2*)(w + L.fields[1]);
   s->U32 = (float2*)(w + L.stage32);
+  s->u32 = stage32(s) ? (float2*)(w + L.u32) : nullptr;
   s->dpart = (double2*)(w + L.dpart);
   for (int i = 0; i < 8; ++i) s->k[i] = (double2*)(w + L.fields[2 + i]);
   for (int i = 0; i < 8; ++i)
@@ -630,6 +658,7 @@ int ns_set_state(ns_solver* s, const void* uhat) {
   NS_HIP(nsk::pack_state(s->g, (const double2*)uhat, s->u, s->st));
   s->have_state = true;
   s->k1_valid = false;
+  s->u32_ok = false;
   s->ctl_warm = false;
   return NS_OK;
 }
@@ -685,6 +714,7 @@ int ns_step_rk4(ns_solver* s, double h) {
   NS_HIP(nsk::combine(s->g, s->u, c, s->h_d, s->U, s->st));
   prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
   std::swap(s->u, s->U);
+  s->u32_ok = false;
   if (s->gexec) {                              // the captured graph holds the old pointers
     (void)hipGraphExecDestroy(s->gexec);
     s->gexec = nullptr;
@@ -771,6 +801,8 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol, double rtol
   }
   const bool first = !s->k1_valid;
   int rc = ensure_k1(s);
+  if (rc) return rc;
+  rc = ensure_u32(s);                          // before any capture: the graph keeps it current
   if (rc) return rc;
   const bool prof = s->prof_on;
   // Attempts run on a private non-blocking stream (a graph cannot be captured
@@ -971,6 +1003,7 @@ int ns_checkpoint_load(ns_solver* s, const void* host_buf, size_t bytes) {
   NS_HIP(hipMemcpy(s->ctl.prev_rej, p + L.prev_rej, 4 * B, hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(s->ctl.consec, p + L.consec, 4 * B, hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(s->u, p + L.u, 16 * E, hipMemcpyHostToDevice));
+  s->u32_ok = false;
   if (hd.k1_valid) {
     NS_HIP(hipMemcpy(s->k[0], p + L.k0, 16 * E, hipMemcpyHostToDevice));
     if (s->k32[0]) NS_HIP(hipMemcpy(s->k32[0], p + L.k32, 8 * E, hipMemcpyHostToDevice));

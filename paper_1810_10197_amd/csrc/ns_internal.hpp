@@ -125,6 +125,9 @@ hipError_t scale_band(const Geom& g, double2* u, const double* alpha, double kf2
 // exceeds that of the copies by the factor |U| / (h sum |a_j k_j|)).
 hipError_t combine_s32(const Geom& g, const double2* base, const Combo& c, const double* h, float2* out32,
                        hipStream_t st);
+// The same from the FP32 rounding of the base (the committed state's FP32 copy).
+hipError_t combine_s32(const Geom& g, const float2* base, const Combo& c, const double* h, float2* out32,
+                       hipStream_t st);
 hipError_t masked_copy32(const Geom& g, const float2* src, float2* dst, const int* mask_dev, hipStream_t st);
 hipError_t masked_copy(const Geom& g, const double2* src, double2* dst, const int* mask_dev,
                        hipStream_t st);

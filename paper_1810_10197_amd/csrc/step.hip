@@ -103,9 +103,11 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ bas
 }
 
 // out32 = base + h_m sum_j coef_j src32_j (FP64 accumulation of FP32 sources),
-// rounded to FP32.
-template <int NT>
-__global__ __launch_bounds__(256) void k_combine_s32(const double2* __restrict__ base, Combo c,
+// rounded to FP32.  The base is the FP64 state or its FP32 rounding (BT).
+__device__ __forceinline__ double2 to_d2s(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2s(float2 v) { return make_double2((double)v.x, (double)v.y); }
+template <int NT, typename BT>
+__global__ __launch_bounds__(256) void k_combine_s32(const BT* __restrict__ base, Combo c,
                                                      const double* __restrict__ h, float2* __restrict__ out32,
                                                      long long epm) {
   const long long off = (long long)blockIdx.y * epm;
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(256) void k_combine_s32(const double2* __restrict__
     float2 v[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) v[j] = ld_stream(c.src32[j] + off + i);
-    double2 r = ld_stream(base + off + i);
+    const double2 r = to_d2s(ld_stream(base + off + i));
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
@@ -151,8 +153,9 @@ static hipError_t combine_to(const Geom& g, const double2* base, const Combo& c,
   return hipGetLastError();
 }
 
-hipError_t combine_s32(const Geom& g, const double2* base, const Combo& c, const double* h, float2* out32,
-                       hipStream_t st) {
+template <typename BT>
+static hipError_t combine_s32_from(const Geom& g, const BT* base, const Combo& c, const double* h, float2* out32,
+                                   hipStream_t st) {
   if (!base || !out32) return hipErrorInvalidValue;
   for (int j = 0; j < c.nterms; ++j)
     if (!c.src32[j]) return hipErrorInvalidValue;
@@ -160,7 +163,7 @@ hipError_t combine_s32(const Geom& g, const double2* base, const Combo& c, const
   switch (c.nterms) {
 #define NSK_COMBINE(k)                                                                                  \
     case k:                                                                                             \
-      hipLaunchKernelGGL((k_combine_s32<k>), grid, dim3(256), 0, st, base, c, h, out32, g.epm); \
+      hipLaunchKernelGGL((k_combine_s32<k, BT>), grid, dim3(256), 0, st, base, c, h, out32, g.epm); \
       break;
     NSK_COMBINE(1) NSK_COMBINE(2) NSK_COMBINE(3) NSK_COMBINE(4) NSK_COMBINE(5)
     NSK_COMBINE(6) NSK_COMBINE(7) NSK_COMBINE(8) NSK_COMBINE(9)
@@ -168,6 +171,15 @@ hipError_t combine_s32(const Geom& g, const double2* base, const Combo& c, const
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t combine_s32(const Geom& g, const double2* base, const Combo& c, const double* h, float2* out32,
+                       hipStream_t st) {
+  return combine_s32_from(g, base, c, h, out32, st);
+}
+hipError_t combine_s32(const Geom& g, const float2* base, const Combo& c, const double* h, float2* out32,
+                       hipStream_t st) {
+  return combine_s32_from(g, base, c, h, out32, st);
 }
 
 hipError_t combine(const Geom& g, const double2* base, const Combo& c, const double* h,
