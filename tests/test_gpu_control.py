@@ -171,3 +171,37 @@ def test_forced_integrate_at_1024(ns):
     s.close()
     assert st["t"] == 0.01 and st["n_accept"] >= 1
     assert abs(e[0] - e0) <= 1e-12 * e0
+
+
+def test_host_steps_with_partial_acceptance_equal_single_runs(ns):
+    """ns_step_bs5 on a batch where one member accepts and the other rejects
+    (the host commit copies the accepted member's state, its first stage and
+    the FP32 rounding of its state; a batch that accepts whole swaps them):
+    every member stays bitwise equal to the same steps taken alone, with a
+    right-hand side whose stage combinations start from the FP32 copy."""
+    n = 16
+    announce("host steps, partial acceptance == single n=%d" % n)
+    ua = inputs.tgv3d(n)
+    ub = 40.0 * inputs.random_isotropic(n, 5)        # large: rejected at the larger steps
+    nus = [0.01, 0.02]
+    sb = ns.Solver(dim=3, n=n, batch=2, nu=nus, rhs_precision="fp32")
+    sb.set_state(np.stack([ua, ub]))
+    singles = []
+    for u, nu in ((ua, nus[0]), (ub, nus[1])):
+        s1 = ns.Solver(dim=3, n=n, nu=nu, rhs_precision="fp32")
+        s1.set_state(u[None])
+        singles.append(s1)
+    mixed = 0
+    for h in (0.05, 0.05, 0.02, 0.01, 0.01, 0.005, 0.005, 0.005):
+        _, eb = sb.step_bs5(h, 1e-6, 1e-6)
+        for m, s1 in enumerate(singles):
+            _, e1 = s1.step_bs5(h, 1e-6, 1e-6)
+            assert eb[m] == e1[0] or (np.isnan(eb[m]) and np.isnan(e1[0]))
+        mixed += (eb[0] <= 1.0) != (eb[1] <= 1.0)
+    assert mixed >= 1                                  # the partial commit was exercised
+    ubatch = sb.get_state().cpu().numpy()
+    for m, s1 in enumerate(singles):
+        u1 = s1.get_state().cpu().numpy()[0]
+        assert np.array_equal(u1.view(np.float64), ubatch[m].view(np.float64))
+        s1.close()
+    sb.close()
