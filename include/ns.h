@@ -336,9 +336,10 @@ int ns_profile_mode(ns_solver* s, int mode);
  * receives the per-parameter averages of the first round in milliseconds (0
  * for variants a parameter lacks).  tune_get /
  * tune_set read or restore the choice (e.g. from a cache).  2D (n >= 256):
- * parameter 0 is the y-inverse's and parameter 4 the y-forward's variant
- * (radix plan and column tile, 0-4; with the Boussinesq scalar, y-forward
- * variants 2 and 4 split the four fields over two blocks), timed per launch;
+ * parameter 0 is the y-inverse's (0-4) and parameter 4 the y-forward's (0-6)
+ * variant (radix plan and column tile; with the Boussinesq scalar, y-forward
+ * variants 2, 4, 5 and 6 split the four fields over two blocks, 5 and 6 with
+ * tiles of at most two and four columns), timed per launch;
  * parameter 2 the x-pass: bit 0 the layout it hands to the y-forward (0
  * row-major, 1 column-major), 2 and 3 the same layouts with one row per
  * block and one wavefront per transform (at 512, 1024 and the padded 1536

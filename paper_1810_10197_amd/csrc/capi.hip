@@ -1199,6 +1199,7 @@ int ns_tune_get(ns_solver* s, int* v) {
 
 static int tune_nvariants(const ns_solver* s, int p) {
   if (p == 2) return s->g.dim == 2 ? nsk::NVARIANT_ROW2D : nsk::NVARIANT_ROW;
+  if (p == 4 && s->g.dim == 2) return nsk::NVARIANT_Q3_2D;
   return p == 5 ? nsk::NVARIANT_SLAB : nsk::NVARIANT_COL;
 }
 

@@ -49,6 +49,7 @@ struct RhsBufs {
                       // own stream), 2 whole evaluations only (PROF_RHS)
 };
 constexpr int NVARIANT_COL = 5, NVARIANT_ROW = 2, NVARIANT_SLAB = 13;
+constexpr int NVARIANT_Q3_2D = 7;    // 2D y-forward slot: Q3 variants 0-6
 constexpr int NVARIANT_ROW2D = 4;   // 2D x-pass slot: B2 layout x (row per wavefront | row split)
 // 3D slab schedule of the y/x/y passes, variant v: v < 5 one stream with
 // slabs of n >> v planes; 5 <= v < 9 slabs of n >> (v - 4) planes alternating

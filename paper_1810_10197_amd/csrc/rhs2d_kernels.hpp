@@ -423,7 +423,8 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::
 // plan default tile, 4 narrow plan two columns; Q3 (slot 4) 0 up to eight
 // columns, 1 two, 2 one (Boussinesq: the fields split over two blocks, up to
 // eight columns), 3 narrow plan up to eight, 4 narrow plan one (Boussinesq:
-// split, up to eight); slot 2: the layout of B2 (bit 0: 0 row-major, 1
+// split, up to eight), 5 two and 6 four (Boussinesq: split, so that a
+// single grid gives two to four times the blocks of variant 1); slot 2: the layout of B2 (bit 0: 0 row-major, 1
 // column-major) and, from 2 on, the row-split x-pass (one wavefront per
 // transform; where a row's transform is one wavefront).  The x-pass keeps
 // the wide plan (a row stays inside one wavefront).
@@ -432,9 +433,12 @@ template <int N, int V> struct Q1Var {
   static constexpr int CW = N < 256 ? 0 : (V == 1 ? 4 : (V == 2 || V == 4 ? 2 : 0));
 };
 template <int N, int V, bool SCALAR> struct Q3Var {
-  using PL = typename std::conditional<(V >= 3 && N >= 256), PlanS<N>, Plan<N>>::type;
-  static constexpr bool SPLIT = SCALAR && N >= 256 && (V == 2 || V == 4);
-  static constexpr int CMAX = N < 256 ? 8 : (V == 1 ? 2 : ((V == 2 || V == 4) && !SPLIT ? 1 : 8));
+  using PL = typename std::conditional<((V == 3 || V == 4) && N >= 256), PlanS<N>, Plan<N>>::type;
+  static constexpr bool SPLIT = SCALAR && N >= 256 && (V == 2 || V == 4 || V == 5 || V == 6);
+  static constexpr int CMAX = N < 256 ? 8
+                              : (V == 1 || V == 5) ? 2
+                              : V == 6 ? 4
+                              : ((V == 2 || V == 4) && !SPLIT ? 1 : 8);
 };
 
 template <int N, typename T, int VAR>
@@ -465,6 +469,8 @@ static void launch_q3v(int v3, const Geom& g, const cplx<T>* B2, const double2* 
     case 2: launch_q3<N, T, SCALAR, N >= 256 ? 2 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
     case 3: launch_q3<N, T, SCALAR, N >= 256 ? 3 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
     case 4: launch_q3<N, T, SCALAR, N >= 256 ? 4 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
+    case 5: launch_q3<N, T, SCALAR, N >= 256 ? 5 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
+    case 6: launch_q3<N, T, SCALAR, N >= 256 ? 6 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
     default: launch_q3<N, T, SCALAR, 0, COLB2>(g, B2, U, K, p, tw, st);
   }
 }

@@ -113,7 +113,7 @@ def test_boussinesq_bs5_steps_and_diagnostics(ns):
 def test_rhs2d_every_launch_variant(ns, n, scalar, prec):
     """Each variant of the two column passes (radix plan and tile width; the
     narrow 1024-point plan has four passes; with the scalar, y-forward
-    variants 2 and 4 split the fields over two blocks) and of the x-pass
+    variants 2, 4, 5 and 6 split the fields over two blocks) and of the x-pass
     (both B2 layouts, one wavefront per row or, at 1024, one per transform)
     is a correct right-hand side, and the autotuner keeps one of them."""
     announce("rhs2d variants n=%d scalar=%d %s" % (n, scalar, prec))
@@ -123,8 +123,8 @@ def test_rhs2d_every_launch_variant(ns, n, scalar, prec):
     ref = spectral.rhs_ns2d(u, nu, kappa, ri) if scalar else spectral.rhs_ns2d(u, nu)
     s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision=prec, scalar=scalar, ri=ri if scalar else 0.0,
                   kappa=kappa if scalar else 0.0)
-    for v in range(20):                         # x-pass slot: layout bit, row split from 2 on
-        s.tune([v % 5, 0, v // 5, 0, 4 - v % 5, 0])
+    for v in range(28):                         # x-pass slot: layout bit, row split from 2 on
+        s.tune([v % 5, 0, (v // 7) % 4, 0, 6 - v % 7, 0])
         got = s.rhs(u[None]).cpu().numpy()[0]
         err = max(per_field_rel_l2(got, ref))
         assert err <= tol, (v, err)
@@ -133,7 +133,12 @@ def test_rhs2d_every_launch_variant(ns, n, scalar, prec):
     # per slot the fastest variant, or one within 3% of it that won on whole evaluations
     assert ms[0][variants[0]] <= 1.03 * min(x for x in ms[0][:5] if x > 0)
     assert ms[2][variants[2]] <= 1.03 * min(x for x in ms[2][:4] if x > 0)
-    assert ms[4][variants[4]] <= 1.03 * min(x for x in ms[4][:5] if x > 0)
+    assert ms[4][variants[4]] <= 1.03 * min(x for x in ms[4][:7] if x > 0)
+    assert ms[4][7] == 0 and ms[0][5] == 0
+    with pytest.raises(ns.NsError):
+        s.tune([0, 0, 0, 0, 7, 0])               # beyond the y-forward's variants
+    with pytest.raises(ns.NsError):
+        s.tune([5, 0, 0, 0, 0, 0])               # beyond the y-inverse's
     got = s.rhs(u[None]).cpu().numpy()[0]
     assert max(per_field_rel_l2(got, ref)) <= tol
     s.close()

@@ -58,16 +58,16 @@ def test_padded_rhs2d_matches_oracle(ns, n, scalar, prec):
 @pytest.mark.parametrize("n,prec", [(256, "fp32"), (1024, "fp32"), (1024, "fp64")])
 def test_padded_rhs2d_every_launch_variant(ns, n, prec):
     """Every Q1/Q3 variant on the padded 384^2 and 1536^2 grids (the narrow
-    four-pass plan at 384; y-forward variants 2 and 4 split the four fields
-    over two blocks), and the autotuner's pick."""
+    four-pass plan at 384; y-forward variants 2, 4, 5 and 6 split the four
+    fields over two blocks), and the autotuner's pick."""
     announce("padded rhs2d variants n=%d %s" % (n, prec))
     nu, kappa, ri = 1e-3, 2e-3, 0.5
     tol = 3e-6 if prec == "fp32" else 1e-12
     st = band_field(n, 11 * n, 3)
     ref = spectral.rhs_ns2d_padded(st, nu, kappa, ri)
     s = solver(ns, n, prec, 1, nu, kappa, ri)
-    for v in range(20):                         # x-pass slot: layout bit, row split from 2 on
-        s.tune([v % 5, 0, v // 5, 0, 4 - v % 5, 0])
+    for v in range(28):                         # x-pass slot: layout bit, row split from 2 on
+        s.tune([v % 5, 0, (v // 7) % 4, 0, 6 - v % 7, 0])
         got = s.rhs(st[None]).cpu().numpy()[0]
         err = max(per_field_rel_l2(got, ref))
         assert err <= tol, (v, err)
