@@ -291,7 +291,8 @@ int ns_mlp_train(ns_solver* s, int iters, int batch, float lr, unsigned long lon
                  float* loss_host);
 
 /* Kernel timing with HIP events recorded around kernel launches while
- * profiling is on (a tracing aid; the events add a few microseconds per
+ * profiling is on (a tracing aid; timing-only events without the system-scope
+ * cache fence, which still add a few microseconds of packet time per
  * launch).  Index: 0..4 the five right-hand-side passes (z-inverse,
  * y-inverse, x-pass, y-forward, z-forward; in 3D the y/x/y launches are not
  * timed one by one), 5 stage combinations, 6 reductions, 7 other, 8 the
