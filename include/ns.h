@@ -332,8 +332,9 @@ int ns_profile_mode(ns_solver* s, int mode);
  * of the y/x/y phase per evaluation) and keeps the fastest; then, for each
  * parameter with several variants within 3% of its fastest, it times those on
  * whole evaluations (2 x reps each, one event pair per evaluation) and keeps the
- * fastest of them, since a pass's variant also changes what the caches hold
- * for its neighbours.  ms_host (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL)
+ * lowest-numbered of them within 1% of the fastest (variants are numbered from
+ * the plainest launch up; closer timings are within the scatter), since a
+ * pass's variant also changes what the caches hold for its neighbours.  ms_host (NS_NTUNE x NS_TUNE_MAXV doubles, may be NULL)
  * receives the per-parameter averages of the first round in milliseconds (0
  * for variants a parameter lacks).  tune_get /
  * tune_set read or restore the choice (e.g. from a cache).  2D (n >= 256):

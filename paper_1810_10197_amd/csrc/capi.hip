@@ -1312,6 +1312,8 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
     if (ncand < 2) continue;
     double wbest = 1e300;
     int wbest_v = s->rb.variant[p];
+    double wms[NS_TUNE_MAXV];
+    for (double& x : wms) x = 1e300;
     for (int v = 0; v < nv && !rc; ++v) {
       if (!(tms[p][v] <= 1.03 * best)) continue;
       s->rb.variant[p] = v;
@@ -1329,11 +1331,18 @@ int ns_autotune(ns_solver* s, int reps, double* ms_host) {
         break;
       }
       const double ms = kt.count[nsk::PROF_RHS] ? kt.ms[nsk::PROF_RHS] / (double)kt.count[nsk::PROF_RHS] : 1e300;
-      if (ms < wbest) {
-        wbest = ms;
-        wbest_v = v;
-      }
+      wms[v] = ms;
+      if (ms < wbest) wbest = ms;
     }
+    // the lowest-numbered candidate within 1% of the fastest: the numbering
+    // runs from the plainest launch (wide plan, default tile; one slab on one
+    // stream) up, and differences below 1% are within the timing's scatter,
+    // so ties go to the plain launch and the choice is stable between runs
+    for (int v = 0; v < nv && !rc; ++v)
+      if (wms[v] <= 1.01 * wbest) {
+        wbest_v = v;
+        break;
+      }
     s->rb.variant[p] = wbest_v;
   }
   s->rb.fine = was_mode;
