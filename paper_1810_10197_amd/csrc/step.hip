@@ -377,36 +377,26 @@ __global__ __launch_bounds__(RBS) void k_reduce(ReduceArgs a, double* __restrict
   }
 }
 
-// One block per member: thread i sums partial blocks i, i + RBS, ... in order,
-// then a fixed shuffle tree and a fixed-order sum over the waves.
+// One block per (sum q, member): thread i adds partial blocks i, i + RBS, ...
+// of sum q in order, then a fixed shuffle tree and a fixed-order sum over the
+// waves.  Every sum is formed in the same order whatever the batch; spreading
+// the NRED sums over blocks keeps each block's strided loads few (one member's
+// partials are up to 1024 x NRED doubles, which one block read in 11-12 us).
 __global__ __launch_bounds__(RBS) void k_reduce_final(const double* __restrict__ partials, int nblk,
                                                       double* __restrict__ out) {
-  const int m = blockIdx.x;
-  __shared__ double red[RBS / 64][NRED];
+  const int q = blockIdx.x, m = blockIdx.y;
+  __shared__ double red[RBS / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double* p = partials + (long long)m * nblk * NRED;
-  // all NRED sums of a partial block at once (their loads in flight
-  // together); per sum the same order as one sum at a time
-  double s[NRED];
-#pragma unroll
-  for (int q = 0; q < NRED; ++q) s[q] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += RBS) {
-    double v[NRED];
-#pragma unroll
-    for (int q = 0; q < NRED; ++q) v[q] = p[(long long)b * NRED + q];
-#pragma unroll
-    for (int q = 0; q < NRED; ++q) s[q] += v[q];
-  }
-#pragma unroll
-  for (int q = 0; q < NRED; ++q) {
-    const double t = wave_sum(s[q]);
-    if (lane == 0) red[wv][q] = t;
-  }
+  const double* p = partials + (long long)m * nblk * NRED + q;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += RBS) s += p[(long long)b * NRED];
+  const double t = wave_sum(s);
+  if (lane == 0) red[wv] = t;
   __syncthreads();
-  if (threadIdx.x < NRED) {
-    double s = 0.0;
-    for (int w = 0; w < RBS / 64; ++w) s += red[w][threadIdx.x];
-    out[(long long)m * NRED + threadIdx.x] = s;
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < RBS / 64; ++w) r += red[w];
+    out[(long long)m * NRED + q] = r;
   }
 }
 
@@ -467,7 +457,7 @@ hipError_t reduce_state(const Geom& g, const ReduceArgs& a, double* partials, do
       default: return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL(k_reduce_final, dim3(g.batch), dim3(RBS), 0, st, partials, nblk, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(NRED, g.batch), dim3(RBS), 0, st, partials, nblk, out);
   return hipGetLastError();
 }
 
