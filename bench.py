@@ -89,15 +89,19 @@ def pass_bytes(n, fp64=False, stage32=False):
     }
 
 
-def pass_bytes_2d(n, fp64=False):
+def pass_bytes_2d(n, fp64=False, stage32=False):
     """Same for the 2D Boussinesq passes (state u, v, rho; four transformed
-    fields): Q1 y-inverse, Q2 x-pass, Q3 y-forward + epilogue."""
+    fields): Q1 y-inverse, Q2 x-pass, Q3 y-forward + epilogue; stage32 as in
+    pass_bytes (the stage input read in FP32 by Q1 and Q3, f's FP32 copy
+    written by Q3 in 6 of 7 evaluations)."""
     K = (n - 1) // 3
     Kf, Kx = 2 * K + 1, K + 1
     mr = Kf * Kx
     cb = 16 if fp64 else 8
+    sb = 8 if stage32 else 16
     col = 4 * n * Kx * cb
-    return {"zinv": 3 * mr * 16 + col, "xpass": 2 * col, "zfwd": col + 2 * 3 * mr * 16}
+    return {"zinv": 3 * mr * sb + col, "xpass": 2 * col,
+            "zfwd": col + 3 * mr * sb + 3 * mr * 16 + (3 * mr * 8 * 6 // 7 if stage32 else 0)}
 
 
 def hbm_copy_gbs(nbytes=1 << 30, reps=10):
@@ -1032,10 +1036,10 @@ def bench_throughput(args):
 
     rhs_evals = 7 * args.steps * batch
     value = rhs_evals / elapsed
-    # inside the BS5 steps the 3D FP32 right-hand side reads FP32 stage inputs
+    # inside the BS5 steps an FP32 right-hand side reads FP32 stage inputs (3D and 2D)
     # the 3/2 rule runs the same passes on the padded grid 3n/2
     pb = (pass_bytes(3 * n // 2 if padded else n, fp64, stage32=not fp64) if dim == 3
-          else pass_bytes_2d(3 * n // 2 if padded else n, fp64))
+          else pass_bytes_2d(3 * n // 2 if padded else n, fp64, stage32=not fp64))
     pb = {k: v * batch for k, v in pb.items()}
     n_rhs = prof["zinv"][1]                       # one first-pass launch per evaluation
     per_kernel = {}

@@ -215,7 +215,7 @@ int ns_integrate(ns_solver* s, double t_end, double h0, double atol,
  * per-member viscosity and time, the controller's continuation state (next
  * step, rejection flag, consecutive rejections, last three accepted errors),
  * the retained-mode state u_n, the cached first stage f(u_n) when valid
- * (with its FP32 copy, 3D FP32 right-hand side) and the proposer's weights.
+ * (with its FP32 copy, FP32 right-hand side) and the proposer's weights.
  * Not included: the proposer's training rows and optimiser moments, the
  * autotuner's choice.  save: host buffer owned by the caller, written
  * synchronously.  load: into a solver created with the same configuration

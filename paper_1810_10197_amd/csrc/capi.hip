@@ -151,11 +151,11 @@ Layout make_layout(const ns_config* c) {
   L.rows = take((size_t)TRAIN_MAX * 4);
   L.act = take(nsk::mlp_act_floats(TRAIN_MAX) * 4);
   for (int i = 0; i < 10; ++i) L.fields[i] = take((size_t)g.epm * B * 16);
-  L.stage32 = take((size_t)g.epm * B * 8);   // FP32 stage input of an FP32 3D right-hand side
-  const bool s32 = c->dim == 3 && c->rhs_precision == NS_FP32;
+  L.stage32 = take((size_t)g.epm * B * 8);   // FP32 stage input of an FP32 right-hand side
+  const bool s32 = c->rhs_precision == NS_FP32;
   L.u32 = take(s32 ? (size_t)g.epm * B * 8 : 0);   // FP32 rounding of the committed state
   L.dpart = take((size_t)g.epm * B * 16);    // sum_{j<S} (b_j - bh_j) k_j, from the last combination
-  // FP32 copies of the stage derivatives (3D FP32 right-hand side): the
+  // FP32 copies of the stage derivatives (FP32 right-hand side): the
   // sources of the stage combinations whose result is an FP32 stage input
   L.k32 = take(s32 ? (size_t)g.epm * B * 8 * 8 : 0);
   const int fp64 = c->rhs_precision == NS_FP64;
@@ -187,13 +187,13 @@ struct ns_solver {
   void* tw;          // twiddles in the rhs precision
   double2* u;        // committed state u_n (compact)
   double2* U;        // stage / candidate state
-  float2* U32;       // stage state rounded to FP32: the input of an FP32 3D right-hand side
-  float2* u32;       // u_n rounded to FP32 (3D FP32 right-hand side; else null): the base of
+  float2* U32;       // stage state rounded to FP32: the input of an FP32 right-hand side
+  float2* u32;       // u_n rounded to FP32 (FP32 right-hand side; else null): the base of
                      // the stage combinations that are only FP32 inputs
   bool u32_ok = false;   // u32 holds the rounding of the current u
   double2* dpart;    // embedded difference over all stages but the last (written with u_{n+1})
   double2* k[8];     // stage derivatives; k[0] = f(u_n) when k1_valid
-  float2* k32[8];    // their FP32 copies (3D FP32 right-hand side; else null), kept in step with k
+  float2* k32[8];    // their FP32 copies (FP32 right-hand side; else null), kept in step with k
   nsk::RhsBufs rb;
   nsk::CtlState ctl;
   // proposer network
@@ -272,15 +272,28 @@ static int rhs(ns_solver* s, const double2* U, double2* K, bool want32 = false, 
   p.k32 = want32 ? k32_of(s, K) : nullptr;
   p.active = active;
   hipError_t e = s->g.dim == 3 ? nsk::rhs3d_compact(s->g, s->fp64, U, nullptr, K, p, s->rb, s->tw, s->st)
-                               : nsk::rhs2d_compact(s->g, s->fp64, U, K, p, s->rb, s->tw, s->st);
+                               : nsk::rhs2d_compact(s->g, s->fp64, U, nullptr, K, p, s->rb, s->tw, s->st);
   return e == hipSuccess ? NS_OK : NS_ERR_HIP;
 }
 
-// Stage inputs: an FP32 3D right-hand side rounds its input to FP32 anyway
-// (after the curl), so its stages are written once in FP32 and read in FP32
-// by the z passes (half the stage traffic); the FP64 copy is written only
-// where it is needed (the last stage of an FSAL pair is u_{n+1}).
-static bool stage32(const ns_solver* s) { return s->g.dim == 3 && !s->fp64; }
+// Stage inputs: an FP32 right-hand side rounds its input to FP32 anyway
+// (3D: after the curl; 2D: before the y-transforms), so its stages are
+// written once in FP32 and read in FP32 by the first and last passes (half
+// the stage traffic); the FP64 copy is written only where it is needed (the
+// last stage of an FSAL pair is u_{n+1}).
+static bool stage32(const ns_solver* s) { return !s->fp64; }
+
+// k = f(U32), the FP32 stage input (want32: also f's FP32 copy).
+static int rhs_stage32(ns_solver* s, double2* K, bool want32) {
+  nsk::RhsParams p;
+  p.nu = s->nu_d;
+  p.ri = s->cfg.ri;
+  p.kappa = s->cfg.kappa;
+  p.k32 = want32 ? k32_of(s, K) : nullptr;
+  const hipError_t e = s->g.dim == 3 ? nsk::rhs3d_compact(s->g, 0, nullptr, s->U32, K, p, s->rb, s->tw, s->st)
+                                     : nsk::rhs2d_compact(s->g, 0, nullptr, s->U32, K, p, s->rb, s->tw, s->st);
+  return e == hipSuccess ? NS_OK : NS_ERR_HIP;
+}
 
 // u32 = u rounded to FP32, where the FP32 stage combinations need it and it
 // is not current.  Kept current by the commits: the last stage of an attempt
@@ -319,13 +332,7 @@ static int stage(ns_solver* s, Combo c, const double* h, bool keep64, double2* K
   }
   prof_hook(s, nsk::PROF_COMBINE, 1, s->st);
   if (!stage32(s)) return rhs(s, s->U, K, want32);
-  nsk::RhsParams p;
-  p.nu = s->nu_d;
-  p.ri = s->cfg.ri;
-  p.kappa = s->cfg.kappa;
-  p.k32 = want32 ? k32_of(s, K) : nullptr;
-  const hipError_t e = nsk::rhs3d_compact(s->g, 0, nullptr, s->U32, K, p, s->rb, s->tw, s->st);
-  return e == hipSuccess ? NS_OK : NS_ERR_HIP;
+  return rhs_stage32(s, K, want32);
 }
 
 static int ensure_k1(ns_solver* s) {
@@ -1216,16 +1223,11 @@ int ns_tune_set(ns_solver* s, const int* v) {
 }
 
 // The right-hand side the autotuner times: the one the steps run.  With an
-// FP32 3D right-hand side that is the stage form, whose input is the FP32
+// FP32 right-hand side that is the stage form, whose input is the FP32
 // stage state (here u_n rounded once into the stage buffer).
 static int tune_rhs(ns_solver* s) {
   if (!stage32(s)) return rhs(s, s->u, s->k[7]);
-  nsk::RhsParams p;
-  p.nu = s->nu_d;
-  p.ri = s->cfg.ri;
-  p.kappa = s->cfg.kappa;
-  const hipError_t e = nsk::rhs3d_compact(s->g, 0, nullptr, s->U32, s->k[7], p, s->rb, s->tw, s->st);
-  return e == hipSuccess ? NS_OK : NS_ERR_HIP;
+  return rhs_stage32(s, s->k[7], false);
 }
 
 int ns_autotune(ns_solver* s, int reps, double* ms_host) {
@@ -1547,7 +1549,7 @@ int ns_rhs_static(const ns_config* cfg, const double* nu_host, const void* uhat,
   p.ri = cfg->ri;
   p.kappa = cfg->kappa;
   const hipError_t e = g.dim == 3 ? nsk::rhs3d_compact(g, fp64, U, nullptr, K, p, rb, tw, st)
-                                  : nsk::rhs2d_compact(g, fp64, U, K, p, rb, tw, st);
+                                  : nsk::rhs2d_compact(g, fp64, U, nullptr, K, p, rb, tw, st);
   NS_HIP(e);
   NS_HIP(nsk::unpack_state(g, K, (double2*)f, st));
   return NS_OK;

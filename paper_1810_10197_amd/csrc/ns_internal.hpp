@@ -25,7 +25,7 @@ struct Geom {
 struct RhsParams {
   const double* nu;   // [batch]
   double ri, kappa;   // Boussinesq
-  float2* k32 = nullptr;   // 3D FP32 right-hand side: also write f rounded to FP32 (may be null)
+  float2* k32 = nullptr;   // FP32 right-hand side: also write f rounded to FP32 (may be null)
   const int* active = nullptr;   // 3D: [batch] device flags, evaluate only members with a nonzero
                                  // flag (their f and copies are left as they are); null: all
 };
@@ -69,7 +69,7 @@ size_t rhs3d_scratch_bytes(const Geom& g, int fp64);
 hipError_t rhs3d_compact(const Geom& g, int fp64, const double2* U, const float2* U32, double2* k,
                          const RhsParams& p, const RhsBufs& b, const void* tw, hipStream_t st);
 size_t rhs2d_scratch_bytes(const Geom& g, int fp64);
-hipError_t rhs2d_compact(const Geom& g, int fp64, const double2* U, double2* k,
+hipError_t rhs2d_compact(const Geom& g, int fp64, const double2* U, const float2* U32, double2* k,
                          const RhsParams& p, const RhsBufs& b, const void* tw, hipStream_t st);
 
 // ---- FP64 state kernels (step.hip) ----

@@ -11,6 +11,10 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int floor_pow2(int x) { int p = 1; while (p * 2 <= x) p *= 2; return p; }
 
+// A stage input read as FP64 (the FP64 state, or its FP32 rounding widened).
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
 // Column passes: C adjacent columns per block (CW: requested width, 0 = the
 // default of >= 16 columns and >= 256 threads), N/E threads per column.  A
 // request of 64 columns may use up to 160 KB of LDS (one block per CU): the

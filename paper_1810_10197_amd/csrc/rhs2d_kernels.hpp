@@ -27,8 +27,10 @@ namespace nsk {
 // ---------------------------------------------------------------- Q1
 // CW: column tile width (0 = the default); narrower tiles give more blocks
 // but shorter runs per row.
-template <class PL, typename T, int CW>
-__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k2_yinv(const double2* __restrict__ U,
+// UT: the stage input's type (double2: the FP64 state; float2: the FP32
+// stage input of an FP32 right-hand side inside a step).
+template <class PL, typename T, int CW, typename UT>
+__global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k2_yinv(const UT* __restrict__ U,
                                                               cplx<T>* __restrict__ B1, Geom g,
                                                               int nfield, long long nblocks,
                                                               const cplx<T>* __restrict__ tw) {
@@ -48,7 +50,7 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k2_yinv(const double2
   const int kx = tile * C + lc;
   const bool valid = kx < g.Kx;
   const long long cs = g.mr;
-  const double2* Um = U + (long long)m * g.ncomp * cs + (valid ? kx : 0);
+  const UT* Um = U + (long long)m * g.ncomp * cs + (valid ? kx : 0);
   // field f: 0 u, 1 v, 2 omega = i (kx v - ky u), 3 rho
   const int ca = f == 2 ? 1 : (f == 3 ? 2 : f);
   double2 a[E], b[E];
@@ -62,9 +64,9 @@ __global__ __launch_bounds__((ColCfg<PL, T, CW>::NT)) void k2_yinv(const double2
     const int ky = e <= g.K ? e : e - N;
     kys[i] = ky;
     const int kyp = ret ? (ky >= 0 ? ky : ky + g.Kf) : 0;
-    const double2* pp = Um + (long long)kyp * g.Kx;
-    a[i] = pp[ca * cs];
-    if (f == 2) b[i] = pp[0];
+    const UT* pp = Um + (long long)kyp * g.Kx;
+    a[i] = to_d2(pp[ca * cs]);
+    if (f == 2) b[i] = to_d2(pp[0]);
   }
   V v[E];
 #pragma unroll
@@ -322,10 +324,18 @@ template <bool SCALAR, bool SPLIT> struct Q3Fields {
   static constexpr int NFB = (SCALAR && SPLIT) ? 2 : NF;   // fields per block
 };
 
-template <class PL, typename T, bool SCALAR, int CMAX, bool COLB2, bool SPLIT>
+// f is written in FP64 to Kout and, where K32 is not null, rounded to FP32
+// to K32 (the copy a later FP32 stage combination reads).  UT as in Q1.
+__device__ __forceinline__ void put_f(double2* K, float2* K32, long long i, double2 v) {
+  K[i] = v;
+  if (K32) K32[i] = make_float2((float)v.x, (float)v.y);
+}
+
+template <class PL, typename T, bool SCALAR, int CMAX, bool COLB2, bool SPLIT, typename UT>
 __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::NT)) void k2_yfwd(
-    const cplx<T>* __restrict__ B2, const double2* __restrict__ U, double2* __restrict__ Kout, Geom g,
-    const double* __restrict__ nu, double ri, double kappa, const cplx<T>* __restrict__ tw, long long nblocks) {
+    const cplx<T>* __restrict__ B2, const UT* __restrict__ U, double2* __restrict__ Kout,
+    float2* __restrict__ K32, Geom g, const double* __restrict__ nu, double ri, double kappa,
+    const cplx<T>* __restrict__ tw, long long nblocks) {
   constexpr int N = PL::N;
   constexpr int NFB = Q3Fields<SCALAR, SPLIT>::NFB;
   constexpr bool SP = SCALAR && SPLIT;
@@ -383,27 +393,27 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::
     const double k2 = (double)(kx * kx + ky * ky);
     if (k2 == 0.0) {
       if (vel) {
-        Kout[idx] = make_double2(0.0, 0.0);
-        Kout[idx + cs] = make_double2(0.0, 0.0);
+        put_f(Kout, K32, idx, make_double2(0.0, 0.0));
+        put_f(Kout, K32, idx + cs, make_double2(0.0, 0.0));
       }
-      if (sca) Kout[idx + 2 * cs] = make_double2(0.0, 0.0);
+      if (sca) put_f(Kout, K32, idx + 2 * cs, make_double2(0.0, 0.0));
       continue;
     }
     double2 rh = make_double2(0.0, 0.0);
-    if constexpr (SCALAR) rh = U[idx + 2 * cs];
+    if constexpr (SCALAR) rh = to_d2(U[idx + 2 * cs]);
     if (vel) {
       const V v0 = col0[e], v1 = col0[C * LD + e];
       double nx = (double)v0.x * scale, nxi = (double)v0.y * scale;
       double ny = (double)v1.x * scale, nyi = (double)v1.y * scale;
-      const double2 u0 = U[idx], u1 = U[idx + cs];
+      const double2 u0 = to_d2(U[idx]), u1 = to_d2(U[idx + cs]);
       if constexpr (SCALAR) {
         ny -= ri * rh.x;               // buoyancy -Ri rho e_y, before the projection
         nyi -= ri * rh.y;
       }
       const double px = (kx * nx + ky * ny) / k2, py = (kx * nxi + ky * nyi) / k2;
       const double vk = num * k2;
-      Kout[idx] = make_double2(nx - kx * px - vk * u0.x, nxi - kx * py - vk * u0.y);
-      Kout[idx + cs] = make_double2(ny - ky * px - vk * u1.x, nyi - ky * py - vk * u1.y);
+      put_f(Kout, K32, idx, make_double2(nx - kx * px - vk * u0.x, nxi - kx * py - vk * u0.y));
+      put_f(Kout, K32, idx + cs, make_double2(ny - ky * px - vk * u1.x, nyi - ky * py - vk * u1.y));
     }
     if (sca) {
       // -i k . q_hat - kappa |k|^2 rho_hat (q_x, q_y are this block's fields 0, 1 when split)
@@ -412,7 +422,7 @@ __global__ __launch_bounds__((Q3Cfg<PL, T, Q3Fields<SCALAR, SPLIT>::NFB, CMAX>::
       const double sx = kx * ((double)v2.x * scale) + ky * ((double)v3.x * scale);
       const double sy = kx * ((double)v2.y * scale) + ky * ((double)v3.y * scale);
       const double kk2 = kappa * k2;
-      Kout[idx + 2 * cs] = make_double2(sy - kk2 * rh.x, -sx - kk2 * rh.y);
+      put_f(Kout, K32, idx + 2 * cs, make_double2(sy - kk2 * rh.x, -sx - kk2 * rh.y));
     }
   }
 }
@@ -441,28 +451,39 @@ template <int N, int V, bool SCALAR> struct Q3Var {
                               : ((V == 2 || V == 4) && !SPLIT ? 1 : 8);
 };
 
-template <int N, typename T, int VAR>
-static void launch_q1(const Geom& g, const double2* U, cplx<T>* B1, int nfield, const cplx<T>* tw,
+template <int N, typename T, int VAR, typename UT>
+static void launch_q1(const Geom& g, const UT* U, cplx<T>* B1, int nfield, const cplx<T>* tw,
                       hipStream_t st) {
   using QV = Q1Var<N, VAR>;
   using CF = ColCfg<typename QV::PL, T, QV::CW>;
   const long long nb1 = (long long)g.batch * nfield * ((g.Kx + CF::C - 1) / CF::C);
   const long long nb1p = (nb1 + 7) / 8 * 8;
-  hipLaunchKernelGGL((k2_yinv<typename QV::PL, T, QV::CW>), dim3((unsigned)nb1p), dim3(CF::NT), 0, st, U, B1, g,
-                     nfield, nb1, tw);
+  hipLaunchKernelGGL((k2_yinv<typename QV::PL, T, QV::CW, UT>), dim3((unsigned)nb1p), dim3(CF::NT), 0, st, U, B1,
+                     g, nfield, nb1, tw);
 }
-template <int N, typename T, bool SCALAR, int VAR, bool COLB2>
-static void launch_q3(const Geom& g, const cplx<T>* B2, const double2* U, double2* K, const RhsParams& p,
+template <int N, typename T, typename UT>
+static void launch_q1v(int v1, const Geom& g, const UT* U, cplx<T>* B1, int nfield, const cplx<T>* tw,
+                       hipStream_t st) {
+  switch (v1) {
+    case 1: launch_q1<N, T, N >= 256 ? 1 : 0>(g, U, B1, nfield, tw, st); break;
+    case 2: launch_q1<N, T, N >= 256 ? 2 : 0>(g, U, B1, nfield, tw, st); break;
+    case 3: launch_q1<N, T, N >= 256 ? 3 : 0>(g, U, B1, nfield, tw, st); break;
+    case 4: launch_q1<N, T, N >= 256 ? 4 : 0>(g, U, B1, nfield, tw, st); break;
+    default: launch_q1<N, T, 0>(g, U, B1, nfield, tw, st);
+  }
+}
+template <int N, typename T, bool SCALAR, int VAR, bool COLB2, typename UT>
+static void launch_q3(const Geom& g, const cplx<T>* B2, const UT* U, double2* K, const RhsParams& p,
                       const cplx<T>* tw, hipStream_t st) {
   using QV = Q3Var<N, VAR, SCALAR>;
   using QC = Q3Cfg<typename QV::PL, T, Q3Fields<SCALAR, QV::SPLIT>::NFB, QV::CMAX>;
   const long long nb = (long long)((g.Kx + QC::C - 1) / QC::C) * g.batch * (QV::SPLIT ? 2 : 1);
   const long long nbp = (nb + 7) / 8 * 8;
-  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX, COLB2, QV::SPLIT>), dim3((unsigned)nbp),
-                     dim3(QC::NT), 0, st, B2, U, K, g, p.nu, p.ri, p.kappa, tw, nb);
+  hipLaunchKernelGGL((k2_yfwd<typename QV::PL, T, SCALAR, QV::CMAX, COLB2, QV::SPLIT, UT>), dim3((unsigned)nbp),
+                     dim3(QC::NT), 0, st, B2, U, K, p.k32, g, p.nu, p.ri, p.kappa, tw, nb);
 }
-template <int N, typename T, bool SCALAR, bool COLB2>
-static void launch_q3v(int v3, const Geom& g, const cplx<T>* B2, const double2* U, double2* K,
+template <int N, typename T, bool SCALAR, bool COLB2, typename UT>
+static void launch_q3v(int v3, const Geom& g, const cplx<T>* B2, const UT* U, double2* K,
                        const RhsParams& p, const cplx<T>* tw, hipStream_t st) {
   switch (v3) {
     case 1: launch_q3<N, T, SCALAR, N >= 256 ? 1 : 0, COLB2>(g, B2, U, K, p, tw, st); break;
@@ -475,8 +496,11 @@ static void launch_q3v(int v3, const Geom& g, const cplx<T>* B2, const double2* 
   }
 }
 
+// U: the FP64 stage input; U32 (FP32 right-hand side only, else null): its
+// FP32 rounding, read instead of U where given (the stage input of an FP32
+// step, which the transforms round to FP32 anyway).
 template <int N, typename T, bool SCALAR>
-static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsParams& p,
+static hipError_t run2d(const Geom& g, const double2* U, const float2* U32, double2* K, const RhsParams& p,
                         const RhsBufs& bufs, const void* twv, hipStream_t st) {
   using V = cplx<T>;
   using PL = Plan<N>;
@@ -494,13 +518,15 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
 #define NSK_MARK(id, ph) \
   if (bufs.hook && bufs.fine != 2) bufs.hook(bufs.hook_ctx, id, ph, st)
   if (bufs.hook && bufs.fine == 2) bufs.hook(bufs.hook_ctx, PROF_RHS, 0, st);
+  constexpr bool f32 = std::is_same<T, float>::value;
+  if (!f32 && U32) return hipErrorInvalidValue;
+  if (!U32 && !U) return hipErrorInvalidValue;
   NSK_MARK(PROF_P1, 0);
-  switch (v1) {
-    case 1: launch_q1<N, T, N >= 256 ? 1 : 0>(g, U, B1, nfield, tw, st); break;
-    case 2: launch_q1<N, T, N >= 256 ? 2 : 0>(g, U, B1, nfield, tw, st); break;
-    case 3: launch_q1<N, T, N >= 256 ? 3 : 0>(g, U, B1, nfield, tw, st); break;
-    case 4: launch_q1<N, T, N >= 256 ? 4 : 0>(g, U, B1, nfield, tw, st); break;
-    default: launch_q1<N, T, 0>(g, U, B1, nfield, tw, st);
+  if constexpr (f32) {
+    if (U32) launch_q1v<N, T>(v1, g, U32, B1, nfield, tw, st);
+    else launch_q1v<N, T>(v1, g, U, B1, nfield, tw, st);
+  } else {
+    launch_q1v<N, T>(v1, g, U, B1, nfield, tw, st);
   }
   NSK_MARK(PROF_P1, 1);
   const long long rows = (long long)g.batch * N;
@@ -526,8 +552,16 @@ static hipError_t run2d(const Geom& g, const double2* U, double2* K, const RhsPa
   }
   NSK_MARK(PROF_P3, 1);
   NSK_MARK(PROF_P5, 0);
-  if (colb2) launch_q3v<N, T, SCALAR, N >= 256>(v3, g, B2, U, K, p, tw, st);
-  else launch_q3v<N, T, SCALAR, false>(v3, g, B2, U, K, p, tw, st);
+  if constexpr (f32) {
+    if (U32) {
+      if (colb2) launch_q3v<N, T, SCALAR, N >= 256>(v3, g, B2, U32, K, p, tw, st);
+      else launch_q3v<N, T, SCALAR, false>(v3, g, B2, U32, K, p, tw, st);
+    }
+  }
+  if (!U32) {
+    if (colb2) launch_q3v<N, T, SCALAR, N >= 256>(v3, g, B2, U, K, p, tw, st);
+    else launch_q3v<N, T, SCALAR, false>(v3, g, B2, U, K, p, tw, st);
+  }
   NSK_MARK(PROF_P5, 1);
   if (bufs.hook && bufs.fine == 2) bufs.hook(bufs.hook_ctx, PROF_RHS, 1, st);
 #undef NSK_MARK

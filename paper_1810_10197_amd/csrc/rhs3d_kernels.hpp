@@ -65,9 +65,6 @@ __host__ __device__ constexpr int a1_pitch(int n) {
 // the curl) at every kz' the thread's registers hold, zero in the gap, with
 // kz per register.  No branches on lanes (band tests fold or become
 // selects), so that all of a thread's loads are in flight together.
-__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
-
 template <class PL, bool PAIR, typename UT>
 __device__ __forceinline__ void zinv_loads(const UT* pa, const UT* pb, unsigned lane, int colc, int t,
                                            double2 (&a)[PL::E], double2 (&b)[PL::E], int (&kzs)[PL::E]) {

@@ -142,3 +142,92 @@ def test_rhs2d_every_launch_variant(ns, n, scalar, prec):
     got = s.rhs(u[None]).cpu().numpy()[0]
     assert max(per_field_rel_l2(got, ref)) <= tol
     s.close()
+
+
+def unit_speed(u, n):
+    """u scaled to a largest physical velocity of one (test input)."""
+    return u / np.abs(spectral.inverse(u, n, 2)[:2]).max()
+
+
+@pytest.mark.parametrize("n,scalar", [(1024, 1), (256, 0)])
+def test_bs5_fp32_stage_inputs_every_variant(ns, n, scalar):
+    """With an FP32 right-hand side the stages of a BS5 attempt reach the
+    first and last passes as FP32 roundings of U_i, formed from the FP32
+    copies of u_n and of the k_j (which the last pass writes beside f): one
+    attempt per launch variant of the three passes against the oracle's
+    attempt (h at a CFL number of 0.5)."""
+    announce("bs5 fp32 stage inputs 2d n=%d scalar=%d" % (n, scalar))
+    nu, kappa, ri = 1e-3, 2e-3, 0.5
+    u = unit_speed(random2d(n, 11 * n + scalar, 3 if scalar else 2), n)
+    h = 0.5 * 2 * np.pi / n
+    rhs = (lambda x: spectral.rhs_ns2d(x, nu, kappa, ri)) if scalar else (lambda x: spectral.rhs_ns2d(x, nu))
+    ref = stepping.bs5_attempt(rhs, u, h, 1e-6, 1e-6)["u_new"]
+    s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision="fp32", scalar=scalar, ri=ri if scalar else 0.0,
+                  kappa=kappa if scalar else 0.0)
+    for v in range(28):
+        s.tune([v % 5, 0, (v // 7) % 4, 0, 6 - v % 7, 0])
+        s.set_state(u[None])
+        s.step_bs5(h, 1e-6, 1e-6, force=True)
+        got = s.get_state().cpu().numpy()[0]
+        err = max(per_field_rel_l2(got, ref))
+        assert err <= 1e-6, (v, err)
+    s.close()
+
+
+def test_fp32_integrate_2d_graph_host_and_oracle(ns):
+    """An adaptive FP32 run of the Boussinesq system (FP32 stage inputs and
+    k_j copies, kept by the commits), with a rejected first step: the
+    graph-captured and the host path agree bitwise, and their decisions equal
+    the oracle's (errors of at most 0.34 away from the rejection) with the
+    state within the FP32 bound."""
+    n, nu, kappa, ri = 64, 1e-3, 1e-3, 0.5
+    announce("fp32 integrate 2d n=%d graph vs host vs oracle" % n)
+    u0 = unit_speed(random2d(n, 17, 3), n)
+    rhs = lambda x: spectral.rhs_ns2d(x, nu, kappa, ri)
+    ref = control.integrate(rhs, u0, 0.5, 0.5, 1e-8, 1e-8)
+    assert ref["n_reject"] >= 1
+    out = []
+    for graph in (True, False):
+        s = ns.Solver(dim=2, n=n, nu=nu, rhs_precision="fp32", scalar=1, ri=ri, kappa=kappa)
+        s.set_state(u0[None])
+        st = s.integrate(0.5, 0.5, 1e-8, 1e-8, graph=graph)[0]
+        out.append((st, s.get_state().cpu().numpy()[0]))
+        s.close()
+    (s1, u1), (s2, u2) = out
+    assert (s1["n_accept"], s1["n_reject"], s1["n_rhs"]) == (s2["n_accept"], s2["n_reject"], s2["n_rhs"])
+    assert np.array_equal(u1.view(np.float64), u2.view(np.float64))
+    assert (s1["n_accept"], s1["n_reject"], s1["n_rhs"]) == (ref["n_accept"], ref["n_reject"], ref["n_rhs"])
+    assert max(per_field_rel_l2(u1, ref["u"])) <= 1e-5
+
+
+def test_fp32_2d_partial_acceptance_equals_single_runs(ns):
+    """Host BS5 steps of a 2D FP32 batch in which one member accepts and the
+    other rejects: the commit keeps each member's FP32 state copy and first
+    stage, so every member stays bitwise equal to its own single run."""
+    n, kappa, ri = 64, 1e-3, 0.5
+    announce("2d fp32 host steps, partial acceptance == single n=%d" % n)
+    ua = unit_speed(random2d(n, 21, 3), n)
+    ub = 40.0 * unit_speed(random2d(n, 22, 3), n)
+    nus = [1e-3, 2e-3]
+    kw = dict(dim=2, n=n, rhs_precision="fp32", scalar=1, ri=ri, kappa=kappa)
+    sb = ns.Solver(batch=2, nu=nus, **kw)
+    sb.set_state(np.stack([ua, ub]))
+    singles = []
+    for u, nu in ((ua, nus[0]), (ub, nus[1])):
+        s1 = ns.Solver(nu=nu, **kw)
+        s1.set_state(u[None])
+        singles.append(s1)
+    mixed = 0
+    for h in (0.05, 0.05, 0.02, 0.01, 0.01, 0.005, 0.005, 0.002, 0.002):
+        _, eb = sb.step_bs5(h, 1e-6, 1e-6)
+        for m, s1 in enumerate(singles):
+            _, e1 = s1.step_bs5(h, 1e-6, 1e-6)
+            assert eb[m] == e1[0] or (np.isnan(eb[m]) and np.isnan(e1[0]))
+        mixed += (eb[0] <= 1.0) != (eb[1] <= 1.0)
+    assert mixed >= 1
+    ubatch = sb.get_state().cpu().numpy()
+    for m, s1 in enumerate(singles):
+        u1 = s1.get_state().cpu().numpy()[0]
+        assert np.array_equal(u1.view(np.float64), ubatch[m].view(np.float64))
+        s1.close()
+    sb.close()
