@@ -57,6 +57,14 @@ __device__ __forceinline__ float2 ld_stream(const float2* p) {
   const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
   return make_float2(v.x, v.y);
 }
+// Store with the same hint, for outputs that are next read only after a
+// whole right-hand side: the FP64 u_{n+1} and the partial embedded difference
+// of an FP32 step's last combination (the next pass reads the FP32 stage
+// input, which keeps plain stores so that it can stay in the caches).
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  const d2v x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<d2v*>(p));
+}
 
 // Grid of the element-wise kernels: one element per thread, blockIdx.y =
 // member (no per-element division to find the member).
@@ -96,9 +104,12 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ bas
     }
     r.x += hm * sx;
     r.y += hm * sy;
-    if (W64) out64[off + i] = r;
+    if (W64) {
+      if (W32) st_stream(out64 + off + i, r);   // FP32 step: the FP32 copy is the next input
+      else out64[off + i] = r;
+    }
     if (W32) out32[off + i] = make_float2((float)r.x, (float)r.y);
-    if (D2) out2[off + i] = make_double2(dx, dy);
+    if (D2) st_stream(out2 + off + i, make_double2(dx, dy));
   }
 }
 
