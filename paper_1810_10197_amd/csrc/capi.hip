@@ -470,8 +470,13 @@ static void errs_from_reductions(ns_solver* s, std::vector<double>& errs) {
 static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
   int nacc = 0;
   for (int a : accept) nacc += a ? 1 : 0;
-  s->maskbuf = accept;
-  NS_HIP(hipMemcpyAsync(s->mask_d, s->maskbuf.data(), sizeof(int) * s->g.batch, hipMemcpyHostToDevice, s->st));
+  // the device mask is needed only when some members accept and others do
+  // not (a batch that accepts whole swaps buffers and forces every member)
+  const bool partial = nacc > 0 && nacc < s->g.batch;
+  if (partial) {
+    s->maskbuf = accept;
+    NS_HIP(hipMemcpyAsync(s->mask_d, s->maskbuf.data(), sizeof(int) * s->g.batch, hipMemcpyHostToDevice, s->st));
+  }
   if (nacc == s->g.batch) {
     std::swap(s->u, s->U);
     if (s->u32) std::swap(s->u32, s->U32);     // the last stage's input: u_{n+1} rounded to FP32
@@ -487,7 +492,7 @@ static int commit_host(ns_solver* s, const std::vector<int>& accept, int last) {
     NS_HIP(nsk::masked_copy(s->g, s->k[last], s->k[0], s->mask_d, s->st));
     if (s->k32[0]) NS_HIP(nsk::masked_copy32(s->g, s->k32[last], s->k32[0], s->mask_d, s->st));
   }
-  if (nacc > 0) return apply_forcing(s, s->mask_d, true);   // red_out: the attempt's reduction
+  if (nacc > 0) return apply_forcing(s, partial ? s->mask_d : nullptr, true);   // red_out: the attempt's reduction
   return NS_OK;
 }
 
