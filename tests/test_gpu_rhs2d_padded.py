@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from gpu_util import announce, per_field_rel_l2
-from oracle import control, spectral
+from oracle import control, spectral, stepping
 
 pytestmark = pytest.mark.gpu
 
@@ -94,3 +94,24 @@ def test_padded_boussinesq_integrate_matches_oracle_controller(ns):
     assert (stats["n_accept"], stats["n_reject"], stats["n_rhs"]) == \
         (ref["n_accept"], ref["n_reject"], ref["n_rhs"])
     assert np.abs(got - ref["u"]).max() <= 1e-12 * np.abs(ref["u"]).max()
+
+
+@pytest.mark.parametrize("n,scalar", [(256, 1), (64, 0)])
+def test_padded_fp32_bs5_attempt_stage_inputs(ns, n, scalar):
+    """An FP32 BS5 attempt on the 3/2-rule grid takes its stages in FP32 (the
+    FP32 copies of u_n and of the k_j, written by the combinations and the
+    last pass): against the oracle's padded attempt, h at a CFL number of 0.5."""
+    nu, kappa, ri = 2e-3, 2e-3, 0.5
+    announce("padded fp32 bs5 attempt n=%d scalar=%d" % (n, scalar))
+    st = band_field(n, 131 + n + scalar, 3 if scalar else 2)
+    st = st / np.abs(spectral.inverse(st, n, 2)[:2]).max()
+    h = 0.5 * 2 * np.pi / n
+    rhs = (lambda u: spectral.rhs_ns2d_padded(u, nu, kappa, ri)) if scalar else \
+        (lambda u: spectral.rhs_ns2d_padded(u, nu))
+    ref = stepping.bs5_attempt(rhs, st, h, 1e-6, 1e-6)["u_new"]
+    s = solver(ns, n, "fp32", scalar, nu, kappa if scalar else 0.0, ri if scalar else 0.0)
+    s.set_state(st[None])
+    s.step_bs5(h, 1e-6, 1e-6, force=True)
+    got = s.get_state().cpu().numpy()[0]
+    s.close()
+    assert max(per_field_rel_l2(got, ref)) <= 1e-6
