@@ -44,3 +44,19 @@ def test_pass_bytes_match_the_pencil_model_at_256():
     pb = bench.pass_bytes(256)
     assert sum(pb.values()) == pytest.approx(1.7159e9, rel=1e-4)
     assert pb["yinv"] == 6 * 86 * 171 * 256 * 8 + 6 * 86 * 256 * 256 * 8
+
+
+def test_pass_bytes_2d_with_fp32_stage_inputs():
+    """2D Boussinesq at 1024^2 (K = 341: 342 x 683 retained modes, three
+    components; four transformed fields of 1024 x 342 FP32 values): Q1 reads
+    the stage input in FP32 (8 bytes) instead of FP64 (16), Q3 too, and writes
+    f in FP64 plus its FP32 copy in six of seven evaluations."""
+    mr, col = 342 * 683, 4 * 1024 * 342 * 8
+    pb64 = bench.pass_bytes_2d(1024)
+    pb32 = bench.pass_bytes_2d(1024, stage32=True)
+    assert pb64 == {"zinv": 3 * mr * 16 + col, "xpass": 2 * col, "zfwd": col + 6 * mr * 16}
+    assert pb32["zinv"] == 3 * mr * 8 + col
+    assert pb32["xpass"] == pb64["xpass"]
+    assert pb32["zfwd"] == col + 3 * mr * 8 + 3 * mr * 16 + 3 * mr * 8 * 6 // 7
+    assert sum(pb64.values()) / 1e6 == pytest.approx(78.46, abs=0.01)
+    assert sum(pb32.values()) / 1e6 == pytest.approx(72.05, abs=0.01)
